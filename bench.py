@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the FWIME hot path on one MI355X.
+
+One step = one pass of every operator of the hot path over the whole shot set:
+nonlinear modeling f(m), extended Born B~(m) p~, its adjoint B~^T d and the
+FWIME objective with both gradients, each through the C ABI.  The workload is
+the Marmousi-like 300 x 1700 grid (10 m, 60-cell absorbing strip, padded
+420 x 1820), 100 shots every 170 m, 1700 receivers, 8 Hz Ricker, dt = 0.8 ms,
+nt = 5000, 61 subsurface offsets; inputs are synthetic and seeded.
+
+cell-updates/s counts propagations as the paper's cost analysis does
+(Section "Computational aspects": modeling 1, extended Born 2, its adjoint 2,
+gradient 6 per shot), each NZ * NX * (nt - 1) padded cell-updates; recomputed
+propagations of the checkpointing scheme are not counted.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+STENCIL_BYTES = 16         # read u^n, u^{n-1}, V; write u^{n+1}
+PROPAGATIONS = {"model": 1, "born_ext_fwd": 2, "born_ext_adj": 2, "gradient": 6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str, nshots: int | None):
+    import synth
+    if name == "marmousi":
+        w = synth.marmousi_set(100 if nshots is None else nshots)
+    elif name == "plain-small":
+        w = synth.plain_small()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return w
+
+
+def cpu_baseline(w, steps: int):
+    """The FP64 oracle on a bounded sample: one shot, the first `steps` time steps."""
+    import numpy as np
+    import oracle
+    import synth
+    sub = w.subset([0])
+    g = oracle.Grid(sub.nz, sub.nx, sub.nb, steps, sub.dz, sub.dx, sub.dt, sub.sponge_alpha)
+    geo = oracle.Geometry(sub.src_iz, sub.src_ix, sub.rec_iz, sub.rec_ix, sub.wavelet[:, :steps].copy())
+    t = time.perf_counter()
+    oracle.model(g, sub.vel, geo)
+    dt = time.perf_counter() - t
+    cells = (sub.nz + 2 * sub.nb) * (sub.nx + 2 * sub.nb) * (steps - 1)
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle.model, 1 shot of the {sub.nz}x{sub.nx} workload, first {steps} time steps "
+                      f"({cells:.3g} padded cell-updates in {dt:.1f} s, NumPy FP64, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="marmousi")
+    ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--ops", default="model,born_ext_fwd,born_ext_adj,gradient")
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(shots would shard across GPUs with one all-reduce of the gradients).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2206_02362_amd as fw
+    import synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    ops = [o for o in args.ops.split(",") if o]
+    w = make_workload(args.workload, args.shots)
+    log(f"workload {w.name}: {w.nshots} shots, nt {w.nt}, nh {w.nh}, padded {w.nz + 2 * w.nb}x{w.nx + 2 * w.nb}")
+    dev = "cuda:0"
+    ctx = fw.Context(0)
+    grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+    vel = torch.tensor(w.vel, dtype=torch.float32, device=dev)
+    geo = fw.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix,
+                      torch.tensor(w.wavelet, dtype=torch.float32, device=dev))
+    vtrue = torch.tensor(w.vel * (1.0 + 0.03 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 77, 300.0)),
+                         dtype=torch.float32, device=dev)
+    ptilde = torch.tensor(1e-2 * synth.random_ptilde(w.nh, w.nz, w.nx, 78), dtype=torch.float32, device=dev)
+    dso = synth.dso_weights(w.nh)
+    log("setup: observed data")
+    dobs = ctx.model(grid, vtrue, geo)
+    torch.cuda.synchronize()
+
+    outs = {}
+
+    def step():
+        if "model" in ops:
+            outs["model"] = ctx.model(grid, vel, geo)
+        if "born_ext_fwd" in ops:
+            outs["born"] = ctx.born_ext_fwd(grid, vel, geo, ptilde)
+        if "born_ext_adj" in ops:
+            outs["adj"] = ctx.born_ext_adj(grid, vel, geo, dobs, w.nh)
+        if "gradient" in ops:
+            outs["grad"] = ctx.gradient(grid, vel, geo, ptilde, dobs, 1e-4, dso)
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"step {i} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    NZ, NX = w.nz + 2 * w.nb, w.nx + 2 * w.nb
+    per_prop = w.nshots * NZ * NX * (w.nt - 1)
+    nprop = sum(PROPAGATIONS[o] for o in ops)
+    value = nprop * per_prop / (elapsed / args.steps)
+
+    # Dominant kernel: the stencil step.  fwime_model is nt - 1 launches of it
+    # (plus one receiver gather), all shots in one launch; time it with events
+    # on the stream the library launches on.
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    data = torch.empty((w.nshots, w.nrec, w.nt), device=dev)
+    ctx.fwime_model(grid, vel, geo, data)      # tables and arena warm
+    torch.cuda.synchronize()
+    reps = 2
+    tev = 0.0
+    for _ in range(reps):
+        # validation (one reduction + sync) happens before the first launch
+        ctx_t = time.perf_counter()
+        e0.record(st)
+        ctx.fwime_model(grid, vel, geo, data)
+        e1.record(st)
+        e1.synchronize()
+        tev += e0.elapsed_time(e1) / 1e3
+    per_launch = tev / reps / (w.nt - 1)
+    launch_bytes = STENCIL_BYTES * w.nshots * NZ * NX
+    achieved = launch_bytes / per_launch
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None,
+                "kernel": "k_step (stencil time step, all shots per launch)",
+                "bytes_per_launch": launch_bytes, "avg_launch_us": per_launch * 1e6}
+    log(f"stencil: {per_launch * 1e6:.1f} us per launch, {achieved / 1e9:.0f} GB/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_steps} steps")
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    rec = {
+        "metric": "cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nshots} shots, nt {w.nt}, nh {w.nh}, padded {NZ}x{NX}, "
+                               f"ops {'+'.join(ops)} ({nprop} propagations/shot counted)",
+                   "nshots": w.nshots, "nt": w.nt, "nh": w.nh, "padded_cells": NZ * NX,
+                   "model_cells": w.nz * w.nx},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,131 @@
+/*
+ * fwime.h -- C ABI of the MI355X (gfx950) FWIME hot-path library.
+ *
+ * Operations follow Section 2 of Barnier, Biondi, Clapp and Biondi, "Full
+ * waveform inversion by model extension: practical applications" (arXiv
+ * 2206.02362): nonlinear modeling f(m) with an acoustic isotropic
+ * constant-density two-way wave equation, the Born operator extended with
+ * horizontal subsurface offsets B~(m), its adjoint (the extended imaging
+ * condition), and the FWIME objective of eq. fwime.obj with its gradients
+ * (eqs. fwime.gradient.split, fwime.gradient.born, fwime.gradient.tomo),
+ * evaluated at a given extended perturbation p~.
+ *
+ * Discretization (the paper prints none; the choices are stated once here):
+ *   - padded grid: the model grid (nz, nx) plus an absorbing strip of nb cells
+ *     on every side (NZ = nz + 2 nb, NX = nx + 2 nb); the velocity is copied
+ *     from the nearest model cell into the strip;
+ *   - equation n = 0 .. nt-2:  u^{n+1} = g (2 u^n - g u^{n-1} + V (L u^n + f^n)),
+ *     u^{-1} = u^0 = 0, V = v^2 dt^2, L the radius-4 (8th-order) Laplacian with
+ *     zero values outside the padded grid, g(iz, ix) = g_z(iz) g_x(ix) the
+ *     Cerjan taper with g_1D(k) = exp(-(sponge_alpha * k / nb)^2) for the cell
+ *     k = 1..nb cells into the strip (Cerjan et al. 1985, cited in Section 3);
+ *   - point source f^n = w^n / (dx dz) at the source cell; receivers record
+ *     d^k = u^k at their cell for k = 0 .. nt-1 (d^0 = 0);
+ *   - extended Born with offset h = ih dx, ih in [-(nh-1)/2, (nh-1)/2]: in
+ *     equation n the scattered field receives
+ *       s_n(z, y + h) += 2 p~(z, y, h) / (v(z, y)^3 dt^2) * T2u_n(z, y - h),
+ *     T2u_n = u^{n+1}/g - 2 u^n + g u^{n-1}; terms whose y -/+ h leave the
+ *     padded grid are dropped; nh = 1 is ordinary Born;
+ *   - p~ is an extended VELOCITY perturbation (m/s) on the model grid.
+ *
+ * Conventions for every entry point:
+ *   - Layout: z is the fastest axis.  vel[nx][nz], ptilde[nh][nx][nz],
+ *     data[nshots][nrec][nt], wavelet[nshots][nt].
+ *   - Memory: arrays of floating-point values are DEVICE pointers on the
+ *     context's device, owned by the caller.  The geometry index arrays
+ *     (src_iz, src_ix, rec_iz, rec_ix) and the DSO weights are HOST pointers.
+ *     Outputs are overwritten, never accumulated into.
+ *   - Execution: work is enqueued on `stream` (a hipStream_t, passed as void*)
+ *     and the call returns once it is enqueued.  Before enqueuing, each call
+ *     validates its inputs, which includes one small device reduction and a
+ *     stream synchronization (velocity range for the CFL test, finiteness).
+ *   - Errors: on any nonzero return nothing has been written to the outputs.
+ *   - Threads: a context is used by one host thread and one stream at a time.
+ */
+#ifndef FWIME_H
+#define FWIME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define FWIME_OK          0
+#define FWIME_EINVAL      1  /* bad dims, nh even or too large, geometry outside the model grid,
+                                CFL violated, non-positive velocity, null pointer */
+#define FWIME_ENOMEM      2  /* device memory or the context's HBM budget exhausted */
+#define FWIME_EHIP        3  /* HIP runtime error (text via fwime_last_error) */
+#define FWIME_ENONFINITE  4  /* NaN or Inf in an input array */
+
+/* Model grid (unpadded), absorbing strip width and time axis. */
+typedef struct {
+  int32_t nz, nx;      /* model grid, cells                              */
+  int32_t nb;          /* absorbing strip, cells on each side (>= 0)     */
+  int32_t nt;          /* time samples (>= 2)                            */
+  double dz, dx, dt;   /* m, m, s                                        */
+  double sponge_alpha; /* taper strength (0 disables the taper)          */
+} fwime_grid_t;
+
+/* Acquisition: nshots shots sharing the grid and velocity model. */
+typedef struct {
+  int32_t nshots, nrec;
+  const int32_t *src_iz, *src_ix;  /* HOST [nshots], model-grid indices      */
+  const int32_t *rec_iz, *rec_ix;  /* HOST [nshots][nrec], model-grid indices */
+  const float *wavelet;            /* DEVICE [nshots][nt]                     */
+} fwime_geom_t;
+
+typedef struct fwime_ctx fwime_ctx_t;
+
+/* Create a context on `device`.  It owns all scratch memory (wavefield
+ * buffers, checkpoints, geometry tables) and never allocates beyond
+ * `hbm_budget_bytes` (0 = no limit besides the device).  Returns FWIME_OK and
+ * sets *out, or an error code. */
+int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out);
+
+/* Release every allocation of the context (synchronizes the device). */
+void fwime_ctx_destroy(fwime_ctx_t *ctx);
+
+/* Nonlinear modeling f(m), the first term of eq. fwime.obj:
+ * data[s][r][k] = u^k at receiver r of shot s.  vel: DEVICE [nx][nz] m/s. */
+int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                const fwime_geom_t *geom, float *data, void *stream);
+
+/* Extended Born modeling B~(m) p~ (the data-correcting term of eq. fwime.obj).
+ * ptilde: DEVICE [nh][nx][nz]; nh odd, 1 <= nh <= 2 nx - 1; data as above. */
+int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, int32_t nh, const float *ptilde,
+                       float *data, void *stream);
+
+/* Adjoint of fwime_born_ext_fwd (extended migration, the imaging condition of
+ * the variable-projection step, eqs. vp.obj and vp.pseudo.inv):
+ * ptilde_out(z,y,h) = 2/(v(z,y)^3 dt^2) sum_shots sum_n T2u_n(z,y-h) lambda_n(z,y+h),
+ * with lambda the adjoint field driven by `data` at the receivers. */
+int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, int32_t nh, const float *data,
+                       float *ptilde_out, void *stream);
+
+/* FWIME objective of eq. fwime.obj at the given p~ and its gradients:
+ *   r = f(m) + B~(m) p~ - dobs,
+ *   obj = 1/2 ||r||^2 + eps^2/2 sum_h dso[h]^2 ||p~_h||^2,
+ *   grad_vel = (B^* + T^*) r  (eqs. fwime.gradient.born and .tomo, no spline),
+ *   grad_ptilde = B~^* r + eps^2 dso[h]^2 p~.
+ * dobs: DEVICE [nshots][nrec][nt]; dso: HOST double [nh]; obj: DEVICE double[1];
+ * grad_vel: DEVICE [nx][nz]; grad_ptilde: DEVICE [nh][nx][nz]. */
+int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                   const fwime_geom_t *geom, int32_t nh, const float *ptilde,
+                   const float *dobs, double eps, const double *dso,
+                   double *obj, float *grad_vel, float *grad_ptilde, void *stream);
+
+/* Static description of a return code. */
+const char *fwime_strerror(int code);
+
+/* Detail of the last error raised on this context (empty if none). */
+const char *fwime_last_error(const fwime_ctx_t *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWIME_H */

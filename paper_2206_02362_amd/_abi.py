@@ -1,0 +1,228 @@
+"""ctypes binding of libfwime.so (include/fwime.h): argument marshalling only.
+
+Every numerical step runs in the HIP library.  PyTorch supplies device memory
+(tensors) and the stream; the geometry index arrays are host int32 arrays.
+There is no fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwime.so")
+
+FWIME_OK = 0
+FWIME_EINVAL = 1
+FWIME_ENOMEM = 2
+FWIME_EHIP = 3
+FWIME_ENONFINITE = 4
+
+EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_model", "fwime_born_ext_fwd",
+            "fwime_born_ext_adj", "fwime_gradient", "fwime_strerror", "fwime_last_error")
+
+
+class FwimeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32), ("nb", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("dz", ctypes.c_double), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("sponge_alpha", ctypes.c_double)]
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("nshots", ctypes.c_int32), ("nrec", ctypes.c_int32),
+                ("src_iz", ctypes.c_void_p), ("src_ix", ctypes.c_void_p),
+                ("rec_iz", ctypes.c_void_p), ("rec_ix", ctypes.c_void_p),
+                ("wavelet", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libfwime.so (built in-tree by paper_2206_02362_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2206_02362_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.fwime_ctx_create.argtypes = [I, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.fwime_ctx_create.restype = I
+    lib.fwime_ctx_destroy.argtypes = [P]
+    lib.fwime_ctx_destroy.restype = None
+    lib.fwime_model.argtypes = [P, P, P, P, P, P]
+    lib.fwime_model.restype = I
+    lib.fwime_born_ext_fwd.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
+    lib.fwime_born_ext_fwd.restype = I
+    lib.fwime_born_ext_adj.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
+    lib.fwime_born_ext_adj.restype = I
+    lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
+    lib.fwime_gradient.restype = I
+    lib.fwime_strerror.argtypes = [I]
+    lib.fwime_strerror.restype = ctypes.c_char_p
+    lib.fwime_last_error.argtypes = [P]
+    lib.fwime_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Grid:
+    """Model grid (unpadded), absorbing strip and time axis; see fwime_grid_t."""
+    nz: int
+    nx: int
+    nb: int
+    nt: int
+    dz: float
+    dx: float
+    dt: float
+    sponge_alpha: float = 0.3
+
+    def _c(self) -> _Grid:
+        return _Grid(self.nz, self.nx, self.nb, self.nt, self.dz, self.dx, self.dt, self.sponge_alpha)
+
+
+class Geometry:
+    """Acquisition: host int32 index arrays and a device float32 wavelet tensor."""
+
+    def __init__(self, src_iz, src_ix, rec_iz, rec_ix, wavelet: torch.Tensor):
+        self.src_iz = np.ascontiguousarray(src_iz, dtype=np.int32)
+        self.src_ix = np.ascontiguousarray(src_ix, dtype=np.int32)
+        self.rec_iz = np.ascontiguousarray(rec_iz, dtype=np.int32)
+        self.rec_ix = np.ascontiguousarray(rec_ix, dtype=np.int32)
+        if self.rec_iz.ndim != 2 or self.rec_iz.shape != self.rec_ix.shape:
+            raise ValueError("rec_iz / rec_ix must be [nshots][nrec]")
+        if self.src_iz.shape != (self.rec_iz.shape[0],) or self.src_ix.shape != self.src_iz.shape:
+            raise ValueError("src_iz / src_ix must be [nshots]")
+        self.wavelet = wavelet
+
+    @property
+    def nshots(self) -> int:
+        return int(self.src_iz.shape[0])
+
+    @property
+    def nrec(self) -> int:
+        return int(self.rec_iz.shape[1])
+
+    def _c(self) -> _Geom:
+        return _Geom(self.nshots, self.nrec, self.src_iz.ctypes.data, self.src_ix.ctypes.data,
+                     self.rec_iz.ctypes.data, self.rec_ix.ctypes.data, _dptr(self.wavelet, None))
+
+
+def _dptr(t: torch.Tensor, shape) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"expected float32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """Owns a fwime_ctx_t (device scratch arena and HBM budget)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        rc = self._lib.fwime_ctx_create(self.device, int(hbm_budget_bytes), ctypes.byref(h))
+        if rc != FWIME_OK:
+            raise FwimeError(rc, self._lib.fwime_strerror(rc).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fwime_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != FWIME_OK:
+            msg = self._lib.fwime_last_error(self._h).decode() or self._lib.fwime_strerror(rc).decode()
+            raise FwimeError(rc, msg)
+
+    # --- the four entry points, with caller-provided outputs -----------------
+    def fwime_model(self, grid: Grid, vel, geom: Geometry, data):
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_model(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge),
+            _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _stream(vel.device)))
+
+    def fwime_born_ext_fwd(self, grid: Grid, vel, geom: Geometry, nh: int, ptilde, data):
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_born_ext_fwd(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(nh),
+            _dptr(ptilde, (nh, grid.nx, grid.nz)), _dptr(data, (geom.nshots, geom.nrec, grid.nt)),
+            _stream(vel.device)))
+
+    def fwime_born_ext_adj(self, grid: Grid, vel, geom: Geometry, nh: int, data, ptilde_out):
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_born_ext_adj(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(nh),
+            _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _dptr(ptilde_out, (nh, grid.nx, grid.nz)),
+            _stream(vel.device)))
+
+    def fwime_gradient(self, grid: Grid, vel, geom: Geometry, nh: int, ptilde, dobs, eps: float, dso,
+                       obj, grad_vel, grad_ptilde):
+        g = grid._c()
+        ge = geom._c()
+        dso = np.ascontiguousarray(dso, dtype=np.float64)
+        if dso.shape != (nh,):
+            raise ValueError("dso must have nh entries")
+        if not (isinstance(obj, torch.Tensor) and obj.is_cuda and obj.dtype == torch.float64 and obj.numel() == 1):
+            raise TypeError("obj must be a 1-element float64 CUDA tensor")
+        self._check(self._lib.fwime_gradient(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(nh),
+            _dptr(ptilde, (nh, grid.nx, grid.nz)), _dptr(dobs, (geom.nshots, geom.nrec, grid.nt)),
+            float(eps), dso.ctypes.data, obj.data_ptr(), _dptr(grad_vel, (grid.nx, grid.nz)),
+            _dptr(grad_ptilde, (nh, grid.nx, grid.nz)), _stream(vel.device)))
+
+    # --- allocating conveniences --------------------------------------------
+    def model(self, grid: Grid, vel, geom: Geometry):
+        data = torch.empty((geom.nshots, geom.nrec, grid.nt), device=vel.device, dtype=torch.float32)
+        self.fwime_model(grid, vel, geom, data)
+        return data
+
+    def born_ext_fwd(self, grid: Grid, vel, geom: Geometry, ptilde):
+        data = torch.empty((geom.nshots, geom.nrec, grid.nt), device=vel.device, dtype=torch.float32)
+        self.fwime_born_ext_fwd(grid, vel, geom, int(ptilde.shape[0]), ptilde, data)
+        return data
+
+    def born_ext_adj(self, grid: Grid, vel, geom: Geometry, data, nh: int):
+        out = torch.empty((nh, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        self.fwime_born_ext_adj(grid, vel, geom, nh, data, out)
+        return out
+
+    def gradient(self, grid: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
+        nh = int(ptilde.shape[0])
+        obj = torch.empty(1, device=vel.device, dtype=torch.float64)
+        gv = torch.empty((grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        gp = torch.empty((nh, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        self.fwime_gradient(grid, vel, geom, nh, ptilde, dobs, eps, dso, obj, gv, gp)
+        return obj, gv, gp

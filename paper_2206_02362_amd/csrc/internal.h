@@ -1,0 +1,140 @@
+// Internal declarations shared by the kernel and runtime translation units.
+// Not part of the public ABI (include/fwime.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fw {
+
+constexpr int kTZ = 64;        // rows (z) per tile: one wavefront, lane = z
+constexpr int kR = 4;          // stencil radius (8th-order second derivative)
+constexpr int kWaves = 4;      // wavefronts per stencil workgroup
+
+// Per-tile injection list (compressed rows over tile*kWaves + wave).
+// An entry {(j << 6) | lz, idx} adds  val[idx * stride_idx + t] * scale  to the
+// source term of the cell in column j (of the wave's columns) and row lz.
+struct Inject {
+  const int *ptr = nullptr;     // [ntiles_total * kWaves + 1]
+  const int2 *ent = nullptr;
+  const float *val = nullptr;
+  long stride_idx = 0;
+  int t = 0;
+  float scale = 1.f;
+};
+
+// Per-tile extraction list (compressed rows over tiles).  An entry
+// {(lx << 6) | lz, idx} stores the INPUT field's value of that interior tile
+// cell to out[idx * stride_idx + t].
+struct Extract {
+  const int *ptr = nullptr;     // [ntiles_total + 1]
+  const int2 *ent = nullptr;
+  float *out = nullptr;
+  long stride_idx = 0;
+  int t = 0;
+};
+
+// Dense source term read from three time slots of a field ring (the
+// transposed second time difference e_{k-1}/g - 2 e_k + g e_{k+1}).
+struct NuSource {
+  const float *em = nullptr, *e0 = nullptr, *ep = nullptr;   // shot 0 slot pointers
+  long sstride = 0;                                          // per-shot stride
+};
+
+struct StepArgs {
+  const float *cur = nullptr;   // field at the current time, [S][NX][LZ]
+  const float *prev = nullptr;  // field one step behind (read)
+  float *out = nullptr;         // next field (may alias prev)
+  const float *V = nullptr;     // v^2 dt^2, [NX][LZ]
+  const float *gz = nullptr;    // taper along z, [LZ]
+  const float *gx = nullptr;    // taper along x, [NX]
+  float *t2 = nullptr;          // optional V (L cur + src) output, [S] x t2_sstride
+  long t2_sstride = 0;
+  const float *dsrc = nullptr;  // optional dense source, [S] x dsrc_sstride
+  long dsrc_sstride = 0;
+  NuSource nu;
+  Inject inj;
+  Extract ext;
+  int NZ = 0, NX = 0, LZ = 0;
+  int nshots = 0, ntz = 0, ntx = 0;
+  long sstride = 0;             // elements between shots in cur/prev/out
+  float cz[kR] = {};            // w_k / dz^2
+  float cx[kR] = {};            // w_k / dx^2
+};
+
+enum StepMode : int {
+  kModePlain = 0,
+  kModeT2 = 1,       // also write V (L cur + src)
+  kModeDsrc = 2,     // add a dense source field
+  kModeNu = 4,       // add the e-ring second time difference as a dense source
+};
+
+// Tile width in x of the stencil kernel (columns per workgroup).
+int step_tile_x_supported(int tx);
+hipError_t launch_step(const StepArgs &a, int tile_x, int mode, hipStream_t st);
+
+// out[s][r][t] = field[s][cell[s][r]] (cell = padded x * LZ + z)
+hipError_t launch_gather(const float *field, long sstride, const int *cells, int nshots, int nrec,
+                         float *out, long stride_r, int t, hipStream_t st);
+
+// V = vpad^2 dt^2 on the padded grid (edge replication) and model-grid coefficient fields.
+hipError_t launch_prep(const float *vel, int nz, int nx, int nb, int NZ, int NX, int LZ, float dt,
+                       float *V, hipStream_t st);
+
+// min, max and non-finite count of a device array (result in a device buffer of 3 doubles)
+hipError_t launch_minmax(const float *a, long n, double *res, hipStream_t st);
+
+// Fill a float array with zeros (kernel, usable under graph capture).
+hipError_t launch_zero(float *a, long n, hipStream_t st);
+
+// dst[s * dst_sstride + i] = src[s * src_sstride + i], i < n, s < S
+hipError_t launch_copy_fields(float *dst, long dst_sstride, const float *src, long src_sstride, int S, long n,
+                              hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Subsurface-offset kernels.  Coefficient field c(z,y,h) = 2 p~ / (v^3 dt^2)
+// lives on the model grid as [nh][nx][nz].  Fields are padded [NX][LZ].
+// ---------------------------------------------------------------------------
+struct ExtGeom {
+  int nz = 0, nx = 0, nb = 0, NZ = 0, NX = 0, LZ = 0, nh = 0, H = 0;
+};
+
+// c = 2 p~ / (v^3 dt^2)
+hipError_t launch_ext_coef(const float *ptilde, const float *vel, const ExtGeom &g, float dt, float *coef,
+                           hipStream_t st);
+
+// For n < nk and every shot: out_n(z, j) = sum_h c(z, j - sg h, h) in_n(z, j - 2 sg h)
+// (sg = +1: extended scattering source; sg = -1: its transpose, the spread of
+// the receiver-side field).  in/out slot n of shot s at base + s*sstride + n*slot.
+hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const float *in, long in_slot,
+                              float *out, long out_slot, long sstride, int nshots, int nk, hipStream_t st,
+                              int in_ring = 0, int in_first = 0, int out_ring = 0, int out_first = 0);
+
+// acc(z,y,h) += sum_s sum_{n<nk} a_n(z, y-h) b_n(z, y+h).  Slot n of a is a + n*a_slot;
+// slot of b is ring index (b_first + n) % b_ring.
+hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc,
+                            hipStream_t st);
+
+// gacc(x,z) += sum_s sum_{n<nk} (t2u_n + t2d_n) lam_n + t2u_n rho_n
+hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
+                             const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
+                             int nk, int NZ, int NX, int LZ, float *gacc, hipStream_t st);
+
+// r = du + ddu - dobs (in place into du), sum r^2 ADDED to *sumsq (double)
+hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq,
+                           hipStream_t st);
+
+// ptilde_out = 2/(v^3 dt^2) acc  (+ eps^2 d_h^2 p~ when ptilde != null)
+hipError_t launch_ext_finalize(const float *acc, const float *vel, const ExtGeom &g, float dt,
+                               const float *ptilde, const float *dso2eps2, float *out, hipStream_t st);
+
+// grad_vel = P^T (2/(v^3 dt^2) gacc) - 3/v sum_h p~ img   (img already scaled)
+hipError_t launch_grad_finalize(const float *gacc, const float *V, const float *vel, const ExtGeom &g,
+                                float dt, const float *ptilde, const float *img, float *grad, hipStream_t st);
+
+// obj = 0.5 * sumsq + 0.5 * sum_h eps2d2[h] ||p~_h||^2
+hipError_t launch_objective(const double *sumsq, const float *ptilde, const float *eps2d2, const ExtGeom &g,
+                            double *obj, hipStream_t st);
+
+}  // namespace fw

@@ -1,0 +1,398 @@
+// Horizontal subsurface-offset kernels (gfx950, wave64): the extended
+// scattering source of B~, its transpose (the spread of the receiver-side
+// field used by the tomographic gradient), the extended imaging condition of
+// B~^T, the per-cell gradient accumulation and the small finalizers.
+//
+// In all of them lane = model-grid depth z, so every global access of a
+// wavefront is one contiguous 256-byte run of a z-fastest column; offsets act
+// along x only.  Time is handled in chunks: a kernel call consumes nk stored
+// time slots at once, so the coefficient field (nh x model grid) and the
+// image accumulator are touched once per chunk instead of once per step.
+#include "internal.h"
+
+namespace fw {
+
+// ---------------------------------------------------------------------------
+// c(z,y,h) = 2 p~(z,y,h) / (v(z,y)^3 dt^2), model grid, [nh][nx][nz]
+// ---------------------------------------------------------------------------
+__global__ void k_ext_coef(const float *pt, const float *vel, int nz, int nx, int nh, float dt, float *coef) {
+  const long n = (long)nh * nx * nz;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long cell = i % ((long)nx * nz);
+    const float v = vel[cell];
+    coef[i] = 2.f * pt[i] / (v * v * v * dt * dt);
+  }
+}
+
+hipError_t launch_ext_coef(const float *ptilde, const float *vel, const ExtGeom &g, float dt, float *coef,
+                           hipStream_t st) {
+  const long n = (long)g.nh * g.nx * g.nz;
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_ext_coef<<<(unsigned)blocks, 256, 0, st>>>(ptilde, vel, g.nz, g.nx, g.nh, dt, coef);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scatter (sg = +1) / spread (sg = -1):
+//   out_n(z, j) = sum_h c(z, j - sg h, h) in_n(z, j - 2 sg h)
+// One thread per (model z, padded column j); the coefficient of each h is
+// loaded once and reused over a sub-chunk of KC time slots held in registers.
+// Cells outside the written range are never touched (the caller zeroes the
+// output buffers once).
+// ---------------------------------------------------------------------------
+constexpr int kScatterKC = 16;
+
+struct ScatterArgs {
+  const float *coef;
+  const float *in;
+  float *out;
+  long in_slot, out_slot, sstride;
+  int in_ring, in_first, out_ring, out_first;
+  int nz, nx, nb, NX, LZ, nh, H, sg;
+  int j0, nj;       // padded columns [j0, j0 + nj)
+  int nzs;          // z strips
+  int nk, nshots;
+};
+
+__global__ void __launch_bounds__(256) k_ext_scatter(const ScatterArgs a) {
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int per_shot = a.nzs * a.nj;
+  const int s = wave / per_shot;
+  if (s >= a.nshots) return;
+  const int rem = wave - s * per_shot;
+  const int jj = rem / a.nzs;
+  const int zs = rem - jj * a.nzs;
+  const int j = __builtin_amdgcn_readfirstlane(a.j0 + jj);
+  const int z = zs * 64 + lane;
+  const bool zin = z < a.nz;
+  const int zp = a.nb + z;
+  const long sb = (long)s * a.sstride;
+
+  for (int n0 = 0; n0 < a.nk; n0 += kScatterKC) {
+    float acc[kScatterKC];
+#pragma unroll
+    for (int m = 0; m < kScatterKC; ++m) acc[m] = 0.f;
+    const int nn = min(kScatterKC, a.nk - n0);
+    for (int ih = -a.H; ih <= a.H; ++ih) {
+      const int y = j - a.sg * ih - a.nb;
+      const int i = j - 2 * a.sg * ih;
+      if (y < 0 || y >= a.nx || i < 0 || i >= a.NX) continue;   // wave-uniform
+      const float c = zin ? a.coef[((long)(ih + a.H) * a.nx + y) * a.nz + z] : 0.f;
+      const long off = sb + (long)i * a.LZ + zp;
+#pragma unroll
+      for (int m = 0; m < kScatterKC; ++m) {
+        if (m < nn) {
+          const int n = n0 + m;
+          const long slot = a.in_ring ? (long)((a.in_first + n) % a.in_ring) : (long)n;
+          const float v = zin ? a.in[off + slot * a.in_slot] : 0.f;
+          acc[m] += c * v;
+        }
+      }
+    }
+    if (zin) {
+      const long off = sb + (long)j * a.LZ + zp;
+#pragma unroll
+      for (int m = 0; m < kScatterKC; ++m) {
+        if (m < nn) {
+          const int n = n0 + m;
+          const long slot = a.out_ring ? (long)((a.out_first + n) % a.out_ring) : (long)n;
+          a.out[off + slot * a.out_slot] = acc[m];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const float *in, long in_slot,
+                              float *out, long out_slot, long sstride, int nshots, int nk, hipStream_t st,
+                              int in_ring, int in_first, int out_ring, int out_first) {
+  if (nk <= 0 || nshots <= 0) return hipSuccess;
+  ScatterArgs a;
+  a.coef = coef;
+  a.in = in;
+  a.out = out;
+  a.in_slot = in_slot;
+  a.out_slot = out_slot;
+  a.sstride = sstride;
+  a.in_ring = in_ring;
+  a.in_first = in_first;
+  a.out_ring = out_ring;
+  a.out_first = out_first;
+  a.nz = g.nz;
+  a.nx = g.nx;
+  a.nb = g.nb;
+  a.NX = g.NX;
+  a.LZ = g.LZ;
+  a.nh = g.nh;
+  a.H = g.H;
+  a.sg = sg;
+  // columns that can receive a nonzero value: j = nb + y + sg h
+  a.j0 = max(0, g.nb - g.H);
+  const int j1 = min(g.NX, g.nb + g.nx + g.H);
+  a.nj = j1 - a.j0;
+  a.nzs = (g.nz + 63) / 64;
+  a.nk = nk;
+  a.nshots = nshots;
+  const long waves = (long)nshots * a.nzs * a.nj;
+  k_ext_scatter<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Extended imaging condition:
+//   acc(z, y, h) += sum_s sum_n a_n(z, y - h) b_n(z, y + h)
+// A wavefront owns a YT x HT tile of (y, h) for 64 depths; per time slot it
+// loads YT + HT - 1 source-side and receiver-side columns into registers and
+// performs YT * HT multiply-adds.
+// ---------------------------------------------------------------------------
+constexpr int kImgYT = 8;
+constexpr int kImgHT = 8;
+
+struct ImageArgs {
+  const float *a;
+  const float *b;
+  float *acc;
+  long a_slot, b_slot, a_sstride, b_sstride;
+  int b_ring, b_first;
+  int nshots, nk;
+  int nz, nx, nb, NX, LZ, nh, H;
+  int nzs, nyt, nht;
+};
+
+__global__ void __launch_bounds__(256) k_ext_image(const ImageArgs p) {
+  constexpr int NA = kImgYT + kImgHT - 1;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int total = p.nzs * p.nyt * p.nht;
+  if (wave >= total) return;
+  const int zs = wave % p.nzs;
+  const int r = wave / p.nzs;
+  const int yt = r % p.nyt;
+  const int ht = r / p.nyt;
+  const int ya = yt * kImgYT;
+  const int ib0 = -p.H + ht * kImgHT;
+  const int z = zs * 64 + lane;
+  const bool zin = z < p.nz;
+  const int zp = p.nb + z;
+  const int ca = p.nb + ya - ib0 - (kImgHT - 1);   // padded column of a[0]
+  const int cbb = p.nb + ya + ib0;                  // padded column of b[0]
+
+  float acc[kImgYT][kImgHT];
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
+
+  for (int s = 0; s < p.nshots; ++s) {
+    for (int n = 0; n < p.nk; ++n) {
+      const float *an = p.a + (long)s * p.a_sstride + (long)n * p.a_slot;
+      const float *bn = p.b + (long)s * p.b_sstride + (long)((p.b_first + n) % p.b_ring) * p.b_slot;
+      float va[NA], vb[NA];
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        const int xa = ca + m;
+        const int xb = cbb + m;
+        va[m] = (zin && (unsigned)xa < (unsigned)p.NX) ? an[(long)xa * p.LZ + zp] : 0.f;
+        vb[m] = (zin && (unsigned)xb < (unsigned)p.NX) ? bn[(long)xb * p.LZ + zp] : 0.f;
+      }
+#pragma unroll
+      for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+        for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
+    }
+  }
+  if (!zin) return;
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy) {
+    const int y = ya + yy;
+    if (y >= p.nx) continue;
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) {
+      const int ih = ib0 + hh;
+      if (ih > p.H) continue;
+      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
+      p.acc[o] += acc[yy][hh];
+    }
+  }
+}
+
+hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc,
+                            hipStream_t st) {
+  if (nk <= 0 || nshots <= 0) return hipSuccess;
+  ImageArgs p;
+  p.a = a;
+  p.b = b;
+  p.acc = acc;
+  p.a_slot = a_slot;
+  p.b_slot = b_slot;
+  p.a_sstride = a_sstride;
+  p.b_sstride = b_sstride;
+  p.b_ring = b_ring;
+  p.b_first = b_first;
+  p.nshots = nshots;
+  p.nk = nk;
+  p.nz = g.nz;
+  p.nx = g.nx;
+  p.nb = g.nb;
+  p.NX = g.NX;
+  p.LZ = g.LZ;
+  p.nh = g.nh;
+  p.H = g.H;
+  p.nzs = (g.nz + 63) / 64;
+  p.nyt = (g.nx + kImgYT - 1) / kImgYT;
+  p.nht = (g.nh + kImgHT - 1) / kImgHT;
+  const long waves = (long)p.nzs * p.nyt * p.nht;
+  k_ext_image<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gacc(x, z) += sum_s sum_n (t2u_n + t2d_n) lam_n + t2u_n rho_n   (padded grid)
+// ---------------------------------------------------------------------------
+__global__ void k_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
+                             const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
+                             int nk, int NZ, long ncell, int LZ, float *gacc) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const int z = (int)(i % LZ);
+  if (z >= NZ) return;
+  float g = 0.f;
+  for (int s = 0; s < nshots; ++s) {
+    const long sa = (long)s * seg_sstride + i;
+    const long sr = (long)s * ring_sstride + i;
+    for (int n = 0; n < nk; ++n) {
+      const long rs = (long)((first + n) % ring) * ring_slot;
+      const float u = t2u[sa + n * slot];
+      const float d = t2d[sa + n * slot];
+      g += (u + d) * lam[sr + rs] + u * rho[sr + rs];
+    }
+  }
+  gacc[i] += g;
+}
+
+hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
+                             const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
+                             int nk, int NZ, int NX, int LZ, float *gacc, hipStream_t st) {
+  if (nk <= 0 || nshots <= 0) return hipSuccess;
+  const long ncell = (long)NX * LZ;
+  k_grad_accum<<<(unsigned)((ncell + 255) / 256), 256, 0, st>>>(t2u, t2d, slot, seg_sstride, lam, rho, ring_slot,
+                                                                 ring_sstride, ring, first, nshots, nk, NZ, ncell,
+                                                                 LZ, gacc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Residual and sum of squares (FP64 accumulation).
+// ---------------------------------------------------------------------------
+__global__ void k_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq) {
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float r = du[i] + ddu[i] - dobs[i];
+    du[i] = r;
+    acc += (double)r * (double)r;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(sumsq, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq,
+                           hipStream_t st) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_residual<<<(unsigned)blocks, 256, 0, st>>>(du, ddu, dobs, n, sumsq);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Finalizers
+// ---------------------------------------------------------------------------
+__global__ void k_ext_finalize(const float *acc, const float *vel, int nz, int nx, int nh, float dt,
+                               const float *pt, const float *e2d2, float *out) {
+  const long n = (long)nh * nx * nz;
+  const long plane = (long)nx * nz;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float v = vel[i % plane];
+    float r = 2.f * acc[i] / (v * v * v * dt * dt);
+    if (pt != nullptr) r += e2d2[i / plane] * pt[i];
+    out[i] = r;
+  }
+}
+
+hipError_t launch_ext_finalize(const float *acc, const float *vel, const ExtGeom &g, float dt,
+                               const float *ptilde, const float *dso2eps2, float *out, hipStream_t st) {
+  const long n = (long)g.nh * g.nx * g.nz;
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_ext_finalize<<<(unsigned)blocks, 256, 0, st>>>(acc, vel, g.nz, g.nx, g.nh, dt, ptilde, dso2eps2, out);
+  return hipGetLastError();
+}
+
+// grad(y, z) = 2/(v^3 dt^2) sum_{padded cells copied from (y,z)} gacc - 3/v sum_h p~ img
+__global__ void k_grad_finalize(const float *gacc, const float *vel, int nz, int nx, int nb, int NZ, int NX, int LZ,
+                                int nh, float dt, const float *pt, const float *img, float *grad) {
+  const long plane = (long)nx * nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+  const int y = (int)(i / nz);
+  const int z = (int)(i - (long)y * nz);
+  const int x0 = (y == 0) ? 0 : nb + y;
+  const int x1 = (y == nx - 1) ? NX - 1 : nb + y;
+  const int z0 = (z == 0) ? 0 : nb + z;
+  const int z1 = (z == nz - 1) ? NZ - 1 : nb + z;
+  float sum = 0.f;
+  for (int x = x0; x <= x1; ++x)
+    for (int zz = z0; zz <= z1; ++zz) sum += gacc[(long)x * LZ + zz];
+  const float v = vel[i];
+  float g = 2.f * sum / (v * v * v * dt * dt);
+  if (pt != nullptr) {
+    float t = 0.f;
+    for (int h = 0; h < nh; ++h) t += pt[h * plane + i] * img[h * plane + i];
+    g -= 3.f * t / v;
+  }
+  grad[i] = g;
+}
+
+hipError_t launch_grad_finalize(const float *gacc, const float *V, const float *vel, const ExtGeom &g, float dt,
+                                const float *ptilde, const float *img, float *grad, hipStream_t st) {
+  (void)V;
+  const long plane = (long)g.nx * g.nz;
+  k_grad_finalize<<<(unsigned)((plane + 255) / 256), 256, 0, st>>>(gacc, vel, g.nz, g.nx, g.nb, g.NZ, g.NX, g.LZ,
+                                                                    g.nh, dt, ptilde, img, grad);
+  return hipGetLastError();
+}
+
+__global__ void k_obj_init(const double *sumsq, double *obj) { *obj = 0.5 * (*sumsq); }
+
+__global__ void k_obj_reg(const float *pt, const float *e2d2, long plane, int nh, double *obj) {
+  double acc = 0.0;
+  const long n = plane * nh;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double p = pt[i];
+    acc += 0.5 * (double)e2d2[i / plane] * p * p;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(obj, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_objective(const double *sumsq, const float *ptilde, const float *eps2d2, const ExtGeom &g,
+                            double *obj, hipStream_t st) {
+  k_obj_init<<<1, 1, 0, st>>>(sumsq, obj);
+  const long plane = (long)g.nx * g.nz;
+  long blocks = (plane * g.nh + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_obj_reg<<<(unsigned)blocks, 256, 0, st>>>(ptilde, eps2d2, plane, g.nh, obj);
+  return hipGetLastError();
+}
+
+}  // namespace fw

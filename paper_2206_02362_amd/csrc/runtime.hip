@@ -1,0 +1,901 @@
+// Host runtime of the FWIME hot-path library: the C ABI of include/fwime.h.
+//
+// Responsibilities: input validation (including the CFL test, which needs the
+// velocity range and therefore one small device reduction), the context's
+// device-memory arena under an HBM budget, the per-tile source/receiver tables
+// consumed by the stencil kernel, shot batching, and the time loops with
+// sqrt(nt) wavefield checkpointing for the adjoint-state operators.
+//
+// Time bookkeeping (equation n = 0 .. nt-2 advances u^n -> u^{n+1}):
+//   - forward: the kernel of equation n reads u^n, u^{n-1}, writes u^{n+1},
+//     injects f^n and records u^n at the receivers; u^{nt-1} is gathered after
+//     the loop;
+//   - adjoint: the kernel of index k = nt-1 .. 1 reads lambda_k, lambda_{k+1},
+//     writes lambda_{k-1} and injects the adjoint source of time k;
+//   - segments of K = ceil(sqrt(nt - 1)) equations: the forward pass stores
+//     (u^{n0-1}, u^{n0}) at each segment start n0; the backward pass recomputes
+//     one segment from its checkpoint, keeping T2u_n = V (L u^n + f^n) for the
+//     segment, while the adjoint fields live in rings of K + 2 time slots.
+#include "../../include/fwime.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace fw;
+
+struct fwime_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::string err;
+  void *arena = nullptr;
+  size_t arena_bytes = 0;
+  double *host_red = nullptr;   // pinned: reduction results
+  int tile_x = 32;
+};
+
+namespace {
+
+constexpr double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+int set_err(fwime_ctx_t *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(ctx, FWIME_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double cfl_limit(double dz, double dx) {
+  double nyq = -(kW[0] + 2.0 * (-kW[1] + kW[2] - kW[3] + kW[4]));
+  return 2.0 / std::sqrt(nyq * (1.0 / (dz * dz) + 1.0 / (dx * dx)));
+}
+
+struct Dims {
+  int nz, nx, nb, nt, NZ, NX, LZ, ntz, ntx, TX;
+  long field;   // NX * LZ
+};
+
+Dims make_dims(const fwime_grid_t *g, int tx) {
+  Dims d;
+  d.nz = g->nz;
+  d.nx = g->nx;
+  d.nb = g->nb;
+  d.nt = g->nt;
+  d.NZ = g->nz + 2 * g->nb;
+  d.NX = g->nx + 2 * g->nb;
+  d.LZ = (d.NZ + 63) / 64 * 64;
+  d.TX = tx;
+  d.ntz = (d.NZ + kTZ - 1) / kTZ;
+  d.ntx = (d.NX + tx - 1) / tx;
+  d.field = (long)d.NX * d.LZ;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Arena: one device allocation carved into aligned pieces for one call.
+// ---------------------------------------------------------------------------
+struct Carve {
+  std::vector<std::pair<void **, size_t>> items;
+  size_t total = 0;
+  template <class T>
+  void add(T **p, size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) / 256 * 256;
+    items.push_back({(void **)p, bytes});
+    total += bytes;
+  }
+};
+
+int arena_get(fwime_ctx_t *ctx, Carve &cv) {
+  if (cv.total > ctx->arena_bytes) {
+    if (ctx->budget && cv.total > ctx->budget)
+      return set_err(ctx, FWIME_ENOMEM, "request of " + std::to_string(cv.total) + " bytes exceeds the HBM budget");
+    if (ctx->arena) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(ctx->arena));
+      ctx->arena = nullptr;
+      ctx->arena_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->arena, cv.total);
+    if (e != hipSuccess) {
+      ctx->arena = nullptr;
+      (void)hipGetLastError();
+      return set_err(ctx, FWIME_ENOMEM, "hipMalloc of " + std::to_string(cv.total) + " bytes failed");
+    }
+    ctx->arena_bytes = cv.total;
+  }
+  char *p = (char *)ctx->arena;
+  for (auto &it : cv.items) {
+    *it.first = p;
+    p += it.second;
+  }
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+int check_grid(fwime_ctx_t *ctx, const fwime_grid_t *g) {
+  if (!g) return set_err(ctx, FWIME_EINVAL, "grid is null");
+  if (g->nz < 1 || g->nx < 1 || g->nb < 0 || g->nt < 2)
+    return set_err(ctx, FWIME_EINVAL, "grid needs nz, nx >= 1, nb >= 0, nt >= 2");
+  if (!(g->dz > 0 && g->dx > 0 && g->dt > 0) || !std::isfinite(g->dz) || !std::isfinite(g->dx) ||
+      !std::isfinite(g->dt))
+    return set_err(ctx, FWIME_EINVAL, "dz, dx, dt must be positive and finite");
+  if (!(g->sponge_alpha >= 0) || !std::isfinite(g->sponge_alpha))
+    return set_err(ctx, FWIME_EINVAL, "sponge_alpha must be >= 0");
+  const long NZ = (long)g->nz + 2L * g->nb, NX = (long)g->nx + 2L * g->nb;
+  if (NZ * NX > (1L << 30)) return set_err(ctx, FWIME_EINVAL, "padded grid too large");
+  return FWIME_OK;
+}
+
+int check_geom(fwime_ctx_t *ctx, const fwime_grid_t *g, const fwime_geom_t *geo) {
+  if (!geo) return set_err(ctx, FWIME_EINVAL, "geometry is null");
+  if (geo->nshots < 1 || geo->nrec < 1) return set_err(ctx, FWIME_EINVAL, "need nshots >= 1 and nrec >= 1");
+  if (!geo->src_iz || !geo->src_ix || !geo->rec_iz || !geo->rec_ix || !geo->wavelet)
+    return set_err(ctx, FWIME_EINVAL, "geometry pointer is null");
+  for (int s = 0; s < geo->nshots; ++s) {
+    if (geo->src_iz[s] < 0 || geo->src_iz[s] >= g->nz || geo->src_ix[s] < 0 || geo->src_ix[s] >= g->nx)
+      return set_err(ctx, FWIME_EINVAL, "source " + std::to_string(s) + " outside the model grid");
+  }
+  const long n = (long)geo->nshots * geo->nrec;
+  for (long i = 0; i < n; ++i) {
+    if (geo->rec_iz[i] < 0 || geo->rec_iz[i] >= g->nz || geo->rec_ix[i] < 0 || geo->rec_ix[i] >= g->nx)
+      return set_err(ctx, FWIME_EINVAL, "receiver " + std::to_string(i) + " outside the model grid");
+  }
+  return FWIME_OK;
+}
+
+int check_nh(fwime_ctx_t *ctx, const fwime_grid_t *g, int nh) {
+  if (nh < 1 || nh % 2 == 0 || nh > 2 * g->nx - 1)
+    return set_err(ctx, FWIME_EINVAL, "nh must be odd with 1 <= nh <= 2 nx - 1");
+  return FWIME_OK;
+}
+
+// min / max / non-finite count of a device array, synchronously.
+int device_range(fwime_ctx_t *ctx, const float *a, long n, double *scratch, hipStream_t st, double out[3]) {
+  HIPCHK(launch_minmax(a, n, scratch, st));
+  HIPCHK(hipMemcpyAsync(ctx->host_red, scratch, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out[0] = ctx->host_red[0];
+  out[1] = ctx->host_red[1];
+  out[2] = ctx->host_red[2];
+  return FWIME_OK;
+}
+
+// Common prologue: validates velocity (positive, finite, CFL) and the other
+// float inputs; runs before any output is touched.
+int check_inputs(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                 std::vector<std::pair<const float *, long>> extra, hipStream_t st) {
+  if (!vel) return set_err(ctx, FWIME_EINVAL, "vel is null");
+  double *scratch = nullptr;
+  Carve cv;
+  cv.add(&scratch, 4);
+  // The scratch reduction buffer sits at the front of the arena; a later
+  // carve of the same call reuses the memory (the reduction is complete).
+  int rc = arena_get(ctx, cv);
+  if (rc) return rc;
+  double r[3];
+  rc = device_range(ctx, vel, (long)g->nx * g->nz, scratch, st, r);
+  if (rc) return rc;
+  if (r[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "vel has non-finite values");
+  if (!(r[0] > 0)) return set_err(ctx, FWIME_EINVAL, "velocity must be positive");
+  if (r[1] * g->dt > cfl_limit(g->dz, g->dx) * (1 + 1e-12))
+    return set_err(ctx, FWIME_EINVAL, "CFL condition violated: v_max dt = " + std::to_string(r[1] * g->dt) +
+                                          " > " + std::to_string(cfl_limit(g->dz, g->dx)));
+  extra.push_back({geo->wavelet, (long)geo->nshots * g->nt});
+  for (auto &e : extra) {
+    if (!e.first) return set_err(ctx, FWIME_EINVAL, "input pointer is null");
+    rc = device_range(ctx, e.first, e.second, scratch, st, r);
+    if (rc) return rc;
+    if (r[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "input array has non-finite values");
+  }
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry tables for one batch of shots [s0, s0 + S).  Indices stored in the
+// tables are batch-local (shot s, receiver s * nrec + r); callers offset the
+// wavelet and data pointers to the batch start.
+// ---------------------------------------------------------------------------
+struct HostTables {
+  std::vector<int> src_ptr, rext_ptr, rinj_ptr, cells;
+  std::vector<int2> src_ent, rext_ent, rinj_ent;
+};
+
+struct DevTables {
+  int *src_ptr, *rext_ptr, *rinj_ptr, *cells;
+  int2 *src_ent, *rext_ent, *rinj_ent;
+};
+
+void csr_build(std::vector<int> &ptr, std::vector<int2> &ent, long nbucket,
+               const std::vector<std::pair<long, int2>> &items) {
+  ptr.assign(nbucket + 1, 0);
+  for (auto &it : items) ptr[it.first + 1]++;
+  for (long b = 0; b < nbucket; ++b) ptr[b + 1] += ptr[b];
+  ent.resize(items.size());
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (auto &it : items) ent[fill[it.first]++] = it.second;
+  // inject lists are consumed in column order by each wave
+  for (long b = 0; b < nbucket; ++b)
+    std::stable_sort(ent.begin() + ptr[b], ent.begin() + ptr[b + 1],
+                     [](const int2 &a, const int2 &c) { return (a.x >> 6) < (c.x >> 6); });
+}
+
+HostTables build_tables(const Dims &d, const fwime_geom_t *geo, int s0, int S) {
+  HostTables t;
+  const int CPW = d.TX / kWaves;
+  const long ntiles = (long)d.ntz * d.ntx * S;
+  auto locate = [&](int s, int px, int pz, long &tile, int &lx, int &lz) {
+    const int txi = px / d.TX, tzi = pz / kTZ;
+    tile = ((long)txi * d.ntz + tzi) * S + s;
+    lx = px - txi * d.TX;
+    lz = pz - tzi * kTZ;
+  };
+  std::vector<std::pair<long, int2>> src, rext, rinj;
+  for (int s = 0; s < S; ++s) {
+    const int sg = s0 + s;
+    long tile;
+    int lx, lz;
+    locate(s, geo->src_ix[sg] + d.nb, geo->src_iz[sg] + d.nb, tile, lx, lz);
+    src.push_back({tile * kWaves + lx / CPW, make_int2(((lx % CPW) << 6) | lz, s)});
+    for (int r = 0; r < geo->nrec; ++r) {
+      const long ir = (long)sg * geo->nrec + r;      // global receiver (geometry lookup)
+      const int il = s * geo->nrec + r;              // batch-local receiver (table index)
+      const int px = geo->rec_ix[ir] + d.nb, pz = geo->rec_iz[ir] + d.nb;
+      locate(s, px, pz, tile, lx, lz);
+      rext.push_back({tile, make_int2((lx << 6) | lz, il)});
+      rinj.push_back({tile * kWaves + lx / CPW, make_int2(((lx % CPW) << 6) | lz, il)});
+      t.cells.push_back(px * d.LZ + pz);
+    }
+  }
+  csr_build(t.src_ptr, t.src_ent, ntiles * kWaves, src);
+  csr_build(t.rext_ptr, t.rext_ent, ntiles, rext);
+  csr_build(t.rinj_ptr, t.rinj_ent, ntiles * kWaves, rinj);
+  return t;
+}
+
+size_t tables_ints(const HostTables &t) {
+  return t.src_ptr.size() + t.rext_ptr.size() + t.rinj_ptr.size() + t.cells.size() +
+         2 * (t.src_ent.size() + t.rext_ent.size() + t.rinj_ent.size()) + 7 * 64;
+}
+
+// Lay out all batch tables into one host blob and one device buffer.
+struct TableSet {
+  std::vector<HostTables> host;
+  std::vector<DevTables> dev;
+  std::vector<int> blob;
+};
+
+TableSet build_table_set(const Dims &d, const fwime_geom_t *geo, const std::vector<std::pair<int, int>> &batches) {
+  TableSet ts;
+  for (auto &b : batches) ts.host.push_back(build_tables(d, geo, b.first, b.second));
+  return ts;
+}
+
+size_t table_set_ints(const TableSet &ts) {
+  size_t n = 0;
+  for (auto &t : ts.host) n += tables_ints(t);
+  return n;
+}
+
+int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
+  ts.blob.clear();
+  ts.dev.clear();
+  auto put = [&](const void *src, size_t nint) -> size_t {
+    size_t off = (ts.blob.size() + 63) / 64 * 64;
+    ts.blob.resize(off + nint);
+    if (nint) std::memcpy(ts.blob.data() + off, src, nint * sizeof(int));
+    return off;
+  };
+  std::vector<std::vector<size_t>> offs;
+  for (auto &t : ts.host) {
+    std::vector<size_t> o;
+    o.push_back(put(t.src_ptr.data(), t.src_ptr.size()));
+    o.push_back(put(t.rext_ptr.data(), t.rext_ptr.size()));
+    o.push_back(put(t.rinj_ptr.data(), t.rinj_ptr.size()));
+    o.push_back(put(t.cells.data(), t.cells.size()));
+    o.push_back(put(t.src_ent.data(), 2 * t.src_ent.size()));
+    o.push_back(put(t.rext_ent.data(), 2 * t.rext_ent.size()));
+    o.push_back(put(t.rinj_ent.data(), 2 * t.rinj_ent.size()));
+    offs.push_back(o);
+  }
+  for (auto &o : offs) {
+    DevTables dt;
+    dt.src_ptr = dev + o[0];
+    dt.rext_ptr = dev + o[1];
+    dt.rinj_ptr = dev + o[2];
+    dt.cells = dev + o[3];
+    dt.src_ent = (int2 *)(dev + o[4]);
+    dt.rext_ent = (int2 *)(dev + o[5]);
+    dt.rinj_ent = (int2 *)(dev + o[6]);
+    ts.dev.push_back(dt);
+  }
+  // The blob is copied synchronously (pageable memory): the call owns no
+  // host staging that could outlive it.
+  HIPCHK(hipMemcpyAsync(dev, ts.blob.data(), ts.blob.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Shared per-call state
+// ---------------------------------------------------------------------------
+struct Common {
+  Dims d;
+  float *V = nullptr, *gz = nullptr, *gx = nullptr;
+  int *tables = nullptr;
+  StepArgs base;
+};
+
+void taper_host(int n, int nb, double alpha, int len, std::vector<float> &out) {
+  out.assign(len, 0.f);
+  for (int i = 0; i < n + 2 * nb; ++i) {
+    int k = 0;
+    if (i < nb) k = nb - i;
+    else if (i >= nb + n) k = i - (nb + n - 1);
+    const double a = nb > 0 ? alpha * k / nb : 0.0;
+    out[i] = (float)std::exp(-a * a);
+  }
+}
+
+int setup_common(fwime_ctx_t *ctx, Common &c, const fwime_grid_t *g, const float *vel, hipStream_t st) {
+  const Dims &d = c.d;
+  HIPCHK(launch_prep(vel, d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, (float)g->dt, c.V, st));
+  std::vector<float> gz, gx;
+  taper_host(d.nz, d.nb, g->sponge_alpha, d.LZ, gz);
+  taper_host(d.nx, d.nb, g->sponge_alpha, d.NX, gx);
+  HIPCHK(hipMemcpyAsync(c.gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(c.gx, gx.data(), gx.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  StepArgs &a = c.base;
+  a = StepArgs();
+  a.V = c.V;
+  a.gz = c.gz;
+  a.gx = c.gx;
+  a.NZ = d.NZ;
+  a.NX = d.NX;
+  a.LZ = d.LZ;
+  a.ntz = d.ntz;
+  a.ntx = d.ntx;
+  const double idz2 = 1.0 / (g->dz * g->dz), idx2 = 1.0 / (g->dx * g->dx);
+  for (int k = 0; k < kR; ++k) {
+    a.cz[k] = (float)(kW[k + 1] * idz2);
+    a.cx[k] = (float)(kW[k + 1] * idx2);
+  }
+  return FWIME_OK;
+}
+
+// Step-argument helpers for one batch.
+StepArgs batch_args(const Common &c, int S, long sstride) {
+  StepArgs a = c.base;
+  a.nshots = S;
+  a.sstride = sstride;
+  return a;
+}
+
+void with_src(StepArgs &a, const DevTables &t, const fwime_geom_t *geo, const fwime_grid_t *g, int s0, int n) {
+  a.inj.ptr = t.src_ptr;
+  a.inj.ent = t.src_ent;
+  a.inj.val = geo->wavelet + (long)s0 * g->nt;
+  a.inj.stride_idx = g->nt;
+  a.inj.t = n;
+  a.inj.scale = (float)(1.0 / (g->dx * g->dz));
+}
+
+void with_rec_inject(StepArgs &a, const DevTables &t, const float *data, int nt, int k) {
+  a.inj.ptr = t.rinj_ptr;
+  a.inj.ent = t.rinj_ent;
+  a.inj.val = data;
+  a.inj.stride_idx = nt;
+  a.inj.t = k;
+  a.inj.scale = 1.f;
+}
+
+void with_rec_extract(StepArgs &a, const DevTables &t, float *data, int nt, int n) {
+  a.ext.ptr = t.rext_ptr;
+  a.ext.ent = t.rext_ent;
+  a.ext.out = data;
+  a.ext.stride_idx = nt;
+  a.ext.t = n;
+}
+
+int choose_batch(fwime_ctx_t *ctx, long per_shot_bytes, size_t fixed_bytes, int nshots) {
+  size_t avail = 0, total = 0;
+  if (hipMemGetInfo(&avail, &total) != hipSuccess) avail = 0;
+  avail += ctx->arena_bytes;               // the arena can be reused
+  size_t cap = (size_t)(avail * 0.85);
+  if (ctx->budget && ctx->budget < cap) cap = ctx->budget;
+  if (cap <= fixed_bytes) return 1;
+  long S = (long)((cap - fixed_bytes) / std::max<long>(per_shot_bytes, 1));
+  S = std::max<long>(1, std::min<long>(S, nshots));
+  return (int)S;
+}
+
+std::vector<std::pair<int, int>> split_batches(int nshots, int S) {
+  std::vector<std::pair<int, int>> b;
+  const int nb = (nshots + S - 1) / S;
+  const int base = nshots / nb, extra = nshots % nb;   // balanced batch sizes
+  int s0 = 0;
+  for (int i = 0; i < nb; ++i) {
+    const int n = base + (i < extra ? 1 : 0);
+    b.push_back({s0, n});
+    s0 += n;
+  }
+  return b;
+}
+
+int seg_len(int nt) {
+  int K = (int)std::ceil(std::sqrt((double)(nt - 1)));
+  return std::max(K, 1);
+}
+
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *fwime_strerror(int code) {
+  switch (code) {
+    case FWIME_OK: return "ok";
+    case FWIME_EINVAL: return "invalid argument";
+    case FWIME_ENOMEM: return "out of device memory or HBM budget";
+    case FWIME_EHIP: return "HIP runtime error";
+    case FWIME_ENONFINITE: return "non-finite input";
+    default: return "unknown error";
+  }
+}
+
+const char *fwime_last_error(const fwime_ctx_t *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
+  if (!out) return FWIME_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FWIME_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return FWIME_EHIP;
+  fwime_ctx_t *ctx = new fwime_ctx_t();
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  if (hipHostMalloc((void **)&ctx->host_red, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return FWIME_EHIP;
+  }
+  const char *tx = std::getenv("FWIME_TILE_X");
+  if (tx && step_tile_x_supported(std::atoi(tx))) ctx->tile_x = std::atoi(tx);
+  *out = ctx;
+  return FWIME_OK;
+}
+
+void fwime_ctx_destroy(fwime_ctx_t *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->host_red) (void)hipHostFree(ctx->host_red);
+  delete ctx;
+}
+
+// ---------------------------------------------------------------------------
+int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo, float *data,
+                void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo))) return rc;
+  if (!data) return set_err(ctx, FWIME_EINVAL, "data is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  const long per_shot = 2 * d.field * 4 + (long)geo->nrec * 64;
+  const int S = choose_batch(ctx, per_shot, (size_t)d.field * 8, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches);
+
+  float *fields = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&fields, 2 * d.field * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    float *A = fields, *B = fields + d.field * Sb;
+    HIPCHK(launch_zero(fields, 2 * d.field * Sb, st));
+    float *cur = A, *prev = B;
+    float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    for (int n = 0; n < g->nt - 1; ++n) {
+      StepArgs a = batch_args(c, Sb, d.field);
+      a.cur = cur;
+      a.prev = prev;
+      a.out = prev;
+      with_src(a, t, geo, g, s0, n);
+      with_rec_extract(a, t, out_b, g->nt, n);
+      HIPCHK(launch_step(a, d.TX, kModePlain, st));
+      std::swap(cur, prev);
+    }
+    HIPCHK(launch_gather(cur, d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
+  }
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       int32_t nh, const float *ptilde, float *data, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if (!data || !ptilde) return set_err(ctx, FWIME_EINVAL, "data or ptilde is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {{ptilde, (long)nh * g->nx * g->nz}}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
+  const int KC = 16;
+  const long per_shot = (4 + 2L * KC) * d.field * 4 + (long)geo->nrec * 64;
+  const size_t fixed = (size_t)d.field * 8 + (size_t)nh * d.nx * d.nz * 4;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches);
+
+  float *coef = nullptr, *pairs = nullptr, *t2 = nullptr, *sc = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&coef, (long)nh * d.nx * d.nz);
+  cv.add(&pairs, 4 * d.field * S);
+  cv.add(&t2, (long)KC * d.field * S);
+  cv.add(&sc, (long)KC * d.field * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  HIPCHK(launch_ext_coef(ptilde, vel, eg, (float)g->dt, coef, st));
+
+  const long chunk_stride = (long)KC * d.field;   // per shot in t2 / sc
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    float *u0 = pairs, *u1 = pairs + d.field * Sb;
+    float *w0 = pairs + 2 * d.field * Sb, *w1 = pairs + 3 * d.field * Sb;
+    HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
+    HIPCHK(launch_zero(sc, chunk_stride * Sb, st));
+    float *ucur = u0, *uprev = u1, *wcur = w0, *wprev = w1;
+    for (int c0 = 0; c0 < g->nt - 1; c0 += KC) {
+      const int nk = std::min(KC, g->nt - 1 - c0);
+      for (int m = 0; m < nk; ++m) {
+        StepArgs a = batch_args(c, Sb, d.field);
+        a.cur = ucur;
+        a.prev = uprev;
+        a.out = uprev;
+        a.t2 = t2 + m * d.field;
+        a.t2_sstride = chunk_stride;
+        with_src(a, t, geo, g, s0, c0 + m);
+        HIPCHK(launch_step(a, d.TX, kModeT2, st));
+        std::swap(ucur, uprev);
+      }
+      HIPCHK(launch_ext_scatter(coef, eg, +1, t2, d.field, sc, d.field, chunk_stride, Sb, nk, st));
+      for (int m = 0; m < nk; ++m) {
+        StepArgs a = batch_args(c, Sb, d.field);
+        a.cur = wcur;
+        a.prev = wprev;
+        a.out = wprev;
+        a.dsrc = sc + m * d.field;
+        a.dsrc_sstride = chunk_stride;
+        with_rec_extract(a, t, out_b, g->nt, c0 + m);
+        HIPCHK(launch_step(a, d.TX, kModeDsrc, st));
+        std::swap(wcur, wprev);
+      }
+    }
+    HIPCHK(launch_gather(wcur, d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
+  }
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       int32_t nh, const float *data, float *ptilde_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if (!data || !ptilde_out) return set_err(ctx, FWIME_EINVAL, "data or ptilde_out is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {{data, (long)geo->nshots * geo->nrec * g->nt}}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
+  const int K = seg_len(g->nt);
+  const int nseg = (g->nt - 1 + K - 1) / K;
+  const int R = K + 2;
+  const long per_shot = (2L + 2L * nseg + K + R) * d.field * 4 + (long)geo->nrec * 64;
+  const long img = (long)nh * d.nx * d.nz;
+  const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches);
+
+  float *acc = nullptr, *pairs = nullptr, *ckpt = nullptr, *t2 = nullptr, *ring = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&acc, img);
+  cv.add(&pairs, 2 * d.field * S);
+  cv.add(&ckpt, 2L * nseg * d.field * S);
+  cv.add(&t2, (long)K * d.field * S);
+  cv.add(&ring, (long)R * d.field * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  HIPCHK(launch_zero(acc, img, st));
+
+  const long ck_stride = 2L * nseg * d.field;   // per shot
+  const long t2_stride = (long)K * d.field;
+  const long ring_stride = (long)R * d.field;
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    const float *data_b = data + (long)s0 * geo->nrec * g->nt;
+    // forward pass storing (u^{n0-1}, u^{n0}) at every segment start
+    float *p0 = pairs, *p1 = pairs + d.field * Sb;
+    HIPCHK(launch_zero(pairs, 2 * d.field * Sb, st));
+    float *cur = p0, *prev = p1;
+    for (int j = 0; j < nseg; ++j) {
+      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1);
+      HIPCHK(launch_copy_fields(ckpt + (2L * j) * d.field, ck_stride, prev, d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(ckpt + (2L * j + 1) * d.field, ck_stride, cur, d.field, Sb, d.field, st));
+      if (j == nseg - 1) break;   // the last segment is recomputed anyway
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, d.field);
+        a.cur = cur;
+        a.prev = prev;
+        a.out = prev;
+        with_src(a, t, geo, g, s0, n);
+        HIPCHK(launch_step(a, d.TX, kModePlain, st));
+        std::swap(cur, prev);
+      }
+    }
+    // backward pass
+    HIPCHK(launch_zero(ring, ring_stride * Sb, st));
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
+      float *ccur = ckpt + (2L * j + 1) * d.field, *cprev = ckpt + (2L * j) * d.field;
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, ck_stride);
+        a.cur = ccur;
+        a.prev = cprev;
+        a.out = cprev;
+        a.t2 = t2 + (long)(n - n0) * d.field;
+        a.t2_sstride = t2_stride;
+        with_src(a, t, geo, g, s0, n);
+        HIPCHK(launch_step(a, d.TX, kModeT2, st));
+        std::swap(ccur, cprev);
+      }
+      for (int k = n1; k >= n0 + 1; --k) {
+        StepArgs a = batch_args(c, Sb, ring_stride);
+        a.cur = ring + (long)(k % R) * d.field;
+        a.prev = ring + (long)((k + 1) % R) * d.field;
+        a.out = ring + (long)((k - 1) % R) * d.field;
+        with_rec_inject(a, t, data_b, g->nt, k);
+        HIPCHK(launch_step(a, d.TX, kModePlain, st));
+      }
+      HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
+    }
+  }
+  HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, ptilde_out, st));
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo, int32_t nh,
+                   const float *ptilde, const float *dobs, double eps, const double *dso, double *obj,
+                   float *grad_vel, float *grad_ptilde, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if (!ptilde || !dobs || !dso || !obj || !grad_vel || !grad_ptilde)
+    return set_err(ctx, FWIME_EINVAL, "null pointer argument");
+  if (!std::isfinite(eps)) return set_err(ctx, FWIME_EINVAL, "eps must be finite");
+  for (int h = 0; h < nh; ++h)
+    if (!std::isfinite(dso[h])) return set_err(ctx, FWIME_EINVAL, "dso must be finite");
+  HIPCHK(hipSetDevice(ctx->device));
+  const long ndata = (long)geo->nshots * geo->nrec * g->nt;
+  if ((rc = check_inputs(ctx, g, vel, geo, {{ptilde, (long)nh * g->nx * g->nz}, {dobs, ndata}}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
+  const int K = seg_len(g->nt);
+  const int nseg = (g->nt - 1 + K - 1) / K;
+  const int R = K + 2;
+  const long img = (long)nh * d.nx * d.nz;
+  const long nrt = (long)geo->nrec * g->nt;
+  const long per_shot = (4L + 4L * nseg + 2L * K + 3L * R) * d.field * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const size_t fixed = (size_t)d.field * 12 + (size_t)img * 12;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches);
+
+  float *coef = nullptr, *acc = nullptr, *imgs = nullptr, *gacc = nullptr, *pairs = nullptr, *uck = nullptr,
+        *dck = nullptr, *t2u = nullptr, *t2d = nullptr, *lam = nullptr, *er = nullptr, *rho = nullptr,
+        *drec = nullptr, *ddrec = nullptr, *e2d2 = nullptr;
+  double *sumsq = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&sumsq, 2);
+  cv.add(&e2d2, nh);
+  cv.add(&coef, img);
+  cv.add(&acc, img);
+  cv.add(&imgs, img);
+  cv.add(&gacc, d.field);
+  cv.add(&pairs, 4 * d.field * S);
+  cv.add(&uck, 2L * nseg * d.field * S);
+  cv.add(&dck, 2L * nseg * d.field * S);
+  cv.add(&t2u, (long)K * d.field * S);
+  cv.add(&t2d, (long)K * d.field * S);
+  cv.add(&lam, (long)R * d.field * S);
+  cv.add(&er, (long)R * d.field * S);
+  cv.add(&rho, (long)R * d.field * S);
+  cv.add(&drec, nrt * S);
+  cv.add(&ddrec, nrt * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  std::vector<float> e2(nh);
+  for (int h = 0; h < nh; ++h) e2[h] = (float)(eps * eps * dso[h] * dso[h]);
+  HIPCHK(hipMemcpyAsync(e2d2, e2.data(), nh * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_ext_coef(ptilde, vel, eg, (float)g->dt, coef, st));
+  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero(gacc, d.field, st));
+  HIPCHK(hipMemsetAsync(sumsq, 0, 2 * sizeof(double), st));
+
+  const long ck_stride = 2L * nseg * d.field;
+  const long seg_stride = (long)K * d.field;
+  const long ring_stride = (long)R * d.field;
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    const float *dobs_b = dobs + (long)s0 * nrt;
+    // ---------------- forward: u and du~ with checkpoints ----------------
+    float *u0 = pairs, *u1 = pairs + d.field * Sb, *w0 = pairs + 2 * d.field * Sb, *w1 = pairs + 3 * d.field * Sb;
+    HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
+    HIPCHK(launch_zero(t2d, seg_stride * Sb, st));
+    float *ucur = u0, *uprev = u1, *wcur = w0, *wprev = w1;
+    for (int j = 0; j < nseg; ++j) {
+      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
+      HIPCHK(launch_copy_fields(uck + (2L * j) * d.field, ck_stride, uprev, d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(uck + (2L * j + 1) * d.field, ck_stride, ucur, d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(dck + (2L * j) * d.field, ck_stride, wprev, d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(dck + (2L * j + 1) * d.field, ck_stride, wcur, d.field, Sb, d.field, st));
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, d.field);
+        a.cur = ucur;
+        a.prev = uprev;
+        a.out = uprev;
+        a.t2 = t2u + (long)(n - n0) * d.field;
+        a.t2_sstride = seg_stride;
+        with_src(a, t, geo, g, s0, n);
+        with_rec_extract(a, t, drec, g->nt, n);
+        HIPCHK(launch_step(a, d.TX, kModeT2, st));
+        std::swap(ucur, uprev);
+      }
+      HIPCHK(launch_ext_scatter(coef, eg, +1, t2u, d.field, t2d, d.field, seg_stride, Sb, nk, st));
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, d.field);
+        a.cur = wcur;
+        a.prev = wprev;
+        a.out = wprev;
+        a.dsrc = t2d + (long)(n - n0) * d.field;
+        a.dsrc_sstride = seg_stride;
+        with_rec_extract(a, t, ddrec, g->nt, n);
+        HIPCHK(launch_step(a, d.TX, kModeDsrc, st));
+        std::swap(wcur, wprev);
+      }
+    }
+    HIPCHK(launch_gather(ucur, d.field, t.cells, Sb, geo->nrec, drec, g->nt, g->nt - 1, st));
+    HIPCHK(launch_gather(wcur, d.field, t.cells, Sb, geo->nrec, ddrec, g->nt, g->nt - 1, st));
+    HIPCHK(launch_residual(drec, ddrec, dobs_b, nrt * Sb, sumsq, st));
+    // ---------------- backward ----------------
+    HIPCHK(launch_zero(lam, ring_stride * Sb, st));
+    HIPCHK(launch_zero(er, ring_stride * Sb, st));
+    HIPCHK(launch_zero(rho, ring_stride * Sb, st));
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
+      float *uc = uck + (2L * j + 1) * d.field, *up = uck + (2L * j) * d.field;
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, ck_stride);
+        a.cur = uc;
+        a.prev = up;
+        a.out = up;
+        a.t2 = t2u + (long)(n - n0) * d.field;
+        a.t2_sstride = seg_stride;
+        with_src(a, t, geo, g, s0, n);
+        HIPCHK(launch_step(a, d.TX, kModeT2, st));
+        std::swap(uc, up);
+      }
+      // t2d holds T2 du~ of the later segment outside the scatter's range: clear it
+      HIPCHK(launch_zero(t2d, seg_stride * Sb, st));
+      HIPCHK(launch_ext_scatter(coef, eg, +1, t2u, d.field, t2d, d.field, seg_stride, Sb, nk, st));
+      float *wc = dck + (2L * j + 1) * d.field, *wp = dck + (2L * j) * d.field;
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, ck_stride);
+        a.cur = wc;
+        a.prev = wp;
+        a.out = wp;
+        a.dsrc = t2d + (long)(n - n0) * d.field;   // read the source, then
+        a.dsrc_sstride = seg_stride;
+        a.t2 = t2d + (long)(n - n0) * d.field;     // overwrite it with T2 du~_n
+        a.t2_sstride = seg_stride;
+        HIPCHK(launch_step(a, d.TX, kModeT2 | kModeDsrc, st));
+        std::swap(wc, wp);
+      }
+      for (int k = n1; k >= n0 + 1; --k) {
+        StepArgs a = batch_args(c, Sb, ring_stride);
+        a.cur = lam + (long)(k % R) * d.field;
+        a.prev = lam + (long)((k + 1) % R) * d.field;
+        a.out = lam + (long)((k - 1) % R) * d.field;
+        with_rec_inject(a, t, drec, g->nt, k);
+        HIPCHK(launch_step(a, d.TX, kModePlain, st));
+      }
+      HIPCHK(launch_ext_scatter(coef, eg, -1, lam, d.field, er, d.field, ring_stride, Sb, nk, st, R, n0, R, n0));
+      for (int k = n1; k >= n0 + 1; --k) {
+        StepArgs a = batch_args(c, Sb, ring_stride);
+        a.cur = rho + (long)(k % R) * d.field;
+        a.prev = rho + (long)((k + 1) % R) * d.field;
+        a.out = rho + (long)((k - 1) % R) * d.field;
+        a.nu.em = er + (long)((k - 1) % R) * d.field;
+        a.nu.e0 = er + (long)(k % R) * d.field;
+        a.nu.ep = er + (long)((k + 1) % R) * d.field;
+        a.nu.sstride = ring_stride;
+        HIPCHK(launch_step(a, d.TX, kModeNu, st));
+      }
+      HIPCHK(launch_ext_image(t2u, d.field, seg_stride, lam, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
+      HIPCHK(launch_grad_accum(t2u, t2d, d.field, seg_stride, lam, rho, d.field, ring_stride, R, n0, Sb, nk, d.NZ,
+                               d.NX, d.LZ, gacc, st));
+    }
+  }
+  HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, imgs, st));
+  HIPCHK(launch_grad_finalize(gacc, c.V, vel, eg, (float)g->dt, ptilde, imgs, grad_vel, st));
+  HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, ptilde, e2d2, grad_ptilde, st));
+  HIPCHK(launch_objective(sumsq, ptilde, e2d2, eg, obj, st));
+  return FWIME_OK;
+}
+
+}  // extern "C"

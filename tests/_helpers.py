@@ -20,3 +20,26 @@ def rel_l2(a, b):
 
 def dot_err(a, b):
     return abs(a - b) / max(abs(a), abs(b))
+
+
+def gpu_problem(w, dev="cuda:0"):
+    """synth workload -> (Grid, vel tensor, Geometry) for the HIP library."""
+    import torch
+    import paper_2206_02362_amd as fw
+    grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+    vel = torch.tensor(w.vel, dtype=torch.float32, device=dev)
+    wav = torch.tensor(w.wavelet, dtype=torch.float32, device=dev)
+    geo = fw.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix, wav)
+    return grid, vel, geo
+
+
+def oracle_problem_f32(w):
+    """Oracle inputs rounded to float32 first, so both sides see identical inputs."""
+    import oracle
+    import synth
+    w32 = synth.Workload(w.name, w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt,
+                         w.vel.astype(np.float32).astype(np.float64), w.src_iz, w.src_ix, w.rec_iz, w.rec_ix,
+                         w.wavelet.astype(np.float32).astype(np.float64), w.nh, w.sponge_alpha)
+    g = oracle.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+    geo = oracle.Geometry(w32.src_iz, w32.src_ix, w32.rec_iz, w32.rec_ix, w32.wavelet)
+    return g, geo, w32.vel

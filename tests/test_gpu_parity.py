@@ -1,0 +1,308 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: relative L2 <= 1e-4 on traces, images and gradients over the whole
+output array, and dot-product error <= 1e-5 with inner products in FP64.
+Both sides receive identical inputs (the oracle takes the float32-rounded
+arrays as float64).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _helpers import dot_err, gpu_problem, oracle_problem_f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+DOT_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2206_02362_amd as fw
+    assert torch.cuda.is_available()
+    c = fw.Context(0)
+    yield c
+    c.close()
+
+
+def t2n(t):
+    return t.detach().double().cpu().numpy()
+
+
+def dev(a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda:0")
+
+
+# ---------------------------------------------------------------------------
+# Nonlinear modeling
+# ---------------------------------------------------------------------------
+
+def test_model_tiny_multishot(ctx):
+    say("case: model tiny 24x32 nb8 nt160 3 shots")
+    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=3)
+    g, geo, vel = oracle_problem_f32(w)
+    ref = oracle.model(g, vel, geo)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.model(grid, tv, tg))
+    assert rel_l2(out, ref) < TOL
+
+
+def test_model_plain_small(ctx):
+    say("case: model 100x200 nb40 nt1500 (plain-small)")
+    w = synth.plain_small()
+    g, geo, vel = oracle_problem_f32(w)
+    ref = oracle.model(g, vel, geo)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.model(grid, tv, tg))
+    err = rel_l2(out, ref)
+    say("  rel-L2", err)
+    assert err < TOL
+
+
+def test_model_tile_widths_bitwise(ctx):
+    # The per-cell arithmetic does not depend on the tile shape.
+    import paper_2206_02362_amd as fw
+    say("case: model tile widths 16/32/64")
+    w = synth.tiny(nz=70, nx=90, nb=6, nt=120, nshots=2)
+    grid, tv, tg = gpu_problem(w)
+    outs = []
+    old = os.environ.get("FWIME_TILE_X")
+    try:
+        for tx in ("16", "32", "64"):
+            os.environ["FWIME_TILE_X"] = tx
+            c = fw.Context(0)
+            outs.append(t2n(c.model(grid, tv, tg)))
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("FWIME_TILE_X", None)
+        else:
+            os.environ["FWIME_TILE_X"] = old
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+def test_model_shot_alone_equals_in_batch(ctx):
+    say("case: model shot alone vs batch")
+    w = synth.tiny(nz=40, nx=60, nb=8, nt=150, nshots=4)
+    grid, tv, tg = gpu_problem(w)
+    full = t2n(ctx.model(grid, tv, tg))
+    w1 = w.subset([2])
+    grid1, tv1, tg1 = gpu_problem(w1)
+    one = t2n(ctx.model(grid1, tv1, tg1))
+    assert np.array_equal(full[2], one[0])
+
+
+def test_model_edge_geometry(ctx):
+    # receivers on the model corners, duplicated receivers, no absorbing strip
+    say("case: model edge geometry nb0")
+    w = synth.tiny(nz=20, nx=30, nb=0, nt=100, nshots=1)
+    w.rec_iz = np.array([[0, 0, 19, 19, 5, 5]], np.int32)
+    w.rec_ix = np.array([[0, 29, 0, 29, 7, 7]], np.int32)
+    w.src_iz[:] = 0
+    w.src_ix[:] = 29
+    g, geo, vel = oracle_problem_f32(w)
+    ref = oracle.model(g, vel, geo)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.model(grid, tv, tg))
+    assert rel_l2(out, ref) < TOL
+    assert np.array_equal(out[0, 4], out[0, 5])
+
+
+# ---------------------------------------------------------------------------
+# Extended Born
+# ---------------------------------------------------------------------------
+
+def _ptilde(w, seed):
+    return synth.random_ptilde(w.nh, w.nz, w.nx, seed).astype(np.float32)
+
+
+def test_born_ext_fwd_tiny(ctx):
+    say("case: born_ext_fwd tiny nh5")
+    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5)
+    g, geo, vel = oracle_problem_f32(w)
+    pt = _ptilde(w, 3)
+    ref = oracle.born_ext_fwd(g, vel, geo, pt.astype(np.float64))
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_fwd(grid, tv, tg, dev(pt)))
+    assert rel_l2(out, ref) < TOL
+
+
+def test_born_ext_fwd_offsets_leave_grid(ctx):
+    say("case: born_ext_fwd nb3 nh11 (offsets leave the padded grid)")
+    w = synth.tiny(nz=12, nx=14, nb=3, nt=90, nshots=1, nh=11)
+    g, geo, vel = oracle_problem_f32(w)
+    pt = _ptilde(w, 4)
+    ref = oracle.born_ext_fwd(g, vel, geo, pt.astype(np.float64))
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_fwd(grid, tv, tg, dev(pt)))
+    assert rel_l2(out, ref) < TOL
+
+
+def test_born_ext_fwd_nh1_is_born(ctx):
+    say("case: born_ext_fwd nh1")
+    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=1)
+    g, geo, vel = oracle_problem_f32(w)
+    dv = synth.random_ptilde(1, w.nz, w.nx, 5).astype(np.float32)
+    dvp = np.zeros((w.nx + 2 * w.nb, w.nz + 2 * w.nb))
+    dvp[w.nb:w.nb + w.nx, w.nb:w.nb + w.nz] = dv[0]
+    ref = oracle.born(g, vel, geo, dvp)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_fwd(grid, tv, tg, dev(dv)))
+    assert rel_l2(out, ref) < TOL
+
+
+def test_born_ext_fwd_plain_small(ctx):
+    say("case: born_ext_fwd 100x200 nt1500 nh11")
+    w = synth.plain_small()
+    g, geo, vel = oracle_problem_f32(w)
+    pt = _ptilde(w, 6)
+    ref = oracle.born_ext_fwd(g, vel, geo, pt.astype(np.float64))
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_fwd(grid, tv, tg, dev(pt)))
+    err = rel_l2(out, ref)
+    say("  rel-L2", err)
+    assert err < TOL
+
+
+def _residual_data(w, g, geo, vel):
+    # a realistic adjoint source: data of a perturbed model minus data of vel
+    pert = vel + 100.0 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 9, 60.0)
+    d = oracle.model(g, pert, geo) - oracle.model(g, vel, geo)
+    return d.astype(np.float32)
+
+
+def test_born_ext_adj_tiny(ctx):
+    say("case: born_ext_adj tiny nh5")
+    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5)
+    g, geo, vel = oracle_problem_f32(w)
+    d = _residual_data(w, g, geo, vel)
+    ref = oracle.born_ext_adj(g, vel, geo, d.astype(np.float64), w.nh)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_adj(grid, tv, tg, dev(d), w.nh))
+    assert rel_l2(out, ref) < TOL
+
+
+def test_born_ext_adj_plain_small(ctx):
+    say("case: born_ext_adj 100x200 nt1500 nh11")
+    w = synth.plain_small()
+    g, geo, vel = oracle_problem_f32(w)
+    d = _residual_data(w, g, geo, vel)
+    ref = oracle.born_ext_adj(g, vel, geo, d.astype(np.float64), w.nh)
+    grid, tv, tg = gpu_problem(w)
+    out = t2n(ctx.born_ext_adj(grid, tv, tg, dev(d), w.nh))
+    err = rel_l2(out, ref)
+    say("  rel-L2", err)
+    assert err < TOL
+
+
+def test_dot_product_plain_small(ctx):
+    say("case: dot product 100x200 nt1500 nh11")
+    w = synth.plain_small()
+    grid, tv, tg = gpu_problem(w)
+    rng = np.random.default_rng(8)
+    pt = rng.standard_normal((w.nh, w.nx, w.nz)).astype(np.float32)
+    d = rng.standard_normal((w.nshots, w.nrec, w.nt)).astype(np.float32)
+    bp = t2n(ctx.born_ext_fwd(grid, tv, tg, dev(pt)))
+    btd = t2n(ctx.born_ext_adj(grid, tv, tg, dev(d), w.nh))
+    lhs = float(np.sum(bp * d.astype(np.float64)))
+    rhs = float(np.sum(pt.astype(np.float64) * btd))
+    say("  dot err", dot_err(lhs, rhs))
+    assert dot_err(lhs, rhs) < DOT_TOL
+
+
+# ---------------------------------------------------------------------------
+# FWIME gradient
+# ---------------------------------------------------------------------------
+
+def _grad_case(w, seed=0):
+    g, geo, vel = oracle_problem_f32(w)
+    true = vel + 120.0 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 40 + seed, 80.0)
+    dobs = oracle.model(g, true, geo).astype(np.float32)
+    rng = np.random.default_rng(50 + seed)
+    pt = (0.2 * rng.standard_normal((w.nh, w.nx, w.nz))).astype(np.float32)
+    dso = synth.dso_weights(w.nh)
+    return g, geo, vel, dobs, pt, dso
+
+
+def _check_gradient(ctx, w, eps, seed=0, tol=TOL):
+    g, geo, vel, dobs, pt, dso = _grad_case(w, seed)
+    obj_r, gv_r, gp_r = oracle.gradient(g, vel, geo, pt.astype(np.float64), dobs.astype(np.float64), eps, dso)
+    grid, tv, tg = gpu_problem(w)
+    obj, gv, gp = ctx.gradient(grid, tv, tg, dev(pt), dev(dobs), eps, dso)
+    e_obj = abs(float(obj.item()) - obj_r) / abs(obj_r)
+    e_gv = rel_l2(t2n(gv), gv_r)
+    e_gp = rel_l2(t2n(gp), gp_r)
+    say("  obj", e_obj, "grad_vel", e_gv, "grad_ptilde", e_gp)
+    assert e_obj < tol and e_gv < tol and e_gp < tol
+
+
+def test_gradient_tiny(ctx):
+    say("case: gradient tiny nh5 eps1e-3")
+    _check_gradient(ctx, synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5), 1e-3)
+
+
+def test_gradient_tiny_eps0(ctx):
+    say("case: gradient tiny nh3 eps0")
+    _check_gradient(ctx, synth.tiny(nz=20, nx=26, nb=5, nt=130, nshots=1, nh=3), 0.0, seed=1)
+
+
+def test_gradient_plain_small_600(ctx):
+    say("case: gradient 100x200 nt600 nh11")
+    w = synth.plain_small()
+    w = synth.Workload(w.name, w.nz, w.nx, w.nb, 600, w.dz, w.dx, w.dt, w.vel, w.src_iz, w.src_ix, w.rec_iz,
+                       w.rec_ix, w.wavelet[:, :600].copy(), w.nh)
+    _check_gradient(ctx, w, 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# Error paths: nothing is written to the outputs
+# ---------------------------------------------------------------------------
+
+def test_errors_leave_outputs_untouched(ctx):
+    import torch
+    import paper_2206_02362_amd as fw
+    say("case: error paths")
+    w = synth.tiny(nz=16, nx=20, nb=4, nt=50, nshots=1, nh=3)
+    grid, tv, tg = gpu_problem(w)
+    data = torch.full((1, w.nrec, w.nt), 7.0, device="cuda:0")
+    # CFL violation
+    bad = fw.Grid(grid.nz, grid.nx, grid.nb, grid.nt, grid.dz, grid.dx, 0.01)
+    with pytest.raises(fw.FwimeError) as e:
+        ctx.fwime_model(bad, tv, tg, data)
+    assert e.value.code == fw.FWIME_EINVAL
+    # receiver outside the model grid
+    rz = w.rec_iz.copy()
+    rz[0, 0] = w.nz
+    g2 = fw.Geometry(w.src_iz, w.src_ix, rz, w.rec_ix, tg.wavelet)
+    with pytest.raises(fw.FwimeError) as e:
+        ctx.fwime_model(grid, tv, g2, data)
+    assert e.value.code == fw.FWIME_EINVAL
+    # even nh
+    pt = torch.zeros((2, w.nx, w.nz), device="cuda:0")
+    with pytest.raises(fw.FwimeError) as e:
+        ctx.fwime_born_ext_fwd(grid, tv, tg, 2, pt, data)
+    assert e.value.code == fw.FWIME_EINVAL
+    # non-finite velocity
+    tv2 = tv.clone()
+    tv2[3, 3] = float("nan")
+    with pytest.raises(fw.FwimeError) as e:
+        ctx.fwime_model(grid, tv2, tg, data)
+    assert e.value.code == fw.FWIME_ENONFINITE
+    # non-positive velocity
+    tv3 = tv.clone()
+    tv3[0, 0] = 0.0
+    with pytest.raises(fw.FwimeError) as e:
+        ctx.fwime_model(grid, tv3, tg, data)
+    assert e.value.code == fw.FWIME_EINVAL
+    torch.cuda.synchronize()
+    assert bool(torch.all(data == 7.0))
