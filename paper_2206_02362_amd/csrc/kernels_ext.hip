@@ -10,7 +10,20 @@
 // image accumulator are touched once per chunk instead of once per step.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace fw {
+
+// Raw buffer access: a load whose byte offset falls outside [0, bytes) of the
+// resource returns 0 in hardware (negative offsets wrap to large unsigned
+// values).  Window staging relies on this to drop the terms whose column lies
+// outside the padded grid without any per-element test.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const float *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
 
 // ---------------------------------------------------------------------------
 // c(z,y,h) = 2 p~(z,y,h) / (v(z,y)^3 dt^2), model grid, [nh][nx][nz]
@@ -36,13 +49,13 @@ hipError_t launch_ext_coef(const float *ptilde, const float *vel, const ExtGeom 
 // ---------------------------------------------------------------------------
 // Scatter (sg = +1) / spread (sg = -1):
 //   out_n(z, j) = sum_h c(z, j - sg h, h) in_n(z, j - 2 sg h)
-// One thread per (model z, padded column j); the coefficient of each h is
-// loaded once and reused over a sub-chunk of KC time slots held in registers.
-// Cells outside the written range are never touched (the caller zeroes the
-// output buffers once).
+//
+// Weight-stationary: the offset weights of an output column are loaded once
+// per launch into registers and reused for every time slot of every shot.
+// Out-of-grid input columns read as zero and out-of-model weights are zero,
+// which drops exactly the terms the operator drops.  Requires H <= HMAX (30);
+// larger offset counts use the generic kernel further below.
 // ---------------------------------------------------------------------------
-constexpr int kScatterKC = 16;
-
 struct ScatterArgs {
   const float *coef;
   const float *in;
@@ -50,10 +63,141 @@ struct ScatterArgs {
   long in_slot, out_slot, sstride;
   int in_ring, in_first, out_ring, out_first;
   int nz, nx, nb, NX, LZ, nh, H, sg;
-  int j0, nj;       // padded columns [j0, j0 + nj)
+  int j0, nj;       // writable padded columns [j0, j0 + nj)
   int nzs;          // z strips
   int nk, nshots;
+  int slots_per_block;
 };
+
+// Pipelined weight-stationary kernel.  A workgroup of 8 wavefronts owns 16
+// consecutive output columns of one 64-row depth strip; wavefront w holds the
+// weights of two same-parity columns ja and ja + 2 in registers for every h.
+// Input windows [jb - 2H, jb + 16 + 2H) of successive time slots flow through a
+// 3-deep LDS ring: slot q is consumed while slot q + 1 is written from
+// registers and the global loads of slot q + 2 are in flight, with one barrier
+// per slot.  Each wavefront forms its two outputs with 2 nh multiply-adds from
+// nh + 1 LDS reads.
+constexpr int kScJB = 16;         // output columns per workgroup
+constexpr int kScThreads = 512;
+
+template <int HMAX, int SG>
+__global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs a) {
+  constexpr int NH = 2 * HMAX + 1;
+  constexpr int WMAX = kScJB + 4 * HMAX;                          // staged columns
+  constexpr int PER = (WMAX + 7) / 8;                             // staged rows per thread
+  __shared__ float ring[3][WMAX * 64];
+
+  // XCD-contiguous order: hardware workgroup b runs on XCD b % 8; give each
+  // XCD a contiguous range of (strip, column block) tiles so the overlapping
+  // input windows of neighbouring tiles are served by that XCD's L2.
+  const int nblk_j = (a.nj + kScJB - 1) / kScJB;
+  const int ntile = a.nzs * nblk_j;
+  const int per = (ntile + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntile) return;
+  const int zs = tile % a.nzs;
+  const int jbk = tile / a.nzs;
+  const int jb = a.j0 + jbk * kScJB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int z = zs * 64 + lane;
+  const bool zin = z < a.nz;
+  const int zp = a.nb + z;
+  const int H = a.H;
+  const int col0 = jb - 2 * HMAX;                       // padded column of ring row 0 (window sized for HMAX)
+  const int ja = jb + (w & 1) + 4 * (w >> 1);
+  const int jc = ja + 2;
+  const int jend = a.j0 + a.nj;
+
+  float ca[NH], cb[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int ih = k - HMAX;
+    float va = 0.f, vb = 0.f;
+    if (ih >= -H && ih <= H && zin) {
+      const int ya = ja - SG * ih - a.nb, yc = jc - SG * ih - a.nb;
+      const long hb = (long)(ih + H) * a.nx;
+      if (ya >= 0 && ya < a.nx) va = a.coef[(hb + ya) * a.nz + z];
+      if (yc >= 0 && yc < a.nx) vb = a.coef[(hb + yc) * a.nz + z];
+    }
+    ca[k] = va;
+    cb[k] = vb;
+  }
+
+  const int total = a.nshots * a.nk;
+  const int q0 = blockIdx.y * a.slots_per_block;
+  const int q1 = min(total, q0 + a.slots_per_block);
+  if (q0 >= q1) return;
+
+  // thread (w, lane) stages ring rows w + 8 r (r < PER) at depth lane; columns
+  // outside [0, NX) come back as zero from the bounds-checked buffer load
+  const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
+  const int off0 = ((col0 + w) * a.LZ + zp) * 4;
+  const int rstep = 8 * a.LZ * 4;
+  auto fetch = [&](int q, float (&pre)[PER]) {
+    if (q >= q1) return;
+    const int s = q / a.nk, n = q - s * a.nk;
+    const long sl = a.in_ring ? (long)((a.in_first + n) % a.in_ring) : (long)n;
+    const auto rs = slot_rsrc(a.in + (long)s * a.sstride + sl * a.in_slot, slot_bytes);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) pre[r] = bload(rs, off0 + r * rstep);
+  };
+  auto put = [&](int slot_buf, const float (&pre)[PER]) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int c = w + 8 * r;
+      if (c < WMAX) ring[slot_buf][c * 64 + lane] = pre[r];
+    }
+  };
+  auto consume = [&](int q, int rbuf) {
+    const float *row = &ring[rbuf][(ja - col0) * 64 + lane];   // input column ja
+    float oa = 0.f, ob = 0.f;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const int ih = k - HMAX;
+      // input column of (ja, ih) is ja - 2 sg ih; of (ja + 2, ih) two further.
+      // Weights of |ih| > H are zero and their rows lie inside the window.
+      oa += ca[k] * row[-2 * SG * ih * 64];
+      ob += cb[k] * row[(2 - 2 * SG * ih) * 64];
+    }
+    const int s = q / a.nk, n = q - s * a.nk;
+    const long sl = a.out_ring ? (long)((a.out_first + n) % a.out_ring) : (long)n;
+    float *dst = a.out + (long)s * a.sstride + sl * a.out_slot;
+    if (zin) {
+      if (ja < jend) dst[(long)ja * a.LZ + zp] = oa;
+      if (jc < jend) dst[(long)jc * a.LZ + zp] = ob;
+    }
+  };
+
+  // ring[rb] holds slot q; pA / pB hold the two following slots
+  float pA[PER], pB[PER];
+  fetch(q0, pA);
+  put(0, pA);
+  fetch(q0 + 1, pA);
+  fetch(q0 + 2, pB);
+  __syncthreads();
+  int rb = 0;
+  for (int q = q0; q < q1; q += 2) {
+    int nb1 = rb == 2 ? 0 : rb + 1;
+    consume(q, rb);
+    if (q + 1 < q1) put(nb1, pA);
+    fetch(q + 3, pA);
+    __syncthreads();
+    rb = nb1;
+    if (q + 1 >= q1) break;
+    nb1 = rb == 2 ? 0 : rb + 1;
+    consume(q + 1, rb);
+    if (q + 2 < q1) put(nb1, pB);
+    fetch(q + 4, pB);
+    __syncthreads();
+    rb = nb1;
+  }
+}
+
+// Generic fallback (any H): one thread per (z, j), coefficient reused over up
+// to kScatterKC slots held in registers.
+constexpr int kScatterKC = 16;
 
 __global__ void __launch_bounds__(256) k_ext_scatter(const ScatterArgs a) {
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -135,6 +279,25 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
   a.nzs = (g.nz + 63) / 64;
   a.nk = nk;
   a.nshots = nshots;
+  if (g.H <= 30) {
+    // spread the slots over enough workgroups to fill the device
+    const int ntile = a.nzs * ((a.nj + kScJB - 1) / kScJB);
+    const int nblk = (ntile + 7) / 8 * 8;
+    const int total = nshots * nk;
+    int groups = std::max(1, std::min(total, (2048 + nblk - 1) / nblk));
+    a.slots_per_block = (total + groups - 1) / groups;
+    groups = (total + a.slots_per_block - 1) / a.slots_per_block;
+    const dim3 grid((unsigned)nblk, (unsigned)groups);
+    if (g.H <= 8)
+      sg > 0 ? k_ext_scatter_ws<8, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<8, -1><<<grid, kScThreads, 0, st>>>(a);
+    else if (g.H <= 16)
+      sg > 0 ? k_ext_scatter_ws<16, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<16, -1><<<grid, kScThreads, 0, st>>>(a);
+    else if (g.H <= 24)
+      sg > 0 ? k_ext_scatter_ws<24, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<24, -1><<<grid, kScThreads, 0, st>>>(a);
+    else
+      sg > 0 ? k_ext_scatter_ws<30, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<30, -1><<<grid, kScThreads, 0, st>>>(a);
+    return hipGetLastError();
+  }
   const long waves = (long)nshots * a.nzs * a.nj;
   k_ext_scatter<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a);
   return hipGetLastError();
@@ -218,6 +381,124 @@ __global__ void __launch_bounds__(256) k_ext_image(const ImageArgs p) {
   }
 }
 
+// LDS-staged, pipelined version.  A workgroup of 16 wavefronts covers one
+// depth strip, YB = 8 NYT model columns and 8 NHT offsets of the group
+// blockIdx.y; the wavefronts tile (y, h) as NYT x NHT tiles of 8 x 8
+// (NYT NHT = 16).  Per time slot the source-side window (y - h) and the
+// receiver-side window (y + h), each YB + 8 NHT - 1 columns wide, are staged in
+// a 3-deep LDS ring: slot q is consumed while slot q + 1 is written from
+// registers and the loads of slot q + 2 are in flight (one barrier per slot).
+template <int NYT, int NHT>
+__global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
+  constexpr int NA = kImgYT + kImgHT - 1;
+  constexpr int YB = 8 * NYT;
+  constexpr int HSPAN = 8 * NHT;
+  constexpr int WW = YB + HSPAN - 1;
+  constexpr int ROWS = 2 * WW;                  // a-window rows then b-window rows
+  constexpr int PER = (ROWS + 15) / 16;         // rows staged per thread
+  __shared__ float ring[3][ROWS * 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ntile = p.nzs * ((p.nx + YB - 1) / YB);
+  const int per = (ntile + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-contiguous tiles
+  if (tile >= ntile) return;
+  const int zs = tile % p.nzs;
+  const int yblk = tile / p.nzs;
+  const int yb = yblk * YB;
+  const int hlo = -p.H + HSPAN * blockIdx.y;
+  const int hhi = min(p.H, hlo + HSPAN - 1);
+  const int z = zs * 64 + lane;
+  const bool zin = z < p.nz;
+  const int zp = p.nb + z;
+  const int yt = w % NYT, ht = w / NYT;
+  const int y0 = yb + 8 * yt;
+  const int h0 = hlo + 8 * ht;
+  const bool active = h0 <= hhi && y0 < p.nx;
+  // window origins (padded columns)
+  const int xa0 = p.nb + yb - (hlo + HSPAN - 1);
+  const int xb0 = p.nb + yb + hlo;
+  const int ia = 8 * yt + (HSPAN - 8 - 8 * ht);  // a-window row of A[0]
+  const int ib = WW + 8 * yt + 8 * ht;           // b-window row of B[0]
+
+  float acc[kImgYT][kImgHT];
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
+
+  const int total = p.nshots * p.nk;
+  // thread (w, lane) stages rows w + 16 r at depth lane; out-of-grid columns
+  // read as zero through the bounds-checked buffer loads
+  const unsigned slot_bytes = (unsigned)((long)p.NX * p.LZ * 4);
+  auto fetch = [&](int q, float (&pre)[PER]) {
+    if (q >= total) return;
+    const int s = q / p.nk, n = q - s * p.nk;
+    const auto ra = slot_rsrc(p.a + (long)s * p.a_sstride + (long)n * p.a_slot, slot_bytes);
+    const auto rbb = slot_rsrc(p.b + (long)s * p.b_sstride + (long)((p.b_first + n) % p.b_ring) * p.b_slot,
+                               slot_bytes);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int c = w + 16 * r;
+      if (c < WW)
+        pre[r] = bload(ra, ((xa0 + c) * p.LZ + zp) * 4);
+      else
+        pre[r] = bload(rbb, ((xb0 + c - WW) * p.LZ + zp) * 4);
+    }
+  };
+  auto put = [&](int rbuf, const float (&pre)[PER]) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int c = w + 16 * r;
+      if (c < ROWS) ring[rbuf][c * 64 + lane] = pre[r];
+    }
+  };
+  if (total <= 0) return;
+  float p1[PER], p2[PER];
+  fetch(0, p1);
+  put(0, p1);
+  fetch(1, p1);
+  fetch(2, p2);
+  __syncthreads();
+  int rb = 0;
+  for (int q = 0; q < total; ++q) {
+    if (active) {
+      const float *win = ring[rb];
+      float va[NA], vb[NA];
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        va[m] = win[(ia + m) * 64 + lane];
+        vb[m] = win[(ib + m) * 64 + lane];
+      }
+#pragma unroll
+      for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+        for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
+    }
+    const int nb1 = rb == 2 ? 0 : rb + 1;
+    if (q + 1 < total) put(nb1, p1);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) p1[r] = p2[r];
+    fetch(q + 3, p2);
+    __syncthreads();
+    rb = nb1;
+  }
+  if (!active || !zin) return;
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy) {
+    const int y = y0 + yy;
+    if (y >= p.nx) continue;
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) {
+      const int ih = h0 + hh;
+      if (ih > hhi) continue;
+      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
+      p.acc[o] += acc[yy][hh];
+    }
+  }
+}
+
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
                             int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc,
                             hipStream_t st) {
@@ -242,10 +523,15 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.nh = g.nh;
   p.H = g.H;
   p.nzs = (g.nz + 63) / 64;
-  p.nyt = (g.nx + kImgYT - 1) / kImgYT;
-  p.nht = (g.nh + kImgHT - 1) / kImgHT;
-  const long waves = (long)p.nzs * p.nyt * p.nht;
-  k_ext_image<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(p);
+  if (g.nh > 16) {
+    const int ntile = p.nzs * ((g.nx + 31) / 32);
+    const dim3 grid((unsigned)((ntile + 7) / 8 * 8), (unsigned)((g.nh + 31) / 32));
+    k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
+  } else {
+    const int ntile = p.nzs * ((g.nx + 63) / 64);
+    const dim3 grid((unsigned)((ntile + 7) / 8 * 8), 1u);
+    k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
+  }
   return hipGetLastError();
 }
 
