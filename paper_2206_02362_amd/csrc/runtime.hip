@@ -40,6 +40,7 @@ struct fwime_ctx {
 
 namespace {
 
+constexpr int kGxPad = 64;   // zero taper entries past NX read by the last x-tile
 constexpr double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 
 int set_err(fwime_ctx_t *ctx, int code, const std::string &msg) {
@@ -72,7 +73,7 @@ Dims make_dims(const fwime_grid_t *g, int tx) {
   d.nt = g->nt;
   d.NZ = g->nz + 2 * g->nb;
   d.NX = g->nx + 2 * g->nb;
-  d.LZ = (d.NZ + 63) / 64 * 64;
+  d.LZ = (d.NZ + 4 + 63) / 64 * 64;   // >= 4 zero rows below the grid in every column
   d.TX = tx;
   d.ntz = (d.NZ + kTZ - 1) / kTZ;
   d.ntx = (d.NX + tx - 1) / tx;
@@ -133,7 +134,9 @@ int check_grid(fwime_ctx_t *ctx, const fwime_grid_t *g) {
   if (!(g->sponge_alpha >= 0) || !std::isfinite(g->sponge_alpha))
     return set_err(ctx, FWIME_EINVAL, "sponge_alpha must be >= 0");
   const long NZ = (long)g->nz + 2L * g->nb, NX = (long)g->nx + 2L * g->nb;
-  if (NZ * NX > (1L << 30)) return set_err(ctx, FWIME_EINVAL, "padded grid too large");
+  const long LZ = (NZ + 4 + 63) / 64 * 64;
+  // kernels address one shot's field with 32-bit byte offsets
+  if ((NX + 256) * LZ * 4 >= (1L << 31)) return set_err(ctx, FWIME_EINVAL, "padded grid too large");
   return FWIME_OK;
 }
 
@@ -352,7 +355,7 @@ int setup_common(fwime_ctx_t *ctx, Common &c, const fwime_grid_t *g, const float
   HIPCHK(launch_prep(vel, d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, (float)g->dt, c.V, st));
   std::vector<float> gz, gx;
   taper_host(d.nz, d.nb, g->sponge_alpha, d.LZ, gz);
-  taper_host(d.nx, d.nb, g->sponge_alpha, d.NX, gx);
+  taper_host(d.nx, d.nb, g->sponge_alpha, d.NX + kGxPad, gx);
   HIPCHK(hipMemcpyAsync(c.gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(c.gx, gx.data(), gx.size() * sizeof(float), hipMemcpyHostToDevice, st));
   StepArgs &a = c.base;
@@ -510,7 +513,7 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
-  cv.add(&c.gx, d.NX);
+  cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&fields, 2 * d.field * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -566,7 +569,7 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
-  cv.add(&c.gx, d.NX);
+  cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&coef, (long)nh * d.nx * d.nz);
   cv.add(&pairs, 4 * d.field * S);
@@ -648,7 +651,7 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
-  cv.add(&c.gx, d.NX);
+  cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&acc, img);
   cv.add(&pairs, 2 * d.field * S);
@@ -757,7 +760,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
-  cv.add(&c.gx, d.NX);
+  cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&sumsq, 2);
   cv.add(&e2d2, nh);
