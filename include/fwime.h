@@ -119,6 +119,31 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                    const float *dobs, double eps, const double *dso,
                    double *obj, float *grad_vel, float *grad_ptilde, void *stream);
 
+/* ---- Forward / backward split for automatic differentiation ------------
+ * The pair below evaluates d = f(m) + B~(m) p~ (the predicted data of
+ * eq. fwime.obj) and, later, the adjoint-state backward of that map: given
+ * an adjoint source a = dL/dd, grad_vel = (B^* + T^*) a (the Born and
+ * tomographic parts of eqs. fwime.gradient.born and .tomo) and
+ * grad_ptilde = B~^* a.  The forward keeps sqrt(nt)-spaced checkpoints of the
+ * background and scattered wavefields of every shot in a tape (device memory
+ * owned by the tape, counted against the context's HBM budget), plus copies of
+ * vel, ptilde and the wavelets; the backward recomputes one segment at a time
+ * from them.  A tape serves exactly one backward (its checkpoints are
+ * consumed); free it with fwime_tape_free in every case. */
+typedef struct fwime_tape fwime_tape_t;
+
+/* data: DEVICE [nshots][nrec][nt] receives f(m) + B~(m) p~; *tape is set on success. */
+int fwime_forward_tape(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, int32_t nh, const float *ptilde, float *data,
+                       fwime_tape_t **tape, void *stream);
+
+/* adjsrc: DEVICE [nshots][nrec][nt]; grad_vel: DEVICE [nx][nz]; grad_ptilde: DEVICE [nh][nx][nz]. */
+int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tape, const float *adjsrc,
+                        float *grad_vel, float *grad_ptilde, void *stream);
+
+/* Release a tape (synchronizes the device); null is ignored. */
+void fwime_tape_free(fwime_tape_t *tape);
+
 /* Static description of a return code. */
 const char *fwime_strerror(int code);
 

@@ -16,5 +16,7 @@ from ._abi import (  # noqa: F401
     FwimeError,
     Geometry,
     Grid,
+    Tape,
     load,
 )
+from .autograd import FwimeOp, predicted_data  # noqa: F401,E402

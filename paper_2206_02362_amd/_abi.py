@@ -23,7 +23,8 @@ FWIME_EHIP = 3
 FWIME_ENONFINITE = 4
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_gradient", "fwime_strerror", "fwime_last_error")
+            "fwime_born_ext_adj", "fwime_gradient", "fwime_forward_tape", "fwime_backward_tape",
+            "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
 class FwimeError(RuntimeError):
@@ -69,6 +70,12 @@ def load() -> ctypes.CDLL:
     lib.fwime_born_ext_adj.restype = I
     lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
     lib.fwime_gradient.restype = I
+    lib.fwime_forward_tape.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.POINTER(P), P]
+    lib.fwime_forward_tape.restype = I
+    lib.fwime_backward_tape.argtypes = [P, P, P, P, P, P]
+    lib.fwime_backward_tape.restype = I
+    lib.fwime_tape_free.argtypes = [P]
+    lib.fwime_tape_free.restype = None
     lib.fwime_strerror.argtypes = [I]
     lib.fwime_strerror.restype = ctypes.c_char_p
     lib.fwime_last_error.argtypes = [P]
@@ -203,6 +210,22 @@ class Context:
             float(eps), dso.ctypes.data, obj.data_ptr(), _dptr(grad_vel, (grid.nx, grid.nz)),
             _dptr(grad_ptilde, (nh, grid.nx, grid.nz)), _stream(vel.device)))
 
+    def fwime_forward_tape(self, grid: Grid, vel, geom: Geometry, nh: int, ptilde, data) -> "Tape":
+        g = grid._c()
+        ge = geom._c()
+        h = ctypes.c_void_p()
+        self._check(self._lib.fwime_forward_tape(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(nh),
+            _dptr(ptilde, (nh, grid.nx, grid.nz)), _dptr(data, (geom.nshots, geom.nrec, grid.nt)),
+            ctypes.byref(h), _stream(vel.device)))
+        return Tape(self, h, grid, geom.nshots, geom.nrec, nh, vel.device)
+
+    def fwime_backward_tape(self, tape: "Tape", adjsrc, grad_vel, grad_ptilde):
+        g = tape.grid
+        self._check(self._lib.fwime_backward_tape(
+            self._h, tape._h, _dptr(adjsrc, (tape.nshots, tape.nrec, g.nt)), _dptr(grad_vel, (g.nx, g.nz)),
+            _dptr(grad_ptilde, (tape.nh, g.nx, g.nz)), _stream(adjsrc.device)))
+
     # --- allocating conveniences --------------------------------------------
     def model(self, grid: Grid, vel, geom: Geometry):
         data = torch.empty((geom.nshots, geom.nrec, grid.nt), device=vel.device, dtype=torch.float32)
@@ -226,3 +249,25 @@ class Context:
         gp = torch.empty((nh, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
         self.fwime_gradient(grid, vel, geom, nh, ptilde, dobs, eps, dso, obj, gv, gp)
         return obj, gv, gp
+
+
+class Tape:
+    """Device-resident checkpoints between fwime_forward_tape and fwime_backward_tape."""
+
+    def __init__(self, ctx: Context, handle, grid: Grid, nshots: int, nrec: int, nh: int, device):
+        self.ctx = ctx            # keeps the context alive while the tape exists
+        self._h = handle
+        self.grid = grid
+        self.nshots, self.nrec, self.nh = nshots, nrec, nh
+        self.device = device
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            self.ctx._lib.fwime_tape_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -125,6 +125,9 @@ hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long
 hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq,
                            hipStream_t st);
 
+// out = a + b (receiver data of u and du~)
+hipError_t launch_residual_sum(float *out, const float *a, const float *b, long n, hipStream_t st);
+
 // ptilde_out = 2/(v^3 dt^2) acc  (+ eps^2 d_h^2 p~ when ptilde != null)
 hipError_t launch_ext_finalize(const float *acc, const float *vel, const ExtGeom &g, float dt,
                                const float *ptilde, const float *dso2eps2, float *out, hipStream_t st);

@@ -596,6 +596,19 @@ hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long 
   return hipGetLastError();
 }
 
+__global__ void k_sum2(float *out, const float *a, const float *b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = a[i] + b[i];
+}
+
+hipError_t launch_residual_sum(float *out, const float *a, const float *b, long n, hipStream_t st) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_sum2<<<(unsigned)blocks, 256, 0, st>>>(out, a, b, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Finalizers
 // ---------------------------------------------------------------------------

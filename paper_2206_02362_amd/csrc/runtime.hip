@@ -36,6 +36,7 @@ struct fwime_ctx {
   size_t arena_bytes = 0;
   double *host_red = nullptr;   // pinned: reduction results
   int tile_x = 32;
+  size_t tape_bytes = 0;        // device memory held by live tapes
 };
 
 namespace {
@@ -384,13 +385,17 @@ StepArgs batch_args(const Common &c, int S, long sstride) {
   return a;
 }
 
-void with_src(StepArgs &a, const DevTables &t, const fwime_geom_t *geo, const fwime_grid_t *g, int s0, int n) {
+void with_src_w(StepArgs &a, const DevTables &t, const float *wav_b, const fwime_grid_t *g, int n) {
   a.inj.ptr = t.src_ptr;
   a.inj.ent = t.src_ent;
-  a.inj.val = geo->wavelet + (long)s0 * g->nt;
+  a.inj.val = wav_b;
   a.inj.stride_idx = g->nt;
   a.inj.t = n;
   a.inj.scale = (float)(1.0 / (g->dx * g->dz));
+}
+
+void with_src(StepArgs &a, const DevTables &t, const fwime_geom_t *geo, const fwime_grid_t *g, int s0, int n) {
+  with_src_w(a, t, geo->wavelet + (long)s0 * g->nt, g, n);
 }
 
 void with_rec_inject(StepArgs &a, const DevTables &t, const float *data, int nt, int k) {
@@ -720,6 +725,193 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   return FWIME_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// FWIME gradient building blocks, shared by fwime_gradient and the tape API.
+//
+// Forward (one batch): u and du~ together, segment by segment; at each segment
+// start the pairs (u^{n0-1}, u^{n0}) and (du~^{n0-1}, du~^{n0}) are stored, the
+// segment's T2u_n feeds the extended scatter whose output drives du~, and the
+// receivers of u and du~ are recorded separately.
+// Backward (one batch, adjoint source r at the receivers): per segment, from
+// last to first, recompute u (keeping T2u_n) and du~ (keeping T2du~_n), march
+// lambda (source r), spread lambda into the e ring, march rho (source the
+// transposed second time difference of e), then accumulate the extended image
+// sum T2u(y-h) lambda(y+h) and the per-cell sum (T2u + T2du~) lambda + T2u rho.
+// ---------------------------------------------------------------------------
+struct GradPlan {
+  int K, nseg, R;
+  long ck_stride, seg_stride, ring_stride;
+};
+
+GradPlan grad_plan(const Dims &d, int nt) {
+  GradPlan p;
+  p.K = seg_len(nt);
+  p.nseg = (nt - 1 + p.K - 1) / p.K;
+  p.R = p.K + 2;
+  p.ck_stride = 2L * p.nseg * d.field;
+  p.seg_stride = (long)p.K * d.field;
+  p.ring_stride = (long)p.R * d.field;
+  return p;
+}
+
+struct GradWork {       // per-batch working fields
+  float *pairs, *t2u, *t2d, *lam, *er, *rho;
+};
+
+int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
+                       const fwime_grid_t *g, int Sb, const DevTables &t, const float *wav_b, const float *coef,
+                       float *uck, float *dck, const GradWork &wk, float *drec, float *ddrec, int nrec,
+                       hipStream_t st) {
+  const Dims &d = c.d;
+  float *u0 = wk.pairs, *u1 = wk.pairs + d.field * Sb, *w0 = wk.pairs + 2 * d.field * Sb,
+        *w1 = wk.pairs + 3 * d.field * Sb;
+  HIPCHK(launch_zero(wk.pairs, 4 * d.field * Sb, st));
+  HIPCHK(launch_zero(wk.t2d, pl.seg_stride * Sb, st));
+  float *ucur = u0, *uprev = u1, *wcur = w0, *wprev = w1;
+  for (int j = 0; j < pl.nseg; ++j) {
+    const int n0 = j * pl.K, n1 = std::min(n0 + pl.K, g->nt - 1), nk = n1 - n0;
+    HIPCHK(launch_copy_fields(uck + (2L * j) * d.field, pl.ck_stride, uprev, d.field, Sb, d.field, st));
+    HIPCHK(launch_copy_fields(uck + (2L * j + 1) * d.field, pl.ck_stride, ucur, d.field, Sb, d.field, st));
+    HIPCHK(launch_copy_fields(dck + (2L * j) * d.field, pl.ck_stride, wprev, d.field, Sb, d.field, st));
+    HIPCHK(launch_copy_fields(dck + (2L * j + 1) * d.field, pl.ck_stride, wcur, d.field, Sb, d.field, st));
+    for (int n = n0; n < n1; ++n) {
+      StepArgs a = batch_args(c, Sb, d.field);
+      a.cur = ucur;
+      a.prev = uprev;
+      a.out = uprev;
+      a.t2 = wk.t2u + (long)(n - n0) * d.field;
+      a.t2_sstride = pl.seg_stride;
+      with_src_w(a, t, wav_b, g, n);
+      with_rec_extract(a, t, drec, g->nt, n);
+      HIPCHK(launch_step(a, d.TX, kModeT2, st));
+      std::swap(ucur, uprev);
+    }
+    HIPCHK(launch_ext_scatter(coef, eg, +1, wk.t2u, d.field, wk.t2d, d.field, pl.seg_stride, Sb, nk, st));
+    for (int n = n0; n < n1; ++n) {
+      StepArgs a = batch_args(c, Sb, d.field);
+      a.cur = wcur;
+      a.prev = wprev;
+      a.out = wprev;
+      a.dsrc = wk.t2d + (long)(n - n0) * d.field;
+      a.dsrc_sstride = pl.seg_stride;
+      with_rec_extract(a, t, ddrec, g->nt, n);
+      HIPCHK(launch_step(a, d.TX, kModeDsrc, st));
+      std::swap(wcur, wprev);
+    }
+  }
+  HIPCHK(launch_gather(ucur, d.field, t.cells, Sb, nrec, drec, g->nt, g->nt - 1, st));
+  HIPCHK(launch_gather(wcur, d.field, t.cells, Sb, nrec, ddrec, g->nt, g->nt - 1, st));
+  return FWIME_OK;
+}
+
+int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
+                        const fwime_grid_t *g, int Sb, const DevTables &t, const float *wav_b, const float *coef,
+                        float *uck, float *dck, const GradWork &wk, const float *r, float *acc, float *gacc,
+                        hipStream_t st) {
+  const Dims &d = c.d;
+  const int K = pl.K, R = pl.R;
+  HIPCHK(launch_zero(wk.lam, pl.ring_stride * Sb, st));
+  HIPCHK(launch_zero(wk.er, pl.ring_stride * Sb, st));
+  HIPCHK(launch_zero(wk.rho, pl.ring_stride * Sb, st));
+  for (int j = pl.nseg - 1; j >= 0; --j) {
+    const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
+    float *uc = uck + (2L * j + 1) * d.field, *up = uck + (2L * j) * d.field;
+    for (int n = n0; n < n1; ++n) {
+      StepArgs a = batch_args(c, Sb, pl.ck_stride);
+      a.cur = uc;
+      a.prev = up;
+      a.out = up;
+      a.t2 = wk.t2u + (long)(n - n0) * d.field;
+      a.t2_sstride = pl.seg_stride;
+      with_src_w(a, t, wav_b, g, n);
+      HIPCHK(launch_step(a, d.TX, kModeT2, st));
+      std::swap(uc, up);
+    }
+    // t2d holds T2 du~ of the later segment outside the scatter's range: clear it
+    HIPCHK(launch_zero(wk.t2d, pl.seg_stride * Sb, st));
+    HIPCHK(launch_ext_scatter(coef, eg, +1, wk.t2u, d.field, wk.t2d, d.field, pl.seg_stride, Sb, nk, st));
+    float *wc = dck + (2L * j + 1) * d.field, *wp = dck + (2L * j) * d.field;
+    for (int n = n0; n < n1; ++n) {
+      StepArgs a = batch_args(c, Sb, pl.ck_stride);
+      a.cur = wc;
+      a.prev = wp;
+      a.out = wp;
+      a.dsrc = wk.t2d + (long)(n - n0) * d.field;   // read the source, then
+      a.dsrc_sstride = pl.seg_stride;
+      a.t2 = wk.t2d + (long)(n - n0) * d.field;     // overwrite it with T2 du~_n
+      a.t2_sstride = pl.seg_stride;
+      HIPCHK(launch_step(a, d.TX, kModeT2 | kModeDsrc, st));
+      std::swap(wc, wp);
+    }
+    for (int k = n1; k >= n0 + 1; --k) {
+      StepArgs a = batch_args(c, Sb, pl.ring_stride);
+      a.cur = wk.lam + (long)(k % R) * d.field;
+      a.prev = wk.lam + (long)((k + 1) % R) * d.field;
+      a.out = wk.lam + (long)((k - 1) % R) * d.field;
+      with_rec_inject(a, t, r, g->nt, k);
+      HIPCHK(launch_step(a, d.TX, kModePlain, st));
+    }
+    HIPCHK(launch_ext_scatter(coef, eg, -1, wk.lam, d.field, wk.er, d.field, pl.ring_stride, Sb, nk, st, R, n0, R,
+                              n0));
+    for (int k = n1; k >= n0 + 1; --k) {
+      StepArgs a = batch_args(c, Sb, pl.ring_stride);
+      a.cur = wk.rho + (long)(k % R) * d.field;
+      a.prev = wk.rho + (long)((k + 1) % R) * d.field;
+      a.out = wk.rho + (long)((k - 1) % R) * d.field;
+      a.nu.em = wk.er + (long)((k - 1) % R) * d.field;
+      a.nu.e0 = wk.er + (long)(k % R) * d.field;
+      a.nu.ep = wk.er + (long)((k + 1) % R) * d.field;
+      a.nu.sstride = pl.ring_stride;
+      HIPCHK(launch_step(a, d.TX, kModeNu, st));
+    }
+    HIPCHK(launch_ext_image(wk.t2u, d.field, pl.seg_stride, wk.lam, d.field, pl.ring_stride, R, n0, Sb, nk, eg, acc,
+                            st));
+    HIPCHK(launch_grad_accum(wk.t2u, wk.t2d, d.field, pl.seg_stride, wk.lam, wk.rho, d.field, pl.ring_stride, R, n0,
+                             Sb, nk, d.NZ, d.NX, d.LZ, gacc, st));
+  }
+  return FWIME_OK;
+}
+
+long grad_work_per_shot(const Dims &d, const GradPlan &pl) {
+  return (4L + 2L * pl.K + 3L * pl.R) * d.field * 4;
+}
+
+void carve_work(Carve &cv, GradWork &wk, const Dims &d, const GradPlan &pl, int S) {
+  cv.add(&wk.pairs, 4 * d.field * S);
+  cv.add(&wk.t2u, (long)pl.K * d.field * S);
+  cv.add(&wk.t2d, (long)pl.K * d.field * S);
+  cv.add(&wk.lam, (long)pl.R * d.field * S);
+  cv.add(&wk.er, (long)pl.R * d.field * S);
+  cv.add(&wk.rho, (long)pl.R * d.field * S);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Tape: device-resident state between a forward and a backward call.
+// ---------------------------------------------------------------------------
+struct fwime_tape {
+  fwime_ctx_t *ctx = nullptr;
+  fwime_grid_t g{};
+  int nh = 0, nshots = 0, nrec = 0;
+  Dims d{};
+  GradPlan pl{};
+  std::vector<std::pair<int, int>> batches;
+  TableSet ts;
+  void *mem = nullptr;
+  size_t bytes = 0;
+  float *V = nullptr, *gz = nullptr, *gx = nullptr, *vel = nullptr, *pt = nullptr, *coef = nullptr, *wav = nullptr;
+  float *uck = nullptr, *dck = nullptr;   // [nshots] x ck_stride each
+  int *tables = nullptr;
+  bool used = false;
+};
+
+extern "C" {
+
 // ---------------------------------------------------------------------------
 int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo, int32_t nh,
                    const float *ptilde, const float *dobs, double eps, const double *dso, double *obj,
@@ -742,21 +934,19 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   c.d = make_dims(g, ctx->tile_x);
   const Dims &d = c.d;
   ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
-  const int K = seg_len(g->nt);
-  const int nseg = (g->nt - 1 + K - 1) / K;
-  const int R = K + 2;
+  const GradPlan pl = grad_plan(d, g->nt);
   const long img = (long)nh * d.nx * d.nz;
   const long nrt = (long)geo->nrec * g->nt;
-  const long per_shot = (4L + 4L * nseg + 2L * K + 3L * R) * d.field * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const long per_shot = grad_work_per_shot(d, pl) + 2 * pl.ck_stride * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
   const size_t fixed = (size_t)d.field * 12 + (size_t)img * 12;
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches);
 
-  float *coef = nullptr, *acc = nullptr, *imgs = nullptr, *gacc = nullptr, *pairs = nullptr, *uck = nullptr,
-        *dck = nullptr, *t2u = nullptr, *t2d = nullptr, *lam = nullptr, *er = nullptr, *rho = nullptr,
+  float *coef = nullptr, *acc = nullptr, *imgs = nullptr, *gacc = nullptr, *uck = nullptr, *dck = nullptr,
         *drec = nullptr, *ddrec = nullptr, *e2d2 = nullptr;
   double *sumsq = nullptr;
+  GradWork wk;
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
@@ -768,14 +958,9 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   cv.add(&acc, img);
   cv.add(&imgs, img);
   cv.add(&gacc, d.field);
-  cv.add(&pairs, 4 * d.field * S);
-  cv.add(&uck, 2L * nseg * d.field * S);
-  cv.add(&dck, 2L * nseg * d.field * S);
-  cv.add(&t2u, (long)K * d.field * S);
-  cv.add(&t2d, (long)K * d.field * S);
-  cv.add(&lam, (long)R * d.field * S);
-  cv.add(&er, (long)R * d.field * S);
-  cv.add(&rho, (long)R * d.field * S);
+  cv.add(&uck, pl.ck_stride * S);
+  cv.add(&dck, pl.ck_stride * S);
+  carve_work(cv, wk, d, pl, S);
   cv.add(&drec, nrt * S);
   cv.add(&ddrec, nrt * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -789,115 +974,194 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   HIPCHK(launch_zero(gacc, d.field, st));
   HIPCHK(hipMemsetAsync(sumsq, 0, 2 * sizeof(double), st));
 
-  const long ck_stride = 2L * nseg * d.field;
-  const long seg_stride = (long)K * d.field;
-  const long ring_stride = (long)R * d.field;
   for (size_t bi = 0; bi < batches.size(); ++bi) {
     const int s0 = batches[bi].first, Sb = batches[bi].second;
     const DevTables &t = ts.dev[bi];
-    const float *dobs_b = dobs + (long)s0 * nrt;
-    // ---------------- forward: u and du~ with checkpoints ----------------
-    float *u0 = pairs, *u1 = pairs + d.field * Sb, *w0 = pairs + 2 * d.field * Sb, *w1 = pairs + 3 * d.field * Sb;
-    HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
-    HIPCHK(launch_zero(t2d, seg_stride * Sb, st));
-    float *ucur = u0, *uprev = u1, *wcur = w0, *wprev = w1;
-    for (int j = 0; j < nseg; ++j) {
-      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
-      HIPCHK(launch_copy_fields(uck + (2L * j) * d.field, ck_stride, uprev, d.field, Sb, d.field, st));
-      HIPCHK(launch_copy_fields(uck + (2L * j + 1) * d.field, ck_stride, ucur, d.field, Sb, d.field, st));
-      HIPCHK(launch_copy_fields(dck + (2L * j) * d.field, ck_stride, wprev, d.field, Sb, d.field, st));
-      HIPCHK(launch_copy_fields(dck + (2L * j + 1) * d.field, ck_stride, wcur, d.field, Sb, d.field, st));
-      for (int n = n0; n < n1; ++n) {
-        StepArgs a = batch_args(c, Sb, d.field);
-        a.cur = ucur;
-        a.prev = uprev;
-        a.out = uprev;
-        a.t2 = t2u + (long)(n - n0) * d.field;
-        a.t2_sstride = seg_stride;
-        with_src(a, t, geo, g, s0, n);
-        with_rec_extract(a, t, drec, g->nt, n);
-        HIPCHK(launch_step(a, d.TX, kModeT2, st));
-        std::swap(ucur, uprev);
-      }
-      HIPCHK(launch_ext_scatter(coef, eg, +1, t2u, d.field, t2d, d.field, seg_stride, Sb, nk, st));
-      for (int n = n0; n < n1; ++n) {
-        StepArgs a = batch_args(c, Sb, d.field);
-        a.cur = wcur;
-        a.prev = wprev;
-        a.out = wprev;
-        a.dsrc = t2d + (long)(n - n0) * d.field;
-        a.dsrc_sstride = seg_stride;
-        with_rec_extract(a, t, ddrec, g->nt, n);
-        HIPCHK(launch_step(a, d.TX, kModeDsrc, st));
-        std::swap(wcur, wprev);
-      }
-    }
-    HIPCHK(launch_gather(ucur, d.field, t.cells, Sb, geo->nrec, drec, g->nt, g->nt - 1, st));
-    HIPCHK(launch_gather(wcur, d.field, t.cells, Sb, geo->nrec, ddrec, g->nt, g->nt - 1, st));
-    HIPCHK(launch_residual(drec, ddrec, dobs_b, nrt * Sb, sumsq, st));
-    // ---------------- backward ----------------
-    HIPCHK(launch_zero(lam, ring_stride * Sb, st));
-    HIPCHK(launch_zero(er, ring_stride * Sb, st));
-    HIPCHK(launch_zero(rho, ring_stride * Sb, st));
-    for (int j = nseg - 1; j >= 0; --j) {
-      const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
-      float *uc = uck + (2L * j + 1) * d.field, *up = uck + (2L * j) * d.field;
-      for (int n = n0; n < n1; ++n) {
-        StepArgs a = batch_args(c, Sb, ck_stride);
-        a.cur = uc;
-        a.prev = up;
-        a.out = up;
-        a.t2 = t2u + (long)(n - n0) * d.field;
-        a.t2_sstride = seg_stride;
-        with_src(a, t, geo, g, s0, n);
-        HIPCHK(launch_step(a, d.TX, kModeT2, st));
-        std::swap(uc, up);
-      }
-      // t2d holds T2 du~ of the later segment outside the scatter's range: clear it
-      HIPCHK(launch_zero(t2d, seg_stride * Sb, st));
-      HIPCHK(launch_ext_scatter(coef, eg, +1, t2u, d.field, t2d, d.field, seg_stride, Sb, nk, st));
-      float *wc = dck + (2L * j + 1) * d.field, *wp = dck + (2L * j) * d.field;
-      for (int n = n0; n < n1; ++n) {
-        StepArgs a = batch_args(c, Sb, ck_stride);
-        a.cur = wc;
-        a.prev = wp;
-        a.out = wp;
-        a.dsrc = t2d + (long)(n - n0) * d.field;   // read the source, then
-        a.dsrc_sstride = seg_stride;
-        a.t2 = t2d + (long)(n - n0) * d.field;     // overwrite it with T2 du~_n
-        a.t2_sstride = seg_stride;
-        HIPCHK(launch_step(a, d.TX, kModeT2 | kModeDsrc, st));
-        std::swap(wc, wp);
-      }
-      for (int k = n1; k >= n0 + 1; --k) {
-        StepArgs a = batch_args(c, Sb, ring_stride);
-        a.cur = lam + (long)(k % R) * d.field;
-        a.prev = lam + (long)((k + 1) % R) * d.field;
-        a.out = lam + (long)((k - 1) % R) * d.field;
-        with_rec_inject(a, t, drec, g->nt, k);
-        HIPCHK(launch_step(a, d.TX, kModePlain, st));
-      }
-      HIPCHK(launch_ext_scatter(coef, eg, -1, lam, d.field, er, d.field, ring_stride, Sb, nk, st, R, n0, R, n0));
-      for (int k = n1; k >= n0 + 1; --k) {
-        StepArgs a = batch_args(c, Sb, ring_stride);
-        a.cur = rho + (long)(k % R) * d.field;
-        a.prev = rho + (long)((k + 1) % R) * d.field;
-        a.out = rho + (long)((k - 1) % R) * d.field;
-        a.nu.em = er + (long)((k - 1) % R) * d.field;
-        a.nu.e0 = er + (long)(k % R) * d.field;
-        a.nu.ep = er + (long)((k + 1) % R) * d.field;
-        a.nu.sstride = ring_stride;
-        HIPCHK(launch_step(a, d.TX, kModeNu, st));
-      }
-      HIPCHK(launch_ext_image(t2u, d.field, seg_stride, lam, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
-      HIPCHK(launch_grad_accum(t2u, t2d, d.field, seg_stride, lam, rho, d.field, ring_stride, R, n0, Sb, nk, d.NZ,
-                               d.NX, d.LZ, gacc, st));
-    }
+    const float *wav_b = geo->wavelet + (long)s0 * g->nt;
+    if ((rc = grad_forward_batch(ctx, c, eg, pl, g, Sb, t, wav_b, coef, uck, dck, wk, drec, ddrec, geo->nrec, st)))
+      return rc;
+    HIPCHK(launch_residual(drec, ddrec, dobs + (long)s0 * nrt, nrt * Sb, sumsq, st));
+    if ((rc = grad_backward_batch(ctx, c, eg, pl, g, Sb, t, wav_b, coef, uck, dck, wk, drec, acc, gacc, st)))
+      return rc;
   }
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, imgs, st));
   HIPCHK(launch_grad_finalize(gacc, c.V, vel, eg, (float)g->dt, ptilde, imgs, grad_vel, st));
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, ptilde, e2d2, grad_ptilde, st));
   HIPCHK(launch_objective(sumsq, ptilde, e2d2, eg, obj, st));
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+void fwime_tape_free(fwime_tape_t *tape) {
+  if (!tape) return;
+  if (tape->mem) {
+    (void)hipSetDevice(tape->ctx ? tape->ctx->device : 0);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(tape->mem);
+    if (tape->ctx) tape->ctx->tape_bytes -= tape->bytes;
+  }
+  delete tape;
+}
+
+int fwime_forward_tape(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       int32_t nh, const float *ptilde, float *data, fwime_tape_t **tape_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (!tape_out) return set_err(ctx, FWIME_EINVAL, "tape_out is null");
+  *tape_out = nullptr;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if (!ptilde || !data) return set_err(ctx, FWIME_EINVAL, "null pointer argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {{ptilde, (long)nh * g->nx * g->nz}}, st))) return rc;
+
+  fwime_tape_t *tp = new fwime_tape_t();
+  tp->ctx = ctx;
+  tp->g = *g;
+  tp->nh = nh;
+  tp->nshots = geo->nshots;
+  tp->nrec = geo->nrec;
+  tp->d = make_dims(g, ctx->tile_x);
+  const Dims &d = tp->d;
+  tp->pl = grad_plan(d, g->nt);
+  const GradPlan &pl = tp->pl;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
+  const long img = (long)nh * d.nx * d.nz;
+  const long nrt = (long)geo->nrec * g->nt;
+  // checkpoints of every shot live in the tape; working fields in the arena
+  const long per_shot = grad_work_per_shot(d, pl) + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const size_t tape_fixed = (size_t)(2 * pl.ck_stride * 4) * geo->nshots;
+  const int S = choose_batch(ctx, per_shot, tape_fixed + (size_t)d.field * 8, geo->nshots);
+  tp->batches = split_batches(geo->nshots, S);
+  tp->ts = build_table_set(d, geo, tp->batches);
+
+  Carve tc;   // tape memory
+  tc.add(&tp->V, d.field);
+  tc.add(&tp->gz, d.LZ);
+  tc.add(&tp->gx, d.NX + kGxPad);
+  tc.add(&tp->tables, table_set_ints(tp->ts) + 64 * tp->batches.size() * 8);
+  tc.add(&tp->vel, (long)d.nx * d.nz);
+  tc.add(&tp->pt, img);
+  tc.add(&tp->coef, img);
+  tc.add(&tp->wav, (long)geo->nshots * g->nt);
+  tc.add(&tp->uck, pl.ck_stride * geo->nshots);
+  tc.add(&tp->dck, pl.ck_stride * geo->nshots);
+  if (ctx->budget && ctx->tape_bytes + tc.total + ctx->arena_bytes > ctx->budget) {
+    delete tp;
+    return set_err(ctx, FWIME_ENOMEM, "tape does not fit the HBM budget");
+  }
+  if (hipMalloc(&tp->mem, tc.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete tp;
+    return set_err(ctx, FWIME_ENOMEM, "hipMalloc of the tape failed");
+  }
+  tp->bytes = tc.total;
+  ctx->tape_bytes += tc.total;
+  {
+    char *p = (char *)tp->mem;
+    for (auto &it : tc.items) {
+      *it.first = p;
+      p += it.second;
+    }
+  }
+  auto fail = [&](int code) {
+    fwime_tape_free(tp);
+    return code;
+  };
+  if ((rc = upload_tables(ctx, tp->ts, tp->tables, st))) return fail(rc);
+  Common c;
+  c.d = d;
+  c.V = tp->V;
+  c.gz = tp->gz;
+  c.gx = tp->gx;
+  c.tables = tp->tables;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return fail(rc);
+  if (hipMemcpyAsync(tp->vel, vel, sizeof(float) * d.nx * d.nz, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(tp->pt, ptilde, sizeof(float) * img, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(tp->wav, geo->wavelet, sizeof(float) * geo->nshots * g->nt, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess)
+    return fail(set_err(ctx, FWIME_EHIP, "tape copy failed"));
+  if (launch_ext_coef(tp->pt, tp->vel, eg, (float)g->dt, tp->coef, st) != hipSuccess)
+    return fail(set_err(ctx, FWIME_EHIP, "coefficient launch failed"));
+
+  float *drec = nullptr, *ddrec = nullptr;
+  GradWork wk;
+  Carve cv;
+  carve_work(cv, wk, d, pl, S);
+  cv.add(&drec, nrt * S);
+  cv.add(&ddrec, nrt * S);
+  if ((rc = arena_get(ctx, cv))) return fail(rc);
+  for (size_t bi = 0; bi < tp->batches.size(); ++bi) {
+    const int s0 = tp->batches[bi].first, Sb = tp->batches[bi].second;
+    if ((rc = grad_forward_batch(ctx, c, eg, pl, g, Sb, tp->ts.dev[bi], tp->wav + (long)s0 * g->nt, tp->coef,
+                                 tp->uck + s0 * pl.ck_stride, tp->dck + s0 * pl.ck_stride, wk, drec, ddrec,
+                                 geo->nrec, st)))
+      return fail(rc);
+    // data = f(m) + B~ p~ for the batch
+    if (launch_residual_sum(data + (long)s0 * nrt, drec, ddrec, nrt * Sb, st) != hipSuccess)
+      return fail(set_err(ctx, FWIME_EHIP, "data sum failed"));
+  }
+  *tape_out = tp;
+  return FWIME_OK;
+}
+
+int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc, float *grad_vel,
+                        float *grad_ptilde, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (!tp || tp->ctx != ctx) return set_err(ctx, FWIME_EINVAL, "tape is null or belongs to another context");
+  if (tp->used) return set_err(ctx, FWIME_EINVAL, "the tape's checkpoints were consumed by a previous backward");
+  if (!adjsrc || !grad_vel || !grad_ptilde) return set_err(ctx, FWIME_EINVAL, "null pointer argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  const fwime_grid_t *g = &tp->g;
+  const Dims &d = tp->d;
+  const GradPlan &pl = tp->pl;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, tp->nh, (tp->nh - 1) / 2};
+  const long img = (long)tp->nh * d.nx * d.nz;
+  const long nrt = (long)tp->nrec * g->nt;
+  {
+    // finiteness of the adjoint source, checked before anything is written
+    double *scratch = nullptr;
+    Carve sc;
+    sc.add(&scratch, 4);
+    if ((rc = arena_get(ctx, sc))) return rc;
+    double r3[3];
+    if ((rc = device_range(ctx, adjsrc, nrt * tp->nshots, scratch, st, r3))) return rc;
+    if (r3[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "adjoint source has non-finite values");
+  }
+  int S = 0;
+  for (auto &b : tp->batches) S = std::max(S, b.second);
+  float *acc = nullptr, *imgs = nullptr, *gacc = nullptr;
+  GradWork wk;
+  Carve cv;
+  cv.add(&acc, img);
+  cv.add(&imgs, img);
+  cv.add(&gacc, d.field);
+  carve_work(cv, wk, d, pl, S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  Common c;
+  c.d = d;
+  c.V = tp->V;
+  c.gz = tp->gz;
+  c.gx = tp->gx;
+  c.tables = tp->tables;
+  if ((rc = setup_common(ctx, c, g, tp->vel, st))) return rc;
+  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero(gacc, d.field, st));
+  tp->used = true;   // backward recomputes the segments in place over the checkpoints
+  for (size_t bi = 0; bi < tp->batches.size(); ++bi) {
+    const int s0 = tp->batches[bi].first, Sb = tp->batches[bi].second;
+    if ((rc = grad_backward_batch(ctx, c, eg, pl, g, Sb, tp->ts.dev[bi], tp->wav + (long)s0 * g->nt, tp->coef,
+                                  tp->uck + s0 * pl.ck_stride, tp->dck + s0 * pl.ck_stride, wk,
+                                  adjsrc + (long)s0 * nrt, acc, gacc, st)))
+      return rc;
+  }
+  HIPCHK(launch_ext_finalize(acc, tp->vel, eg, (float)g->dt, nullptr, nullptr, imgs, st));
+  HIPCHK(launch_grad_finalize(gacc, c.V, tp->vel, eg, (float)g->dt, tp->pt, imgs, grad_vel, st));
+  HIPCHK(hipMemcpyAsync(grad_ptilde, imgs, sizeof(float) * img, hipMemcpyDeviceToDevice, st));
   return FWIME_OK;
 }
 
