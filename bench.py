@@ -99,6 +99,48 @@ def cpu_baseline(w, steps: int):
                       f"({cells:.3g} padded cell-updates in {dt:.1f} s, NumPy FP64, one thread)"}
 
 
+def batch_compare(ctx, nshots: int = 256):
+    """256 shots on three grid sizes (200x600, 300x1700, 500x2500), nt 3000-6000:
+    one fwime_model_batch call (all shots per launch, graph-replayed, autotuned
+    tile width) against the plain path, one fwime_model call per shot."""
+    import torch
+    import paper_2206_02362_amd as fw
+    import synth
+    ws = synth.batch_set(nshots)
+    vels = {}
+    jobs = []
+    cells = 0
+    for w in ws:
+        k = w.extra["size"]
+        if k not in vels:
+            vels[k] = torch.tensor(w.vel, dtype=torch.float32, device="cuda:0")
+        grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+        geo = fw.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix,
+                          torch.tensor(w.wavelet, dtype=torch.float32, device="cuda:0"))
+        data = torch.empty((1, w.nrec, w.nt), device="cuda:0")
+        jobs.append((grid, vels[k], geo, data))
+        cells += (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
+    log(f"batch compare: {len(jobs)} jobs, {cells:.3g} cell-updates")
+    ctx.fwime_model_batch(jobs)          # first call tunes the tile width
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.fwime_model_batch(jobs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    log(f"batched: {tb:.2f} s")
+    t = time.perf_counter()
+    for grid, vel, geo, data in jobs:
+        ctx.fwime_model(grid, vel, geo, data)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    log(f"plain: {tp:.2f} s")
+    return {"workload": f"{len(jobs)} shots on 200x600 / 300x1700 / 500x2500 grids (40-cell strip), "
+                        f"nt 3000-6000, Ricker 6-12 Hz, modeling",
+            "cell_updates": cells, "batched_s": tb, "plain_s": tp,
+            "batched_cell_updates_per_s": cells / tb, "plain_cell_updates_per_s": cells / tp,
+            "speedup": tp / tb, "tile_x": ctx.info()["last_batch_tile_x"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +152,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nt", type=int, default=None, help="shorten the time axis (counter runs)")
+    ap.add_argument("--no-batch-compare", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +251,10 @@ def main():
                 "bytes_per_launch": launch_bytes, "avg_launch_us": per_launch * 1e6}
     log(f"stencil: {per_launch * 1e6:.1f} us per launch, {achieved / 1e9:.0f} GB/s algorithmic")
 
+    batch = None
+    if not args.no_batch_compare:
+        batch = batch_compare(ctx)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
@@ -232,6 +279,7 @@ def main():
                    "model_cells": w.nz * w.nx},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_vs_plain": batch,
     }
     print(json.dumps(rec), flush=True)
 

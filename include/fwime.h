@@ -119,6 +119,33 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                    const float *dobs, double eps, const double *dso,
                    double *obj, float *grad_vel, float *grad_ptilde, void *stream);
 
+/* ---- Batched modeling of jobs with different grids ----------------------
+ * One job = one call's worth of fwime_model (grid, velocity, shots).  All
+ * jobs advance together: every time step is one launch over the tiles of all
+ * jobs (a job whose time axis is shorter idles once it is done), the time loop
+ * is replayed from a captured graph, and the tile width is chosen by timing
+ * the candidates on the first call for a given set of grid shapes (cached in
+ * the context).  Results equal fwime_model's for each job. */
+typedef struct {
+  fwime_grid_t grid;
+  const float *vel;        /* DEVICE [nx][nz] */
+  fwime_geom_t geom;
+  float *data;             /* DEVICE [nshots][nrec][nt], overwritten */
+} fwime_job_t;
+
+int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, void *stream);
+
+/* Context state, for schedulers and tests. */
+typedef struct {
+  size_t arena_bytes;        /* scratch arena currently held            */
+  size_t tape_bytes;         /* device memory held by live tapes         */
+  int32_t tile_x;            /* default stencil tile width               */
+  int32_t last_batch_tile_x; /* width used by the last fwime_model_batch */
+  int32_t tuned_signatures;  /* batch shapes with a tuned width          */
+} fwime_info_t;
+
+int fwime_ctx_info(const fwime_ctx_t *ctx, fwime_info_t *out);
+
 /* ---- Forward / backward split for automatic differentiation ------------
  * The pair below evaluates d = f(m) + B~(m) p~ (the predicted data of
  * eq. fwime.obj) and, later, the adjoint-state backward of that map: given

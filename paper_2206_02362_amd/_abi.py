@@ -22,9 +22,9 @@ FWIME_ENOMEM = 2
 FWIME_EHIP = 3
 FWIME_ENONFINITE = 4
 
-EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_gradient", "fwime_forward_tape", "fwime_backward_tape",
-            "fwime_tape_free", "fwime_strerror", "fwime_last_error")
+EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_model", "fwime_born_ext_fwd",
+            "fwime_born_ext_adj", "fwime_gradient", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
 class FwimeError(RuntimeError):
@@ -44,6 +44,15 @@ class _Geom(ctypes.Structure):
                 ("src_iz", ctypes.c_void_p), ("src_ix", ctypes.c_void_p),
                 ("rec_iz", ctypes.c_void_p), ("rec_ix", ctypes.c_void_p),
                 ("wavelet", ctypes.c_void_p)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("vel", ctypes.c_void_p), ("geom", _Geom), ("data", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("tape_bytes", ctypes.c_size_t), ("tile_x", ctypes.c_int32),
+                ("last_batch_tile_x", ctypes.c_int32), ("tuned_signatures", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,6 +79,10 @@ def load() -> ctypes.CDLL:
     lib.fwime_born_ext_adj.restype = I
     lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
     lib.fwime_gradient.restype = I
+    lib.fwime_model_batch.argtypes = [P, ctypes.c_int32, P, P]
+    lib.fwime_model_batch.restype = I
+    lib.fwime_ctx_info.argtypes = [P, P]
+    lib.fwime_ctx_info.restype = I
     lib.fwime_forward_tape.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.POINTER(P), P]
     lib.fwime_forward_tape.restype = I
     lib.fwime_backward_tape.argtypes = [P, P, P, P, P, P]
@@ -209,6 +222,32 @@ class Context:
             _dptr(ptilde, (nh, grid.nx, grid.nz)), _dptr(dobs, (geom.nshots, geom.nrec, grid.nt)),
             float(eps), dso.ctypes.data, obj.data_ptr(), _dptr(grad_vel, (grid.nx, grid.nz)),
             _dptr(grad_ptilde, (nh, grid.nx, grid.nz)), _stream(vel.device)))
+
+    def fwime_model_batch(self, jobs):
+        """jobs: sequence of (Grid, vel, Geometry, data) with caller-provided data tensors."""
+        arr = (_Job * len(jobs))()
+        keep = []
+        stream = None
+        for i, (grid, vel, geom, data) in enumerate(jobs):
+            arr[i].grid = grid._c()
+            arr[i].vel = _dptr(vel, (grid.nx, grid.nz))
+            arr[i].geom = geom._c()
+            arr[i].data = _dptr(data, (geom.nshots, geom.nrec, grid.nt))
+            keep.append(geom)
+            stream = _stream(vel.device)
+        self._check(self._lib.fwime_model_batch(self._h, len(jobs), ctypes.cast(arr, ctypes.c_void_p), stream))
+
+    def info(self) -> dict:
+        out = _Info()
+        self._check(self._lib.fwime_ctx_info(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _Info._fields_}
+
+    def model_batch(self, jobs):
+        """jobs: sequence of (Grid, vel, Geometry); returns one data tensor per job."""
+        outs = [torch.empty((geom.nshots, geom.nrec, grid.nt), device=vel.device, dtype=torch.float32)
+                for grid, vel, geom in jobs]
+        self.fwime_model_batch([(g, v, ge, d) for (g, v, ge), d in zip(jobs, outs)])
+        return outs
 
     def fwime_forward_tape(self, grid: Grid, vel, geom: Geometry, nh: int, ptilde, data) -> "Tape":
         g = grid._c()

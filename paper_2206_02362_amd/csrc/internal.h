@@ -69,6 +69,21 @@ enum StepMode : int {
   kModeNu = 4,       // add the e-ring second time difference as a dense source
 };
 
+// One job of a multi-job launch: its step arguments (cur/prev/out are chosen
+// per step from bufA/bufB by the parity of the job's time index), the job's
+// first tile in the launch, its time origin and length.
+struct BatchJob {
+  StepArgs a;
+  float *bufA = nullptr, *bufB = nullptr;
+  int tile_begin = 0;    // prefix of (tiles x shots) over the preceding jobs
+  int t0 = 0;            // global step at which the job's time index is 0
+  int nt = 0;
+};
+
+hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int tile_x,
+                             hipStream_t st);
+hipError_t launch_bump(int *step, int by, hipStream_t st);
+
 // Tile width in x of the stencil kernel (columns per workgroup).
 int step_tile_x_supported(int tx);
 hipError_t launch_step(const StepArgs &a, int tile_x, int mode, hipStream_t st);

@@ -31,18 +31,22 @@
 
 namespace fw {
 
+template <int TX>
+struct StepTile {
+  static constexpr int HC = TX + 2 * kR;
+  static constexpr int HZ = kTZ + 2 * kR;
+  float v[HC][HZ];
+};
+
+// One 64 x TX tile of one shot.  `logical` enumerates (x-chunk, z-strip, shot)
+// with the shot fastest.  With extract_only the kernel only samples the
+// receivers of the input field (the last time sample of a job).
 template <int TX, int MODE>
-__global__ void __launch_bounds__(256) k_step(const StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTile<TX> &sh, bool extract_only) {
   constexpr int CPW = TX / kWaves;
   constexpr int HC = TX + 2 * kR;
   constexpr int HZ = kTZ + 2 * kR;
-  __shared__ float tile[HC][HZ];
-
-  const int total = a.ntz * a.ntx * a.nshots;
-  const int per = (total + 7) >> 3;
-  const int b = blockIdx.x;
-  const int logical = (b & 7) * per + (b >> 3);
-  if (logical >= total) return;
+  auto &tile = sh.v;
   const int tile_id = logical / a.nshots;
   const int s = logical - tile_id * a.nshots;
   const int txi = tile_id / a.ntz;
@@ -109,6 +113,7 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
       a.ext.out[(long)en.y * a.ext.stride_idx + a.ext.t] = tile[(en.x >> 6) + kR][(en.x & 63) + kR];
     }
   }
+  if (extract_only) return;
 
   int p = 0, pend = 0;
   if (a.inj.ptr != nullptr) {
@@ -156,6 +161,70 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < 2 * kR; ++k) q[k] = q[k + 1];
   }
+}
+
+
+template <int TX, int MODE>
+__global__ void __launch_bounds__(256) k_step(const StepArgs a) {
+  __shared__ StepTile<TX> sh;
+  const int total = a.ntz * a.ntx * a.nshots;
+  const int per = (total + 7) >> 3;
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * per + (b >> 3);    // XCD-contiguous tile ranges
+  if (logical >= total) return;
+  step_body<TX, MODE>(a, logical, sh, false);
+}
+
+// Many jobs (different grids, models and geometries) in one launch.  Blocks
+// cover the concatenated tile lists of the jobs (prefix sums in tile_begin);
+// the time index of job j is *step - t0_j: it advances its fields while the
+// index is below nt_j - 1, samples its receivers at nt_j - 1 and is idle
+// outside [0, nt_j - 1].  Job j's fields alternate between bufA and bufB.
+template <int TX>
+__global__ void __launch_bounds__(256) k_step_multi(const BatchJob *jobs, int njobs, int total,
+                                                    const int *step) {
+  __shared__ StepTile<TX> sh;
+  const int per = (total + 7) >> 3;
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * per + (b >> 3);
+  if (logical >= total) return;
+  int lo = 0, hi = njobs - 1;                       // last job with tile_begin <= logical
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= logical) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchJob &jb = jobs[lo];
+  const int n = *step - jb.t0;
+  if (n < 0 || n > jb.nt - 1) return;
+  StepArgs a = jb.a;
+  const bool even = (n & 1) == 0;
+  a.cur = even ? jb.bufA : jb.bufB;
+  a.prev = even ? jb.bufB : jb.bufA;
+  a.out = const_cast<float *>(a.prev);
+  a.inj.t = n;
+  a.ext.t = n;
+  step_body<TX, kModePlain>(a, logical - jb.tile_begin, sh, n == jb.nt - 1);
+}
+
+__global__ void k_bump(int *step, int by) { *step += by; }
+
+hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int tile_x,
+                             hipStream_t st) {
+  const long per = (total_tiles + 7) / 8;
+  const dim3 grid((unsigned)(per * 8));
+  switch (tile_x) {
+    case 16: k_step_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 32: k_step_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 64: k_step_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bump(int *step, int by, hipStream_t st) {
+  k_bump<<<1, 1, 0, st>>>(step, by);
+  return hipGetLastError();
 }
 
 int step_tile_x_supported(int tx) { return tx == 16 || tx == 32 || tx == 64; }

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -37,7 +38,20 @@ struct fwime_ctx {
   double *host_red = nullptr;   // pinned: reduction results
   int tile_x = 32;
   size_t tape_bytes = 0;        // device memory held by live tapes
+  hipStream_t capture = nullptr;          // private stream used only to record graphs
+  std::map<std::string, int> tuned;       // batch signature -> tile width
+  int last_batch_tile = 0;
+  int graph_steps = 64;                   // steps per captured graph
+  hipGraph_t graph = nullptr;             // last batch graph, released after the
+  hipGraphExec_t graph_exec = nullptr;    // next stream synchronization
 };
+
+static void release_graph(fwime_ctx_t *ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+}
 
 namespace {
 
@@ -481,7 +495,22 @@ int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   }
   const char *tx = std::getenv("FWIME_TILE_X");
   if (tx && step_tile_x_supported(std::atoi(tx))) ctx->tile_x = std::atoi(tx);
+  if (hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipHostFree(ctx->host_red);
+    delete ctx;
+    return FWIME_EHIP;
+  }
   *out = ctx;
+  return FWIME_OK;
+}
+
+int fwime_ctx_info(const fwime_ctx_t *ctx, fwime_info_t *out) {
+  if (!ctx || !out) return FWIME_EINVAL;
+  out->arena_bytes = ctx->arena_bytes;
+  out->tape_bytes = ctx->tape_bytes;
+  out->tile_x = ctx->tile_x;
+  out->last_batch_tile_x = ctx->last_batch_tile;
+  out->tuned_signatures = (int32_t)ctx->tuned.size();
   return FWIME_OK;
 }
 
@@ -489,6 +518,8 @@ void fwime_ctx_destroy(fwime_ctx_t *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  release_graph(ctx);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->host_red) (void)hipHostFree(ctx->host_red);
   delete ctx;
@@ -1162,6 +1193,220 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
   HIPCHK(launch_ext_finalize(acc, tp->vel, eg, (float)g->dt, nullptr, nullptr, imgs, st));
   HIPCHK(launch_grad_finalize(gacc, c.V, tp->vel, eg, (float)g->dt, tp->pt, imgs, grad_vel, st));
   HIPCHK(hipMemcpyAsync(grad_ptilde, imgs, sizeof(float) * img, hipMemcpyDeviceToDevice, st));
+  return FWIME_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Many modeling jobs of different grids in one launch per time step.
+//
+// Every job keeps its own padded velocity, taper, receiver tables and two
+// field buffers per shot; a device array of BatchJob descriptors lets one
+// k_step_multi launch advance all of them.  The time loop is recorded once as
+// a graph of G (stencil, step-counter bump) node pairs on a private capture
+// stream and replayed on the caller's stream until the longest job is done.
+// The tile width comes from an autotuner: for a batch signature not seen
+// before, each candidate width is timed on scratch fields (zero initial
+// state, real velocity and sources) and the fastest is cached in the context.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  std::vector<Common> com;
+  std::vector<TableSet> ts;
+  std::vector<BatchJob> jobs;
+  int total = 0;
+  int nt_max = 0;
+};
+
+int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, BatchPlan &bp,
+               std::vector<std::pair<void **, size_t>> *) {
+  bp.com.assign(njobs, Common());
+  bp.ts.clear();
+  bp.jobs.assign(njobs, BatchJob());
+  bp.total = 0;
+  bp.nt_max = 0;
+  for (int j = 0; j < njobs; ++j) {
+    bp.com[j].d = make_dims(&jobs[j].grid, tx);
+    const Dims &d = bp.com[j].d;
+    bp.ts.push_back(build_table_set(d, &jobs[j].geom, {{0, jobs[j].geom.nshots}}));
+    bp.jobs[j].tile_begin = bp.total;
+    bp.jobs[j].t0 = 0;
+    bp.jobs[j].nt = jobs[j].grid.nt;
+    bp.total += d.ntz * d.ntx * jobs[j].geom.nshots;
+    bp.nt_max = std::max(bp.nt_max, jobs[j].grid.nt);
+  }
+  return FWIME_OK;
+}
+
+int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, BatchPlan &bp, BatchJob **djobs,
+                          int **dstep, hipStream_t st) {
+  Carve cv;
+  std::vector<float *> fields(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const Dims &d = bp.com[j].d;
+    cv.add(&bp.com[j].V, d.field);
+    cv.add(&bp.com[j].gz, d.LZ);
+    cv.add(&bp.com[j].gx, d.NX + kGxPad);
+    cv.add(&bp.com[j].tables, table_set_ints(bp.ts[j]) + 64 * 8);
+    cv.add(&fields[j], 2 * d.field * jobs[j].geom.nshots);
+  }
+  cv.add(djobs, njobs);
+  cv.add(dstep, 1);
+  int rc = arena_get(ctx, cv);
+  if (rc) return rc;
+  for (int j = 0; j < njobs; ++j) {
+    const Dims &d = bp.com[j].d;
+    const int S = jobs[j].geom.nshots;
+    if ((rc = upload_tables(ctx, bp.ts[j], bp.com[j].tables, st))) return rc;
+    if ((rc = setup_common(ctx, bp.com[j], &jobs[j].grid, jobs[j].vel, st))) return rc;
+    HIPCHK(launch_zero(fields[j], 2 * d.field * S, st));
+    BatchJob &bj = bp.jobs[j];
+    bj.a = batch_args(bp.com[j], S, d.field);
+    with_src(bj.a, bp.ts[j].dev[0], &jobs[j].geom, &jobs[j].grid, 0, 0);
+    with_rec_extract(bj.a, bp.ts[j].dev[0], jobs[j].data, jobs[j].grid.nt, 0);
+    bj.bufA = fields[j];
+    bj.bufB = fields[j] + d.field * S;
+  }
+  HIPCHK(hipMemcpyAsync(*djobs, bp.jobs.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FWIME_OK;
+}
+
+std::string batch_signature(int njobs, const fwime_job_t *jobs) {
+  std::string sig;
+  char buf[96];
+  for (int j = 0; j < njobs; ++j) {
+    std::snprintf(buf, sizeof buf, "%d,%d,%d,%d;", jobs[j].grid.nz + 2 * jobs[j].grid.nb,
+                  jobs[j].grid.nx + 2 * jobs[j].grid.nb, jobs[j].geom.nshots, jobs[j].grid.nt > 1);
+    sig += buf;
+  }
+  return sig;
+}
+
+int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStream_t st, int *best_tx) {
+  const int cand[3] = {16, 32, 64};
+  float best = 1e30f;
+  *best_tx = ctx->tile_x;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = FWIME_OK;
+  for (int tx : cand) {
+    BatchPlan bp;
+    BatchJob *dj = nullptr;
+    int *dstep = nullptr;
+    if ((rc = batch_plan(ctx, njobs, jobs, tx, bp, nullptr))) break;
+    // scratch run: receivers off, time kept below every job's last step
+    for (auto &jb : bp.jobs) jb.a.ext.ptr = nullptr;
+    if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) break;
+    for (int k = 0; k < njobs; ++k) bp.jobs[k].a.ext.ptr = nullptr;
+    if (hipMemcpyAsync(dj, bp.jobs.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(dstep, 0, sizeof(int), st) != hipSuccess) {
+      rc = set_err(ctx, FWIME_EHIP, "autotune setup failed");
+      break;
+    }
+    const int warm = 2, timed = 8;
+    for (int i = 0; i < warm + timed; ++i) {
+      if (i == warm) (void)hipEventRecord(e0, st);
+      if (launch_step_multi(dj, njobs, bp.total, dstep, tx, st) != hipSuccess ||
+          launch_bump(dstep, 1, st) != hipSuccess) {
+        rc = set_err(ctx, FWIME_EHIP, "autotune launch failed");
+        break;
+      }
+    }
+    if (rc) break;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = set_err(ctx, FWIME_EHIP, "autotune sync failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      *best_tx = tx;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (njobs < 1 || !jobs) return set_err(ctx, FWIME_EINVAL, "need njobs >= 1 and a job array");
+  long nt_steps = 0;
+  for (int j = 0; j < njobs; ++j) {
+    if ((rc = check_grid(ctx, &jobs[j].grid)) || (rc = check_geom(ctx, &jobs[j].grid, &jobs[j].geom))) return rc;
+    if (!jobs[j].data) return set_err(ctx, FWIME_EINVAL, "job data is null");
+    nt_steps = std::max<long>(nt_steps, jobs[j].grid.nt);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int j = 0; j < njobs; ++j)
+    if ((rc = check_inputs(ctx, &jobs[j].grid, jobs[j].vel, &jobs[j].geom, {}, st))) return rc;
+  release_graph(ctx);   // the input checks synchronized the stream: earlier replays are done
+
+  const std::string sig = batch_signature(njobs, jobs);
+  int tx = ctx->tile_x;
+  if (!std::getenv("FWIME_TILE_X")) {
+    auto it = ctx->tuned.find(sig);
+    if (it != ctx->tuned.end()) {
+      tx = it->second;
+    } else {
+      if ((rc = batch_autotune(ctx, njobs, jobs, st, &tx))) return rc;
+      ctx->tuned[sig] = tx;
+    }
+  }
+  ctx->last_batch_tile = tx;
+
+  BatchPlan bp;
+  BatchJob *dj = nullptr;
+  int *dstep = nullptr;
+  if ((rc = batch_plan(ctx, njobs, jobs, tx, bp, nullptr))) return rc;
+  if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) return rc;
+  HIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), st));
+
+  const int G = ctx->graph_steps;
+  const bool use_graph = !std::getenv("FWIME_NO_GRAPH");
+  if (!use_graph) {
+    for (long n = 0; n < bp.nt_max; ++n) {
+      HIPCHK(launch_step_multi(dj, njobs, bp.total, dstep, tx, st));
+      HIPCHK(launch_bump(dstep, 1, st));
+    }
+    return FWIME_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+  hipError_t cap = hipSuccess;
+  for (int i = 0; i < G && cap == hipSuccess; ++i) {
+    cap = launch_step_multi(dj, njobs, bp.total, dstep, tx, ctx->capture);
+    if (cap == hipSuccess) cap = launch_bump(dstep, 1, ctx->capture);
+  }
+  hipError_t endc = hipStreamEndCapture(ctx->capture, &graph);
+  if (cap != hipSuccess || endc != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return set_err(ctx, FWIME_EHIP, "graph capture failed");
+  }
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return set_err(ctx, FWIME_EHIP, "graph instantiation failed");
+  }
+  const long replays = (bp.nt_max + G - 1) / G;
+  hipError_t le = hipSuccess;
+  for (long r = 0; r < replays && le == hipSuccess; ++r) le = hipGraphLaunch(exec, st);
+  ctx->graph = graph;          // kept until the replays have certainly finished
+  ctx->graph_exec = exec;
+  if (le != hipSuccess) return set_err(ctx, FWIME_EHIP, "graph launch failed");
   return FWIME_OK;
 }
 

@@ -221,3 +221,24 @@ def dso_weights(nh: int) -> np.ndarray:
     H = (nh - 1) // 2
     ih = np.arange(-H, H + 1, dtype=np.float64)
     return np.sqrt(ih ** 2 + 1.0)
+
+
+def batch_set(nshots: int = 256, seed: int = 2362, nt_range=(3000, 6000), dt: float = 8e-4,
+              sizes=((200, 600), (300, 1700), (500, 2500)), nb: int = 40, dx: float = 10.0) -> list:
+    """Shots of uneven grids: each shot is its own job (grid drawn uniformly from
+    `sizes`, smooth random 1500-4500 m/s model of that size with 300 m
+    correlation, Ricker peak U(6, 12) Hz, nt uniform in nt_range, source at a
+    random column 20 m deep, receivers on every column at 20 m)."""
+    rng = np.random.default_rng(seed)
+    models = [smooth_random_velocity(nz, nx, dx, seed + 1 + i, 1500.0, 4500.0, 300.0)
+              for i, (nz, nx) in enumerate(sizes)]
+    jobs = []
+    for s in range(nshots):
+        k = int(rng.integers(len(sizes)))
+        nz, nx = sizes[k]
+        nt = int(rng.integers(nt_range[0], nt_range[1] + 1))
+        f = float(rng.uniform(6.0, 12.0))
+        ix = int(rng.integers(0, nx))
+        geo = surface_line(1, [ix], nx, iz=2, nt=nt, dt=dt, f_peak=f)
+        jobs.append(Workload(f"batch-{nz}x{nx}", nz, nx, nb, nt, dx, dx, dt, models[k], extra={"size": k}, **geo))
+    return jobs
