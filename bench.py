@@ -141,6 +141,62 @@ def batch_compare(ctx, nshots: int = 256):
             "speedup": tp / tb, "tile_x": ctx.info()["last_batch_tile_x"]}
 
 
+def serve_compare(nreq: int, seed: int = 42, slots: int = 3):
+    """A seeded Poisson stream (mean 20 requests/s) of modeling 40 %, extended
+    Born 30 % (half forward, half adjoint) and gradient 30 % requests on grids
+    from 200x600 to 600x3000 (10 m, 40-cell strip), 1-32 shots, nt 2000-6000,
+    11 offsets, over six resident models: the request loop (`slots` streams,
+    footprint admission, merged modeling) against plain first-come-first-served
+    (one request at a time, one context, no merging)."""
+    import torch
+    import synth
+    import paper_2206_02362_amd as fw
+    from paper_2206_02362_amd.serve import Request, Server
+    mix = synth.serve_mix(nreq=nreq, seed=seed)
+
+    def requests(srv):
+        for k, (nz, nx, v) in enumerate(mix.pool):
+            srv.add_model(k, fw.Grid(nz, nx, mix.nb, 2, mix.dx, mix.dx, mix.dt),
+                          torch.tensor(v, dtype=torch.float32, device="cuda:0"))
+        out = []
+        for spec in mix.requests:
+            x = synth.serve_request_inputs(mix, spec, "cuda:0")
+            geo = fw.Geometry(x["src_iz"], x["src_ix"], x["rec_iz"], x["rec_ix"], x["wavelet"])
+            out.append(Request(spec.kind, spec.model, geo, x["nt"], nh=mix.nh, ptilde=x.get("ptilde"),
+                               data=x.get("data"), dobs=x.get("dobs"), dso=x.get("dso")))
+        return out
+
+    arrivals = [s.arrival for s in mix.requests]
+    res = {}
+    for name, kw in (("plain_fifo", dict(slots=1, merge_models=1)), ("served", dict(slots=slots, merge_models=8))):
+        srv = Server(0, **kw)
+        reqs = requests(srv)
+        torch.cuda.synchronize()
+        log(f"serve replay ({name}): {len(reqs)} requests")
+        done = srv.replay(reqs, arrivals)
+        torch.cuda.synchronize()
+        errs = [r for r in done if r.error is not None]
+        if errs:
+            raise RuntimeError(f"{len(errs)} requests failed, first: {errs[0].error}")
+        st = Server.stats(done)
+        st["peak_reserved_bytes"] = srv.peak_reserved
+        st["budget_bytes"] = srv.budget
+        res[name] = st
+        log(f"  {name}: p50 {st['p50_s']:.2f} s, p99 {st['p99_s']:.2f} s, makespan {st['makespan_s']:.2f} s")
+        for s_ in srv.slots:
+            s_.ctx.close()
+        del srv, reqs, done
+        torch.cuda.empty_cache()
+    kinds = {}
+    for s_ in mix.requests:
+        kinds[s_.kind] = kinds.get(s_.kind, 0) + 1
+    return {"workload": f"{nreq} requests, Poisson 20/s (seed {seed}), kinds {kinds}, grids 200x600..600x3000, "
+                        f"1-32 shots, nt 2000-6000, nh {mix.nh}, {len(mix.pool)} resident models",
+            "slots": slots, **res,
+            "throughput_speedup": res["served"]["cell_updates_per_s"] / res["plain_fifo"]["cell_updates_per_s"],
+            "p99_ratio_served_over_plain": res["served"]["p99_s"] / res["plain_fifo"]["p99_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nt", type=int, default=None, help="shorten the time axis (counter runs)")
     ap.add_argument("--no-batch-compare", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16, help="requests in the serving replay (0: skip)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -171,6 +229,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.copy_calibration:
         copy_calibration(1 << 30, 5)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serve_compare(args.serve_requests)}), flush=True)
         return
     ops = [o for o in args.ops.split(",") if o]
     w = make_workload(args.workload, args.shots)
@@ -255,6 +316,15 @@ def main():
     if not args.no_batch_compare:
         batch = batch_compare(ctx)
 
+    serving = None
+    if args.serve_requests > 0:
+        # give the device memory of the step back to the server's budget
+        outs.clear()
+        del data
+        ctx.trim()
+        torch.cuda.empty_cache()
+        serving = serve_compare(args.serve_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
@@ -280,6 +350,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

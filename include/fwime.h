@@ -146,6 +146,21 @@ typedef struct {
 
 int fwime_ctx_info(const fwime_ctx_t *ctx, fwime_info_t *out);
 
+/* Release the context's scratch arena after `stream` (its stream) is idle.
+ * The next call allocates again.  For schedulers that share one HBM budget
+ * among several contexts. */
+int fwime_ctx_trim(fwime_ctx_t *ctx, void *stream);
+
+/* Device bytes one call of operator `op` needs to run all nshots shots in a
+ * single batch (the scratch the context arena must hold).  Calls with less
+ * budget run their shots in several batches. */
+#define FWIME_OP_MODEL     0
+#define FWIME_OP_BORN_FWD  1
+#define FWIME_OP_BORN_ADJ  2
+#define FWIME_OP_GRADIENT  3
+int fwime_footprint(const fwime_grid_t *grid, int32_t nshots, int32_t nrec, int32_t nh, int32_t op,
+                    size_t *bytes);
+
 /* ---- Forward / backward split for automatic differentiation ------------
  * The pair below evaluates d = f(m) + B~(m) p~ (the predicted data of
  * eq. fwime.obj) and, later, the adjoint-state backward of that map: given

@@ -11,12 +11,17 @@ from ._abi import (  # noqa: F401
     FWIME_ENOMEM,
     FWIME_ENONFINITE,
     FWIME_OK,
+    FWIME_OP_BORN_ADJ,
+    FWIME_OP_BORN_FWD,
+    FWIME_OP_GRADIENT,
+    FWIME_OP_MODEL,
     LIB_PATH,
     Context,
     FwimeError,
     Geometry,
     Grid,
     Tape,
+    footprint,
     load,
 )
 from .autograd import FwimeOp, predicted_data  # noqa: F401,E402

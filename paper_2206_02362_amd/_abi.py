@@ -22,7 +22,10 @@ FWIME_ENOMEM = 2
 FWIME_EHIP = 3
 FWIME_ENONFINITE = 4
 
-EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_model", "fwime_born_ext_fwd",
+FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 2, 3
+
+EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
+            "fwime_model", "fwime_born_ext_fwd",
             "fwime_born_ext_adj", "fwime_gradient", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
@@ -83,6 +86,11 @@ def load() -> ctypes.CDLL:
     lib.fwime_model_batch.restype = I
     lib.fwime_ctx_info.argtypes = [P, P]
     lib.fwime_ctx_info.restype = I
+    lib.fwime_ctx_trim.argtypes = [P, P]
+    lib.fwime_ctx_trim.restype = I
+    lib.fwime_footprint.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.fwime_footprint.restype = I
     lib.fwime_forward_tape.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.POINTER(P), P]
     lib.fwime_forward_tape.restype = I
     lib.fwime_backward_tape.argtypes = [P, P, P, P, P, P]
@@ -237,6 +245,11 @@ class Context:
             stream = _stream(vel.device)
         self._check(self._lib.fwime_model_batch(self._h, len(jobs), ctypes.cast(arr, ctypes.c_void_p), stream))
 
+    def trim(self, stream=None):
+        """Release the scratch arena once this context's stream is idle."""
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self._lib.fwime_ctx_trim(self._h, st))
+
     def info(self) -> dict:
         out = _Info()
         self._check(self._lib.fwime_ctx_info(self._h, ctypes.byref(out)))
@@ -310,3 +323,14 @@ class Tape:
             self.free()
         except Exception:
             pass
+
+
+def footprint(grid: Grid, nshots: int, nrec: int, nh: int, op: int) -> int:
+    """Device bytes one call of `op` needs to run all shots in one batch."""
+    lib = load()
+    out = ctypes.c_size_t()
+    g = grid._c()
+    rc = lib.fwime_footprint(ctypes.byref(g), int(nshots), int(nrec), int(nh), int(op), ctypes.byref(out))
+    if rc != FWIME_OK:
+        raise FwimeError(rc, lib.fwime_strerror(rc).decode())
+    return int(out.value)

@@ -38,6 +38,7 @@ struct fwime_ctx {
   double *host_red = nullptr;   // pinned: reduction results
   int tile_x = 32;
   size_t tape_bytes = 0;        // device memory held by live tapes
+  size_t last_arena_request = 0;
   hipStream_t capture = nullptr;          // private stream used only to record graphs
   std::map<std::string, int> tuned;       // batch signature -> tile width
   int last_batch_tile = 0;
@@ -55,7 +56,8 @@ static void release_graph(fwime_ctx_t *ctx) {
 
 namespace {
 
-constexpr int kGxPad = 64;   // zero taper entries past NX read by the last x-tile
+constexpr int kGxPad = 64;
+constexpr int kGraphMaxTiles = 16384;   // batches above this many tiles launch directly   // zero taper entries past NX read by the last x-tile
 constexpr double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 
 int set_err(fwime_ctx_t *ctx, int code, const std::string &msg) {
@@ -115,19 +117,31 @@ int arena_get(fwime_ctx_t *ctx, Carve &cv) {
     if (ctx->budget && cv.total > ctx->budget)
       return set_err(ctx, FWIME_ENOMEM, "request of " + std::to_string(cv.total) + " bytes exceeds the HBM budget");
     if (ctx->arena) {
-      HIPCHK(hipDeviceSynchronize());
+      // the context's work runs on one stream, which every call synchronizes
+      // during its input checks: the old arena is idle here
       HIPCHK(hipFree(ctx->arena));
       ctx->arena = nullptr;
       ctx->arena_bytes = 0;
     }
-    hipError_t e = hipMalloc(&ctx->arena, cv.total);
+    // grow geometrically (within the budget) so that a sequence of slightly
+    // larger calls does not reallocate every time
+    size_t want = std::max(cv.total, ctx->last_arena_request + ctx->last_arena_request / 2);
+    if (ctx->budget) want = std::min(want, ctx->budget);
+    want = std::max(want, cv.total);
+    hipError_t e = hipMalloc(&ctx->arena, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      want = cv.total;
+      e = hipMalloc(&ctx->arena, want);
+    }
     if (e != hipSuccess) {
       ctx->arena = nullptr;
       (void)hipGetLastError();
       return set_err(ctx, FWIME_ENOMEM, "hipMalloc of " + std::to_string(cv.total) + " bytes failed");
     }
-    ctx->arena_bytes = cv.total;
+    ctx->arena_bytes = want;
   }
+  ctx->last_arena_request = std::max(ctx->last_arena_request, cv.total);
   char *p = (char *)ctx->arena;
   for (auto &it : cv.items) {
     *it.first = p;
@@ -495,12 +509,19 @@ int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   }
   const char *tx = std::getenv("FWIME_TILE_X");
   if (tx && step_tile_x_supported(std::atoi(tx))) ctx->tile_x = std::atoi(tx);
-  if (hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipHostFree(ctx->host_red);
-    delete ctx;
-    return FWIME_EHIP;
-  }
   *out = ctx;
+  return FWIME_OK;
+}
+
+int fwime_ctx_trim(fwime_ctx_t *ctx, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FWIME_EHIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return FWIME_EHIP;
+  release_graph(ctx);
+  if (ctx->arena && hipFree(ctx->arena) != hipSuccess) return FWIME_EHIP;
+  ctx->arena = nullptr;
+  ctx->arena_bytes = 0;
+  ctx->last_arena_request = 0;
   return FWIME_OK;
 }
 
@@ -1213,61 +1234,83 @@ namespace {
 // state, real velocity and sources) and the fastest is cached in the context.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-  std::vector<Common> com;
+  std::vector<int> order;        // position k in the launch -> caller's job index
+  std::vector<Common> com;       // per position
   std::vector<TableSet> ts;
   std::vector<BatchJob> jobs;
+  std::vector<int> prefix;       // tiles before position k
   int total = 0;
   int nt_max = 0;
 };
 
+// Jobs are laid out in order of decreasing time-axis length, so the jobs still
+// running at step n are a prefix of the list and a launch can stop at that
+// prefix's last tile.
 int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, BatchPlan &bp,
                std::vector<std::pair<void **, size_t>> *) {
+  (void)ctx;
+  bp.order.resize(njobs);
+  for (int j = 0; j < njobs; ++j) bp.order[j] = j;
+  std::stable_sort(bp.order.begin(), bp.order.end(),
+                   [&](int a, int b) { return jobs[a].grid.nt > jobs[b].grid.nt; });
   bp.com.assign(njobs, Common());
   bp.ts.clear();
   bp.jobs.assign(njobs, BatchJob());
+  bp.prefix.assign(njobs + 1, 0);
   bp.total = 0;
   bp.nt_max = 0;
-  for (int j = 0; j < njobs; ++j) {
-    bp.com[j].d = make_dims(&jobs[j].grid, tx);
-    const Dims &d = bp.com[j].d;
+  for (int k = 0; k < njobs; ++k) {
+    const int j = bp.order[k];
+    bp.com[k].d = make_dims(&jobs[j].grid, tx);
+    const Dims &d = bp.com[k].d;
     bp.ts.push_back(build_table_set(d, &jobs[j].geom, {{0, jobs[j].geom.nshots}}));
-    bp.jobs[j].tile_begin = bp.total;
-    bp.jobs[j].t0 = 0;
-    bp.jobs[j].nt = jobs[j].grid.nt;
+    bp.jobs[k].tile_begin = bp.total;
+    bp.jobs[k].t0 = 0;
+    bp.jobs[k].nt = jobs[j].grid.nt;
     bp.total += d.ntz * d.ntx * jobs[j].geom.nshots;
+    bp.prefix[k + 1] = bp.total;
     bp.nt_max = std::max(bp.nt_max, jobs[j].grid.nt);
   }
   return FWIME_OK;
+}
+
+// tiles of the jobs whose time index n is still within [0, nt - 1]
+int batch_active_tiles(const BatchPlan &bp, long n) {
+  int k = 0;
+  while (k < (int)bp.jobs.size() && n <= bp.jobs[k].nt - 1) ++k;
+  return bp.prefix[k];
 }
 
 int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, BatchPlan &bp, BatchJob **djobs,
                           int **dstep, hipStream_t st) {
   Carve cv;
   std::vector<float *> fields(njobs);
-  for (int j = 0; j < njobs; ++j) {
-    const Dims &d = bp.com[j].d;
-    cv.add(&bp.com[j].V, d.field);
-    cv.add(&bp.com[j].gz, d.LZ);
-    cv.add(&bp.com[j].gx, d.NX + kGxPad);
-    cv.add(&bp.com[j].tables, table_set_ints(bp.ts[j]) + 64 * 8);
-    cv.add(&fields[j], 2 * d.field * jobs[j].geom.nshots);
+  for (int k = 0; k < njobs; ++k) {
+    const int j = bp.order[k];
+    const Dims &d = bp.com[k].d;
+    cv.add(&bp.com[k].V, d.field);
+    cv.add(&bp.com[k].gz, d.LZ);
+    cv.add(&bp.com[k].gx, d.NX + kGxPad);
+    cv.add(&bp.com[k].tables, table_set_ints(bp.ts[k]) + 64 * 8);
+    cv.add(&fields[k], 2 * d.field * jobs[j].geom.nshots);
   }
   cv.add(djobs, njobs);
   cv.add(dstep, 1);
   int rc = arena_get(ctx, cv);
   if (rc) return rc;
-  for (int j = 0; j < njobs; ++j) {
-    const Dims &d = bp.com[j].d;
+  for (int k = 0; k < njobs; ++k) {
+    const int j = bp.order[k];
+    const Dims &d = bp.com[k].d;
     const int S = jobs[j].geom.nshots;
-    if ((rc = upload_tables(ctx, bp.ts[j], bp.com[j].tables, st))) return rc;
-    if ((rc = setup_common(ctx, bp.com[j], &jobs[j].grid, jobs[j].vel, st))) return rc;
-    HIPCHK(launch_zero(fields[j], 2 * d.field * S, st));
-    BatchJob &bj = bp.jobs[j];
-    bj.a = batch_args(bp.com[j], S, d.field);
-    with_src(bj.a, bp.ts[j].dev[0], &jobs[j].geom, &jobs[j].grid, 0, 0);
-    with_rec_extract(bj.a, bp.ts[j].dev[0], jobs[j].data, jobs[j].grid.nt, 0);
-    bj.bufA = fields[j];
-    bj.bufB = fields[j] + d.field * S;
+    if ((rc = upload_tables(ctx, bp.ts[k], bp.com[k].tables, st))) return rc;
+    if ((rc = setup_common(ctx, bp.com[k], &jobs[j].grid, jobs[j].vel, st))) return rc;
+    HIPCHK(launch_zero(fields[k], 2 * d.field * S, st));
+    BatchJob &bj = bp.jobs[k];
+    bj.a = batch_args(bp.com[k], S, d.field);
+    with_src(bj.a, bp.ts[k].dev[0], &jobs[j].geom, &jobs[j].grid, 0, 0);
+    with_rec_extract(bj.a, bp.ts[k].dev[0], jobs[j].data, jobs[j].grid.nt, 0);
+    bj.bufA = fields[k];
+    bj.bufB = fields[k] + d.field * S;
   }
   HIPCHK(hipMemcpyAsync(*djobs, bp.jobs.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1376,16 +1419,22 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   HIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), st));
 
   const int G = ctx->graph_steps;
-  const bool use_graph = !std::getenv("FWIME_NO_GRAPH");
+  // Large batches: one direct launch per step over the still-running jobs
+  // only (launch latency is negligible next to the step).  Small batches:
+  // replay a captured graph of G full-width steps (idle jobs exit at once).
+  const bool use_graph = !std::getenv("FWIME_NO_GRAPH") && bp.total <= kGraphMaxTiles;
   if (!use_graph) {
     for (long n = 0; n < bp.nt_max; ++n) {
-      HIPCHK(launch_step_multi(dj, njobs, bp.total, dstep, tx, st));
+      HIPCHK(launch_step_multi(dj, njobs, batch_active_tiles(bp, n), dstep, tx, st));
       HIPCHK(launch_bump(dstep, 1, st));
     }
     return FWIME_OK;
   }
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the capture stream is made on first use: contexts that never capture
+  // (one per serving slot, say) do not take a hardware queue for it
+  if (!ctx->capture) HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
   hipError_t cap = hipSuccess;
   for (int i = 0; i < G && cap == hipSuccess; ++i) {
@@ -1407,6 +1456,28 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   ctx->graph = graph;          // kept until the replays have certainly finished
   ctx->graph_exec = exec;
   if (le != hipSuccess) return set_err(ctx, FWIME_EHIP, "graph launch failed");
+  return FWIME_OK;
+}
+
+int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t nh, int32_t op, size_t *bytes) {
+  if (!g || !bytes || nshots < 1 || nrec < 1 || nh < 1 || g->nt < 2) return FWIME_EINVAL;
+  const Dims d = make_dims(g, 32);
+  const long fb = d.field * 4;
+  const long img = (long)nh * d.nx * d.nz * 4;
+  const long nrt = (long)nrec * g->nt * 4;
+  const GradPlan pl = grad_plan(d, g->nt);
+  long per_shot = 0, fixed = fb + (long)(d.NX + d.LZ) * 4;
+  switch (op) {
+    case FWIME_OP_MODEL: per_shot = 2 * fb; break;
+    case FWIME_OP_BORN_FWD: per_shot = (4 + 2 * 16) * fb; fixed += img; break;
+    case FWIME_OP_BORN_ADJ: per_shot = (2 + 2L * pl.nseg + pl.K + pl.R) * fb; fixed += img; break;
+    case FWIME_OP_GRADIENT:
+      per_shot = grad_work_per_shot(d, pl) + 2 * pl.ck_stride * 4 + 2 * nrt;
+      fixed += 3 * img;
+      break;
+    default: return FWIME_EINVAL;
+  }
+  *bytes = (size_t)(fixed + per_shot * nshots + (long)nrec * nshots * 64);
   return FWIME_OK;
 }
 

@@ -242,3 +242,86 @@ def batch_set(nshots: int = 256, seed: int = 2362, nt_range=(3000, 6000), dt: fl
         geo = surface_line(1, [ix], nx, iz=2, nt=nt, dt=dt, f_peak=f)
         jobs.append(Workload(f"batch-{nz}x{nx}", nz, nx, nb, nt, dx, dx, dt, models[k], extra={"size": k}, **geo))
     return jobs
+
+
+@dataclass
+class ServeRequestSpec:
+    """One request of a serving replay (host-side description only)."""
+    arrival: float                # seconds after the replay starts
+    kind: str                     # model | born_fwd | born_adj | gradient
+    model: int                    # index into the resident model pool
+    src_ix: np.ndarray            # [nshots] source columns (20 m deep)
+    nt: int
+    f_peak: float
+    seed: int                     # seeds this request's random inputs
+
+
+@dataclass
+class ServeMix:
+    pool: list                    # [(nz, nx, vel [nx][nz] float64)]
+    requests: list                # [ServeRequestSpec], sorted by arrival
+    nb: int
+    dx: float
+    dt: float
+    nh: int
+
+
+def serve_mix(nreq: int = 24, seed: int = 42, rate: float = 20.0, npool: int = 6,
+              nz_choices=tuple(range(200, 601, 100)), nx_choices=tuple(range(600, 3001, 200)),
+              shots=(1, 32), nt_choices=tuple(range(2000, 6001, 500)), dt: float = 8e-4, dx: float = 10.0,
+              nb: int = 40, nh: int = 11,
+              mix=(("model", 0.4), ("born_fwd", 0.15), ("born_adj", 0.15), ("gradient", 0.3))) -> ServeMix:
+    """Seeded Poisson request stream over a pool of resident velocity models.
+
+    Inter-arrival times are exponential with mean 1/rate.  The pool holds
+    `npool` smooth random 1500-4500 m/s models (300 m correlation) whose grid
+    sizes are drawn uniformly from the nz/nx choices; each request picks a
+    pool model uniformly, a kind from `mix`, a shot count uniform in `shots`
+    (sources at distinct random columns), nt from `nt_choices` and a Ricker
+    peak U(6, 12) Hz.  Receivers sit on every column at 20 m depth."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(npool):
+        nz = int(rng.choice(nz_choices))
+        nx = int(rng.choice(nx_choices))
+        pool.append((nz, nx, smooth_random_velocity(nz, nx, dx, seed + 1 + i, 1500.0, 4500.0, 300.0)))
+    kinds = [k for k, _ in mix]
+    probs = np.array([p for _, p in mix], dtype=np.float64)
+    probs /= probs.sum()
+    t = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    for r in range(nreq):
+        kind = str(rng.choice(kinds, p=probs))
+        m = int(rng.integers(npool))
+        nx = pool[m][1]
+        ns = int(rng.integers(shots[0], shots[1] + 1))
+        src = np.sort(rng.choice(nx, size=min(ns, nx), replace=False)).astype(np.int32)
+        reqs.append(ServeRequestSpec(float(t[r]), kind, m, src, int(rng.choice(nt_choices)),
+                                     float(rng.uniform(6.0, 12.0)), seed * 1000 + r))
+    return ServeMix(pool, reqs, nb, dx, dt, nh)
+
+
+def serve_request_inputs(mix: ServeMix, spec: ServeRequestSpec, device: str = "cuda:0", nt_cap: int | None = None):
+    """Geometry arrays (host) and seeded random device tensors for one request.
+
+    ptilde ~ 1e-2 N(0, 1) [nh][nx][nz] for Born forward and gradient requests;
+    data ~ N(0, 1) [nshots][nx][nt] for Born adjoint requests; observed data
+    ~ 1e-3 N(0, 1) and DSO weights sqrt(ih^2 + 1) for gradient requests.
+    nt_cap shortens the time axis (parity runs at the full grid sizes)."""
+    import torch
+    nz, nx, _ = mix.pool[spec.model]
+    nt = spec.nt if nt_cap is None else min(spec.nt, nt_cap)
+    ns = len(spec.src_ix)
+    geo = surface_line(ns, spec.src_ix, nx, iz=2, nt=nt, dt=mix.dt, f_peak=spec.f_peak)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(spec.seed)
+    out = dict(geo, nt=nt)
+    out["wavelet"] = torch.tensor(geo["wavelet"], dtype=torch.float32, device=device)
+    if spec.kind in ("born_fwd", "gradient"):
+        out["ptilde"] = 1e-2 * torch.randn((mix.nh, nx, nz), generator=gen, device=device)
+    if spec.kind == "born_adj":
+        out["data"] = torch.randn((ns, nx, nt), generator=gen, device=device)
+    if spec.kind == "gradient":
+        out["dobs"] = 1e-3 * torch.randn((ns, nx, nt), generator=gen, device=device)
+        out["dso"] = dso_weights(mix.nh)
+    return out

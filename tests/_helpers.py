@@ -43,3 +43,20 @@ def oracle_problem_f32(w):
     g = oracle.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
     geo = oracle.Geometry(w32.src_iz, w32.src_ix, w32.rec_iz, w32.rec_ix, w32.wavelet)
     return g, geo, w32.vel
+
+
+def serve_setup(mix, server, dev="cuda:0", nt_cap=None):
+    """Register the pool's models on `server` and build one Request per spec."""
+    import torch
+    import paper_2206_02362_amd as fw
+    from paper_2206_02362_amd.serve import Request
+    for k, (nz, nx, vel) in enumerate(mix.pool):
+        server.add_model(k, fw.Grid(nz, nx, mix.nb, 2, mix.dx, mix.dx, mix.dt),
+                         torch.tensor(vel, dtype=torch.float32, device=dev))
+    reqs = []
+    for spec in mix.requests:
+        x = synth.serve_request_inputs(mix, spec, dev, nt_cap)
+        geo = fw.Geometry(x["src_iz"], x["src_ix"], x["rec_iz"], x["rec_ix"], x["wavelet"])
+        reqs.append(Request(spec.kind, spec.model, geo, x["nt"], nh=mix.nh, ptilde=x.get("ptilde"),
+                            data=x.get("data"), dobs=x.get("dobs"), dso=x.get("dso")))
+    return reqs
