@@ -10,6 +10,7 @@ namespace fw {
 constexpr int kTZ = 64;        // rows (z) per tile: one wavefront, lane = z
 constexpr int kR = 4;          // stencil radius (8th-order second derivative)
 constexpr int kWaves = 4;      // wavefronts per stencil workgroup
+constexpr int kTZ2 = 56;       // output rows per tile of the two-step kernel (64 lanes = rows z0-4 .. z0+59)
 
 // Per-tile injection list (compressed rows over tile*kWaves + wave).
 // An entry {(j << 6) | lz, idx} adds  val[idx * stride_idx + t] * scale  to the
@@ -67,6 +68,7 @@ enum StepMode : int {
   kModeT2 = 1,       // also write V (L cur + src)
   kModeDsrc = 2,     // add a dense source field
   kModeNu = 4,       // add the e-ring second time difference as a dense source
+  kModeDF = 8,       // two-step kernel only: fields carried as FP32 hi + BF16 lo
 };
 
 // One job of a multi-job launch: its step arguments (cur/prev/out are chosen
@@ -79,6 +81,46 @@ struct BatchJob {
   int t0 = 0;            // global step at which the job's time index is 0
   int nt = 0;
 };
+
+// Two time steps per launch (see kernels_step2.hip).  a.prev = u^{n-1} and
+// a.cur = u^n (both read with halos), a.out = u^{n+1}, out2 = u^{n+2}: four
+// distinct buffers.  a.inj lists the step-1 sources per (tile, wave) over the
+// tile plus a 4-cell halo (time a.inj.t = n), inj2 the step-2 sources on the
+// tile (time n + 1).  a.ext samples u^n at a.ext.t and u^{n+1} at a.ext.t + 1.
+// a.t2 / t2b receive V (L u + f) of the two steps (mode kModeT2); a.dsrc /
+// dsrc2 are dense sources of the two steps (mode kModeDsrc, a.dsrc read on
+// the halo: it must not alias a.t2).  a.ntz counts 56-row tiles.  two == 0:
+// one step only (no out2, t2b, dsrc2, inj2, second sample).
+struct Step2Args {
+  StepArgs a;
+  float *out2 = nullptr;
+  float *t2b = nullptr;
+  const float *dsrc2 = nullptr;
+  NuSource nu2;                 // mode kModeNu: slots of the second step (a.nu: first)
+  Inject inj2;
+  // mode kModeDF: BF16 low parts of prev / cur / out / out2 (same layout and
+  // shot stride as the FP32 fields)
+  const unsigned short *lo_prev = nullptr, *lo_cur = nullptr;
+  unsigned short *lo_out = nullptr, *lo_out2 = nullptr;
+  int two = 1;
+};
+
+// mode: kModePlain, kModeT2, kModeDsrc, kModeNu, kModeDF or kModeT2 | kModeDF
+hipError_t launch_step2(const Step2Args &p, int tile_x, int mode, hipStream_t st);
+
+// One job of a two-step multi-job launch: its step arguments (fields, times
+// and the step flag are filled in per launch from buf and the step counter),
+// four field buffers, first tile in the launch, time origin and length.
+struct BatchJob2 {
+  Step2Args p;
+  float *buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int tile_begin = 0;
+  int t0 = 0;
+  int nt = 0;
+};
+
+hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int tile_x,
+                              hipStream_t st);
 
 hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int tile_x,
                              hipStream_t st);

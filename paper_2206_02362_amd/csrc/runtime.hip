@@ -37,6 +37,7 @@ struct fwime_ctx {
   size_t arena_bytes = 0;
   double *host_red = nullptr;   // pinned: reduction results
   int tile_x = 32;
+  bool two_step = true;         // plain propagation two time steps per launch
   size_t tape_bytes = 0;        // device memory held by live tapes
   size_t last_arena_request = 0;
   hipStream_t capture = nullptr;          // private stream used only to record graphs
@@ -56,8 +57,8 @@ static void release_graph(fwime_ctx_t *ctx) {
 
 namespace {
 
-constexpr int kGxPad = 64;
-constexpr int kGraphMaxTiles = 16384;   // batches above this many tiles launch directly   // zero taper entries past NX read by the last x-tile
+constexpr int kGxPad = 64;              // zero taper entries past NX read by the last x-tile
+constexpr int kGraphMaxTiles = 16384;   // batches above this many tiles launch directly
 constexpr double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 
 int set_err(fwime_ctx_t *ctx, int code, const std::string &msg) {
@@ -79,6 +80,7 @@ double cfl_limit(double dz, double dx) {
 
 struct Dims {
   int nz, nx, nb, nt, NZ, NX, LZ, ntz, ntx, TX;
+  int ntz2;     // 56-row tiles of the two-step kernel
   long field;   // NX * LZ
 };
 
@@ -93,6 +95,7 @@ Dims make_dims(const fwime_grid_t *g, int tx) {
   d.LZ = (d.NZ + 4 + 63) / 64 * 64;   // >= 4 zero rows below the grid in every column
   d.TX = tx;
   d.ntz = (d.NZ + kTZ - 1) / kTZ;
+  d.ntz2 = (d.NZ + kTZ2 - 1) / kTZ2;
   d.ntx = (d.NX + tx - 1) / tx;
   d.field = (long)d.NX * d.LZ;
   return d;
@@ -238,14 +241,18 @@ int check_inputs(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, cons
 // tables are batch-local (shot s, receiver s * nrec + r); callers offset the
 // wavelet and data pointers to the batch start.
 // ---------------------------------------------------------------------------
+// One-step tiling (64-row tiles): src / rinj lists per (tile, wave) on the
+// tile, rext per tile.  Two-step tiling (56-row tiles): src / rinj are the
+// step-2 lists on the tile, src1 / rinj1 the step-1 lists over the tile plus
+// a 4-cell halo, rext per tile.
 struct HostTables {
-  std::vector<int> src_ptr, rext_ptr, rinj_ptr, cells;
-  std::vector<int2> src_ent, rext_ent, rinj_ent;
+  std::vector<int> src_ptr, rext_ptr, rinj_ptr, cells, src1_ptr, rinj1_ptr;
+  std::vector<int2> src_ent, rext_ent, rinj_ent, src1_ent, rinj1_ent;
 };
 
 struct DevTables {
-  int *src_ptr, *rext_ptr, *rinj_ptr, *cells;
-  int2 *src_ent, *rext_ent, *rinj_ent;
+  int *src_ptr, *rext_ptr, *rinj_ptr, *cells, *src1_ptr, *rinj1_ptr;
+  int2 *src_ent, *rext_ent, *rinj_ent, *src1_ent, *rinj1_ent;
 };
 
 void csr_build(std::vector<int> &ptr, std::vector<int2> &ent, long nbucket,
@@ -295,9 +302,56 @@ HostTables build_tables(const Dims &d, const fwime_geom_t *geo, int s0, int S) {
   return t;
 }
 
+// Two-step tiling: a cell (px, pz) lies on the tile (txi, tzi) with
+// txi = px / TX, tzi = pz / 56, and in the step-1 region (tile plus 4-cell
+// halo) of every tile whose [x0 - 4, x0 + TX + 4) x [z0 - 4, z0 + 60) holds it.
+HostTables build_tables2(const Dims &d, const fwime_geom_t *geo, int s0, int S) {
+  HostTables t;
+  const int W1 = (d.TX + 2 * kR) / kWaves, W2 = d.TX / kWaves;
+  const long ntiles = (long)d.ntz2 * d.ntx * S;
+  auto tile_of = [&](int s, int txi, int tzi) { return ((long)txi * d.ntz2 + tzi) * S + s; };
+  std::vector<std::pair<long, int2>> src1, src2, rext, rinj1, rinj2;
+  auto add_inject = [&](int s, int px, int pz, int idx, std::vector<std::pair<long, int2>> &l1,
+                        std::vector<std::pair<long, int2>> &l2) {
+    const int txi = px / d.TX, tzi = pz / kTZ2;
+    {
+      const int lx = px - txi * d.TX, lane = pz - tzi * kTZ2 + kR;
+      l2.push_back({tile_of(s, txi, tzi) * kWaves + lx / W2, make_int2(((lx % W2) << 6) | lane, idx)});
+    }
+    // candidate neighbours: the own tile and the ones before / after it
+    for (int tx = std::max(0, txi - 1); tx <= std::min(d.ntx - 1, txi + 1); ++tx)
+      for (int tz = std::max(0, tzi - 1); tz <= std::min(d.ntz2 - 1, tzi + 1); ++tz) {
+        const int jj = px - (tx * d.TX - kR), lane = pz - (tz * kTZ2 - kR);
+        if (jj < 0 || jj >= d.TX + 2 * kR || lane < 0 || lane >= 64) continue;
+        l1.push_back({tile_of(s, tx, tz) * kWaves + jj / W1, make_int2(((jj % W1) << 6) | lane, idx)});
+      }
+  };
+  for (int s = 0; s < S; ++s) {
+    const int sg = s0 + s;
+    add_inject(s, geo->src_ix[sg] + d.nb, geo->src_iz[sg] + d.nb, s, src1, src2);
+    for (int r = 0; r < geo->nrec; ++r) {
+      const long ir = (long)sg * geo->nrec + r;
+      const int il = s * geo->nrec + r;
+      const int px = geo->rec_ix[ir] + d.nb, pz = geo->rec_iz[ir] + d.nb;
+      const int txi = px / d.TX, tzi = pz / kTZ2;
+      rext.push_back({tile_of(s, txi, tzi), make_int2(((px - txi * d.TX) << 6) | (pz - tzi * kTZ2), il)});
+      add_inject(s, px, pz, il, rinj1, rinj2);
+      t.cells.push_back(px * d.LZ + pz);
+    }
+  }
+  csr_build(t.src1_ptr, t.src1_ent, ntiles * kWaves, src1);
+  csr_build(t.src_ptr, t.src_ent, ntiles * kWaves, src2);
+  csr_build(t.rext_ptr, t.rext_ent, ntiles, rext);
+  csr_build(t.rinj1_ptr, t.rinj1_ent, ntiles * kWaves, rinj1);
+  csr_build(t.rinj_ptr, t.rinj_ent, ntiles * kWaves, rinj2);
+  return t;
+}
+
 size_t tables_ints(const HostTables &t) {
-  return t.src_ptr.size() + t.rext_ptr.size() + t.rinj_ptr.size() + t.cells.size() +
-         2 * (t.src_ent.size() + t.rext_ent.size() + t.rinj_ent.size()) + 7 * 64;
+  return t.src_ptr.size() + t.rext_ptr.size() + t.rinj_ptr.size() + t.cells.size() + t.src1_ptr.size() +
+         t.rinj1_ptr.size() +
+         2 * (t.src_ent.size() + t.rext_ent.size() + t.rinj_ent.size() + t.src1_ent.size() + t.rinj1_ent.size()) +
+         11 * 64;
 }
 
 // Lay out all batch tables into one host blob and one device buffer.
@@ -307,9 +361,11 @@ struct TableSet {
   std::vector<int> blob;
 };
 
-TableSet build_table_set(const Dims &d, const fwime_geom_t *geo, const std::vector<std::pair<int, int>> &batches) {
+TableSet build_table_set(const Dims &d, const fwime_geom_t *geo, const std::vector<std::pair<int, int>> &batches,
+                         bool two_step = false) {
   TableSet ts;
-  for (auto &b : batches) ts.host.push_back(build_tables(d, geo, b.first, b.second));
+  for (auto &b : batches)
+    ts.host.push_back(two_step ? build_tables2(d, geo, b.first, b.second) : build_tables(d, geo, b.first, b.second));
   return ts;
 }
 
@@ -338,6 +394,10 @@ int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
     o.push_back(put(t.src_ent.data(), 2 * t.src_ent.size()));
     o.push_back(put(t.rext_ent.data(), 2 * t.rext_ent.size()));
     o.push_back(put(t.rinj_ent.data(), 2 * t.rinj_ent.size()));
+    o.push_back(put(t.src1_ptr.data(), t.src1_ptr.size()));
+    o.push_back(put(t.src1_ent.data(), 2 * t.src1_ent.size()));
+    o.push_back(put(t.rinj1_ptr.data(), t.rinj1_ptr.size()));
+    o.push_back(put(t.rinj1_ent.data(), 2 * t.rinj1_ent.size()));
     offs.push_back(o);
   }
   for (auto &o : offs) {
@@ -349,6 +409,10 @@ int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
     dt.src_ent = (int2 *)(dev + o[4]);
     dt.rext_ent = (int2 *)(dev + o[5]);
     dt.rinj_ent = (int2 *)(dev + o[6]);
+    dt.src1_ptr = dev + o[7];
+    dt.src1_ent = (int2 *)(dev + o[8]);
+    dt.rinj1_ptr = dev + o[9];
+    dt.rinj1_ent = (int2 *)(dev + o[10]);
     ts.dev.push_back(dt);
   }
   // The blob is copied synchronously (pageable memory): the call owns no
@@ -443,6 +507,124 @@ void with_rec_extract(StepArgs &a, const DevTables &t, float *data, int nt, int 
   a.ext.t = n;
 }
 
+// Four field buffers of one batch for the two-step kernel: prev = f[i],
+// cur = f[i + 1]; a launch of k steps writes f[i + 2] (and f[i + 3]) and
+// advances i by k.  Neither output buffer is read by that launch, and after
+// it u^{n-1}, u^n, u^{n+1}, u^{n+2} are all still in memory.
+template <class T>
+struct Ring4T {
+  T *f[4];
+  int i = 0;
+  Ring4T(T *base, long stride) {
+    for (int k = 0; k < 4; ++k) f[k] = base + k * stride;
+  }
+  T *at(int k) const { return f[(i + k) & 3]; }
+  T *prev() const { return at(0); }
+  T *cur() const { return at(1); }
+  void advance(int k) { i += k; }
+};
+using Ring4 = Ring4T<float>;
+using Ring4L = Ring4T<unsigned short>;   // BF16 low parts of an extended-precision field
+
+Step2Args step2_args(const Common &c, const Ring4 &f, int S, long sstride, int k) {
+  Step2Args p;
+  p.a = batch_args(c, S, sstride);
+  p.a.ntz = c.d.ntz2;
+  p.a.prev = f.prev();
+  p.a.cur = f.cur();
+  p.a.out = f.at(2);
+  p.out2 = k == 2 ? f.at(3) : nullptr;
+  p.two = k == 2;
+  return p;
+}
+
+// point sources: step-1 list at time n, step-2 list at time n + 1
+void with_src2(Step2Args &p, const DevTables &t, const float *wav_b, const fwime_grid_t *g, int n) {
+  with_src_w(p.a, t, wav_b, g, n);
+  p.a.inj.ptr = t.src1_ptr;
+  p.a.inj.ent = t.src1_ent;
+  p.inj2 = p.a.inj;
+  p.inj2.ptr = t.src_ptr;
+  p.inj2.ent = t.src_ent;
+  p.inj2.t = n + 1;
+}
+
+// receiver injection (adjoint sources): time k1 of `data` in step 1, k2 in
+// step 2 (k2 = k1 - 1 when the recursion runs backwards in time)
+void with_rec_inject2(Step2Args &p, const DevTables &t, const float *data, int nt, int k1, int k2) {
+  with_rec_inject(p.a, t, data, nt, k1);
+  p.a.inj.ptr = t.rinj1_ptr;
+  p.a.inj.ent = t.rinj1_ent;
+  p.inj2 = p.a.inj;
+  p.inj2.ptr = t.rinj_ptr;
+  p.inj2.ent = t.rinj_ent;
+  p.inj2.t = k2;
+}
+
+// Advances ring f over the steps n0 .. n1 - 1 forward in time: two steps per
+// launch, one in the last launch when the count is odd.  setup(p, n, k) adds
+// the step-specific arguments of the launch that starts at step n.
+// With lo != nullptr the field is carried in extended precision (mode gets
+// kModeDF) and lo rotates with f.
+template <class Setup>
+int march2(fwime_ctx_t *ctx, const Common &c, Ring4 &f, int S, int n0, int n1, int mode, Setup setup,
+           hipStream_t st, Ring4L *lo = nullptr) {
+  for (int n = n0; n < n1;) {
+    const int k = std::min(2, n1 - n);
+    Step2Args p = step2_args(c, f, S, c.d.field, k);
+    if (lo) {
+      p.lo_prev = lo->prev();
+      p.lo_cur = lo->cur();
+      p.lo_out = lo->at(2);
+      p.lo_out2 = k == 2 ? lo->at(3) : nullptr;
+    }
+    setup(p, n, k);
+    HIPCHK(launch_step2(p, c.d.TX, lo ? (mode | kModeDF) : mode, st));
+    f.advance(k);
+    if (lo) lo->advance(k);
+    n += k;
+  }
+  return FWIME_OK;
+}
+
+// BF16 arrays copied as 32-bit words (fields hold an even number of cells)
+hipError_t copy_lo(unsigned short *dst, long dst_sstride, const unsigned short *src, long src_sstride, int S, long n,
+                   hipStream_t st) {
+  return launch_copy_fields((float *)dst, dst_sstride / 2, (const float *)src, src_sstride / 2, S, n / 2, st);
+}
+
+// Adjoint recursion over a ring of R field slots (slot of time k: k % R),
+// from time k = k1 down to k0 + 1, producing the fields of times k1 - 1 ..
+// k0: two steps per launch.  setup(p, k, kk) adds the sources of the launch
+// that starts at time k.
+template <class Setup>
+int march2_back_ring(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_stride, int R, int S, int k0, int k1,
+                     int mode, Setup setup, hipStream_t st) {
+  const long F = c.d.field;
+  for (int k = k1; k >= k0 + 1;) {
+    const int kk = (k - 2 >= k0) ? 2 : 1;
+    Step2Args p;
+    p.a = batch_args(c, S, ring_stride);
+    p.a.ntz = c.d.ntz2;
+    p.a.cur = ring + (long)(k % R) * F;
+    p.a.prev = ring + (long)((k + 1) % R) * F;
+    p.a.out = ring + (long)((k - 1) % R) * F;
+    p.out2 = kk == 2 ? ring + (long)((k - 2) % R) * F : nullptr;
+    p.two = kk == 2;
+    setup(p, k, kk);
+    HIPCHK(launch_step2(p, c.d.TX, mode, st));
+    k -= kk;
+  }
+  return FWIME_OK;
+}
+
+// lambda: receiver injection of `data` at the current time
+int march2_back_lambda(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_stride, int R, int S, int k0,
+                       int k1, const DevTables &t, const float *data, int nt, hipStream_t st) {
+  return march2_back_ring(ctx, c, ring, ring_stride, R, S, k0, k1, kModePlain,
+                          [&](Step2Args &p, int k, int) { with_rec_inject2(p, t, data, nt, k, k - 1); }, st);
+}
+
 int choose_batch(fwime_ctx_t *ctx, long per_shot_bytes, size_t fixed_bytes, int nshots) {
   size_t avail = 0, total = 0;
   if (hipMemGetInfo(&avail, &total) != hipSuccess) avail = 0;
@@ -468,9 +650,12 @@ std::vector<std::pair<int, int>> split_batches(int nshots, int S) {
   return b;
 }
 
+// Segment length of the sqrt(nt) checkpointing, rounded up to an even count
+// so two-step launches never straddle a segment start.
 int seg_len(int nt) {
   int K = (int)std::ceil(std::sqrt((double)(nt - 1)));
-  return std::max(K, 1);
+  K = std::max(K, 1);
+  return K + (K & 1);
 }
 
 
@@ -509,6 +694,9 @@ int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   }
   const char *tx = std::getenv("FWIME_TILE_X");
   if (tx && step_tile_x_supported(std::atoi(tx))) ctx->tile_x = std::atoi(tx);
+  // FWIME_STEP1=1: one time step per launch everywhere (same results, bit for bit)
+  const char *s1 = std::getenv("FWIME_STEP1");
+  if (s1 && std::atoi(s1) != 0) ctx->two_step = false;
   *out = ctx;
   return FWIME_OK;
 }
@@ -561,10 +749,12 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   Common c;
   c.d = make_dims(g, ctx->tile_x);
   const Dims &d = c.d;
-  const long per_shot = 2 * d.field * 4 + (long)geo->nrec * 64;
+  const bool two = ctx->two_step;
+  const int nf = two ? 4 : 2;                 // field buffers per shot
+  const long per_shot = nf * d.field * 4 + (long)geo->nrec * 64;
   const int S = choose_batch(ctx, per_shot, (size_t)d.field * 8, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
-  TableSet ts = build_table_set(d, geo, batches);
+  TableSet ts = build_table_set(d, geo, batches, two);
 
   float *fields = nullptr;
   Carve cv;
@@ -572,7 +762,7 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   cv.add(&c.gz, d.LZ);
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
-  cv.add(&fields, 2 * d.field * S);
+  cv.add(&fields, nf * d.field * S);
   if ((rc = arena_get(ctx, cv))) return rc;
   if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
   if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
@@ -580,10 +770,25 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   for (size_t bi = 0; bi < batches.size(); ++bi) {
     const int s0 = batches[bi].first, Sb = batches[bi].second;
     const DevTables &t = ts.dev[bi];
+    float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    if (two) {
+      HIPCHK(launch_zero(fields, 4 * d.field * Sb, st));
+      Ring4 f(fields, d.field * Sb);
+      for (int n = 0; n < g->nt - 1;) {
+        const int k = std::min(2, g->nt - 1 - n);
+        Step2Args p = step2_args(c, f, Sb, d.field, k);
+        with_src2(p, t, geo->wavelet + (long)s0 * g->nt, g, n);
+        with_rec_extract(p.a, t, out_b, g->nt, n);
+        HIPCHK(launch_step2(p, d.TX, kModePlain, st));
+        f.advance(k);
+        n += k;
+      }
+      HIPCHK(launch_gather(f.cur(), d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
+      continue;
+    }
     float *A = fields, *B = fields + d.field * Sb;
     HIPCHK(launch_zero(fields, 2 * d.field * Sb, st));
     float *cur = A, *prev = B;
-    float *out_b = data + (long)s0 * geo->nrec * g->nt;
     for (int n = 0; n < g->nt - 1; ++n) {
       StepArgs a = batch_args(c, Sb, d.field);
       a.cur = cur;
@@ -616,20 +821,25 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   const Dims &d = c.d;
   ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, nh, (nh - 1) / 2};
   const int KC = 16;
-  const long per_shot = (4 + 2L * KC) * d.field * 4 + (long)geo->nrec * 64;
+  const bool two = ctx->two_step;
+  const int nf = two ? 8 : 4;                  // u and du~ field buffers per shot
+  // two-step path: the background also carries four BF16 low-part fields
+  const long per_shot = (nf + 2L * KC + (two ? 2 : 0)) * d.field * 4 + (long)geo->nrec * 64;
   const size_t fixed = (size_t)d.field * 8 + (size_t)nh * d.nx * d.nz * 4;
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
-  TableSet ts = build_table_set(d, geo, batches);
+  TableSet ts = build_table_set(d, geo, batches, two);
 
   float *coef = nullptr, *pairs = nullptr, *t2 = nullptr, *sc = nullptr;
+  unsigned short *lows = nullptr;
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&coef, (long)nh * d.nx * d.nz);
-  cv.add(&pairs, 4 * d.field * S);
+  cv.add(&pairs, nf * d.field * S);
+  if (two) cv.add(&lows, 4 * d.field * S);
   cv.add(&t2, (long)KC * d.field * S);
   cv.add(&sc, (long)KC * d.field * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -642,6 +852,35 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
     const int s0 = batches[bi].first, Sb = batches[bi].second;
     const DevTables &t = ts.dev[bi];
     float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    if (two) {
+      HIPCHK(launch_zero(pairs, 8 * d.field * Sb, st));
+      HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
+      HIPCHK(launch_zero(sc, chunk_stride * Sb, st));
+      Ring4 fu(pairs, d.field * Sb), fw(pairs + 4 * d.field * Sb, d.field * Sb);
+      Ring4L lu(lows, d.field * Sb);
+      const float *wav_b = geo->wavelet + (long)s0 * g->nt;
+      for (int c0 = 0; c0 < g->nt - 1; c0 += KC) {
+        const int nk = std::min(KC, g->nt - 1 - c0);
+        // background in extended precision: its T2 term is the scattering source
+        rc = march2(ctx, c, fu, Sb, c0, c0 + nk, kModeT2, [&](Step2Args &p, int n, int k) {
+          p.a.t2 = t2 + (long)(n - c0) * d.field;
+          p.t2b = k == 2 ? t2 + (long)(n - c0 + 1) * d.field : nullptr;
+          p.a.t2_sstride = chunk_stride;
+          with_src2(p, t, wav_b, g, n);
+        }, st, &lu);
+        if (rc) return rc;
+        HIPCHK(launch_ext_scatter(coef, eg, +1, t2, d.field, sc, d.field, chunk_stride, Sb, nk, st));
+        rc = march2(ctx, c, fw, Sb, c0, c0 + nk, kModeDsrc, [&](Step2Args &p, int n, int k) {
+          p.a.dsrc = sc + (long)(n - c0) * d.field;
+          p.dsrc2 = k == 2 ? sc + (long)(n - c0 + 1) * d.field : nullptr;
+          p.a.dsrc_sstride = chunk_stride;
+          with_rec_extract(p.a, t, out_b, g->nt, n);
+        }, st);
+        if (rc) return rc;
+      }
+      HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
+      continue;
+    }
     float *u0 = pairs, *u1 = pairs + d.field * Sb;
     float *w0 = pairs + 2 * d.field * Sb, *w1 = pairs + 3 * d.field * Sb;
     HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
@@ -697,12 +936,15 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   const int K = seg_len(g->nt);
   const int nseg = (g->nt - 1 + K - 1) / K;
   const int R = K + 2;
-  const long per_shot = (2L + 2L * nseg + K + R) * d.field * 4 + (long)geo->nrec * 64;
+  const bool two = ctx->two_step;
+  const int nf = two ? 4 : 2;
+  // two-step path: BF16 low parts of the four work fields and the checkpoints
+  const long per_shot = (nf + 2L * nseg + K + R + (two ? 2L + nseg : 0L)) * d.field * 4 + (long)geo->nrec * 64;
   const long img = (long)nh * d.nx * d.nz;
   const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4;
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
-  TableSet ts = build_table_set(d, geo, batches);
+  TableSet ts = build_table_set(d, geo, batches, two);
 
   float *acc = nullptr, *pairs = nullptr, *ckpt = nullptr, *t2 = nullptr, *ring = nullptr;
   Carve cv;
@@ -710,9 +952,14 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   cv.add(&c.gz, d.LZ);
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  unsigned short *lows = nullptr, *ckpt_lo = nullptr;
   cv.add(&acc, img);
-  cv.add(&pairs, 2 * d.field * S);
+  cv.add(&pairs, nf * d.field * S);
   cv.add(&ckpt, 2L * nseg * d.field * S);
+  if (two) {
+    cv.add(&lows, 4 * d.field * S);
+    cv.add(&ckpt_lo, 2L * nseg * d.field * S);
+  }
   cv.add(&t2, (long)K * d.field * S);
   cv.add(&ring, (long)R * d.field * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -727,6 +974,47 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
     const int s0 = batches[bi].first, Sb = batches[bi].second;
     const DevTables &t = ts.dev[bi];
     const float *data_b = data + (long)s0 * geo->nrec * g->nt;
+    if (two) {
+      const float *wav_b = geo->wavelet + (long)s0 * g->nt;
+      auto src = [&](Step2Args &p, int n, int) { with_src2(p, t, wav_b, g, n); };
+      // forward pass (extended precision) storing (u^{n0-1}, u^{n0}) at every
+      // segment start
+      HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
+      HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
+      Ring4 fu(pairs, d.field * Sb);
+      Ring4L lu(lows, d.field * Sb);
+      for (int j = 0; j < nseg; ++j) {
+        const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1);
+        HIPCHK(launch_copy_fields(ckpt + (2L * j) * d.field, ck_stride, fu.prev(), d.field, Sb, d.field, st));
+        HIPCHK(launch_copy_fields(ckpt + (2L * j + 1) * d.field, ck_stride, fu.cur(), d.field, Sb, d.field, st));
+        HIPCHK(copy_lo(ckpt_lo + (2L * j) * d.field, ck_stride, lu.prev(), d.field, Sb, d.field, st));
+        HIPCHK(copy_lo(ckpt_lo + (2L * j + 1) * d.field, ck_stride, lu.cur(), d.field, Sb, d.field, st));
+        if (j == nseg - 1) break;   // the last segment is recomputed anyway
+        if ((rc = march2(ctx, c, fu, Sb, n0, n1, kModePlain, src, st, &lu))) return rc;
+      }
+      // backward pass: recompute the segment from its checkpoint (keeping
+      // T2 u_n), march lambda through the segment, image
+      HIPCHK(launch_zero(ring, ring_stride * Sb, st));
+      for (int j = nseg - 1; j >= 0; --j) {
+        const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
+        Ring4 wu(pairs, d.field * Sb);
+        Ring4L wl(lows, d.field * Sb);
+        HIPCHK(launch_copy_fields(wu.prev(), d.field, ckpt + (2L * j) * d.field, ck_stride, Sb, d.field, st));
+        HIPCHK(launch_copy_fields(wu.cur(), d.field, ckpt + (2L * j + 1) * d.field, ck_stride, Sb, d.field, st));
+        HIPCHK(copy_lo(wl.prev(), d.field, ckpt_lo + (2L * j) * d.field, ck_stride, Sb, d.field, st));
+        HIPCHK(copy_lo(wl.cur(), d.field, ckpt_lo + (2L * j + 1) * d.field, ck_stride, Sb, d.field, st));
+        rc = march2(ctx, c, wu, Sb, n0, n1, kModeT2, [&](Step2Args &p, int n, int k) {
+          p.a.t2 = t2 + (long)(n - n0) * d.field;
+          p.t2b = k == 2 ? t2 + (long)(n - n0 + 1) * d.field : nullptr;
+          p.a.t2_sstride = t2_stride;
+          with_src2(p, t, wav_b, g, n);
+        }, st, &wl);
+        if (rc) return rc;
+        if ((rc = march2_back_lambda(ctx, c, ring, ring_stride, R, Sb, n0, n1, t, data_b, g->nt, st))) return rc;
+        HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
+      }
+      continue;
+    }
     // forward pass storing (u^{n0-1}, u^{n0}) at every segment start
     float *p0 = pairs, *p1 = pairs + d.field * Sb;
     HIPCHK(launch_zero(pairs, 2 * d.field * Sb, st));
@@ -819,6 +1107,38 @@ int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, con
                        float *uck, float *dck, const GradWork &wk, float *drec, float *ddrec, int nrec,
                        hipStream_t st) {
   const Dims &d = c.d;
+  int rc;
+  if (ctx->two_step) {
+    HIPCHK(launch_zero(wk.pairs, 8 * d.field * Sb, st));
+    HIPCHK(launch_zero(wk.t2d, pl.seg_stride * Sb, st));
+    Ring4 fu(wk.pairs, d.field * Sb), fw(wk.pairs + 4 * d.field * Sb, d.field * Sb);
+    for (int j = 0; j < pl.nseg; ++j) {
+      const int n0 = j * pl.K, n1 = std::min(n0 + pl.K, g->nt - 1), nk = n1 - n0;
+      HIPCHK(launch_copy_fields(uck + (2L * j) * d.field, pl.ck_stride, fu.prev(), d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(uck + (2L * j + 1) * d.field, pl.ck_stride, fu.cur(), d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(dck + (2L * j) * d.field, pl.ck_stride, fw.prev(), d.field, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(dck + (2L * j + 1) * d.field, pl.ck_stride, fw.cur(), d.field, Sb, d.field, st));
+      rc = march2(ctx, c, fu, Sb, n0, n1, kModeT2, [&](Step2Args &p, int n, int k) {
+        p.a.t2 = wk.t2u + (long)(n - n0) * d.field;
+        p.t2b = k == 2 ? wk.t2u + (long)(n - n0 + 1) * d.field : nullptr;
+        p.a.t2_sstride = pl.seg_stride;
+        with_src2(p, t, wav_b, g, n);
+        with_rec_extract(p.a, t, drec, g->nt, n);
+      }, st);
+      if (rc) return rc;
+      HIPCHK(launch_ext_scatter(coef, eg, +1, wk.t2u, d.field, wk.t2d, d.field, pl.seg_stride, Sb, nk, st));
+      rc = march2(ctx, c, fw, Sb, n0, n1, kModeDsrc, [&](Step2Args &p, int n, int k) {
+        p.a.dsrc = wk.t2d + (long)(n - n0) * d.field;
+        p.dsrc2 = k == 2 ? wk.t2d + (long)(n - n0 + 1) * d.field : nullptr;
+        p.a.dsrc_sstride = pl.seg_stride;
+        with_rec_extract(p.a, t, ddrec, g->nt, n);
+      }, st);
+      if (rc) return rc;
+    }
+    HIPCHK(launch_gather(fu.cur(), d.field, t.cells, Sb, nrec, drec, g->nt, g->nt - 1, st));
+    HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, nrec, ddrec, g->nt, g->nt - 1, st));
+    return FWIME_OK;
+  }
   float *u0 = wk.pairs, *u1 = wk.pairs + d.field * Sb, *w0 = wk.pairs + 2 * d.field * Sb,
         *w1 = wk.pairs + 3 * d.field * Sb;
   HIPCHK(launch_zero(wk.pairs, 4 * d.field * Sb, st));
@@ -869,19 +1189,35 @@ int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, co
   HIPCHK(launch_zero(wk.lam, pl.ring_stride * Sb, st));
   HIPCHK(launch_zero(wk.er, pl.ring_stride * Sb, st));
   HIPCHK(launch_zero(wk.rho, pl.ring_stride * Sb, st));
+  const bool two = ctx->two_step;
+  int rc;
   for (int j = pl.nseg - 1; j >= 0; --j) {
     const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
-    float *uc = uck + (2L * j + 1) * d.field, *up = uck + (2L * j) * d.field;
-    for (int n = n0; n < n1; ++n) {
-      StepArgs a = batch_args(c, Sb, pl.ck_stride);
-      a.cur = uc;
-      a.prev = up;
-      a.out = up;
-      a.t2 = wk.t2u + (long)(n - n0) * d.field;
-      a.t2_sstride = pl.seg_stride;
-      with_src_w(a, t, wav_b, g, n);
-      HIPCHK(launch_step(a, d.TX, kModeT2, st));
-      std::swap(uc, up);
+    if (two) {
+      // u from its checkpoint, two steps per launch, keeping T2 u_n
+      Ring4 wu(wk.pairs, d.field * Sb);
+      HIPCHK(launch_copy_fields(wu.prev(), d.field, uck + (2L * j) * d.field, pl.ck_stride, Sb, d.field, st));
+      HIPCHK(launch_copy_fields(wu.cur(), d.field, uck + (2L * j + 1) * d.field, pl.ck_stride, Sb, d.field, st));
+      rc = march2(ctx, c, wu, Sb, n0, n1, kModeT2, [&](Step2Args &p, int n, int k) {
+        p.a.t2 = wk.t2u + (long)(n - n0) * d.field;
+        p.t2b = k == 2 ? wk.t2u + (long)(n - n0 + 1) * d.field : nullptr;
+        p.a.t2_sstride = pl.seg_stride;
+        with_src2(p, t, wav_b, g, n);
+      }, st);
+      if (rc) return rc;
+    } else {
+      float *uc = uck + (2L * j + 1) * d.field, *up = uck + (2L * j) * d.field;
+      for (int n = n0; n < n1; ++n) {
+        StepArgs a = batch_args(c, Sb, pl.ck_stride);
+        a.cur = uc;
+        a.prev = up;
+        a.out = up;
+        a.t2 = wk.t2u + (long)(n - n0) * d.field;
+        a.t2_sstride = pl.seg_stride;
+        with_src_w(a, t, wav_b, g, n);
+        HIPCHK(launch_step(a, d.TX, kModeT2, st));
+        std::swap(uc, up);
+      }
     }
     // t2d holds T2 du~ of the later segment outside the scatter's range: clear it
     HIPCHK(launch_zero(wk.t2d, pl.seg_stride * Sb, st));
@@ -899,26 +1235,36 @@ int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, co
       HIPCHK(launch_step(a, d.TX, kModeT2 | kModeDsrc, st));
       std::swap(wc, wp);
     }
-    for (int k = n1; k >= n0 + 1; --k) {
-      StepArgs a = batch_args(c, Sb, pl.ring_stride);
-      a.cur = wk.lam + (long)(k % R) * d.field;
-      a.prev = wk.lam + (long)((k + 1) % R) * d.field;
-      a.out = wk.lam + (long)((k - 1) % R) * d.field;
-      with_rec_inject(a, t, r, g->nt, k);
-      HIPCHK(launch_step(a, d.TX, kModePlain, st));
+    if (two) {
+      if ((rc = march2_back_lambda(ctx, c, wk.lam, pl.ring_stride, R, Sb, n0, n1, t, r, g->nt, st))) return rc;
+    } else {
+      for (int k = n1; k >= n0 + 1; --k) {
+        StepArgs a = batch_args(c, Sb, pl.ring_stride);
+        a.cur = wk.lam + (long)(k % R) * d.field;
+        a.prev = wk.lam + (long)((k + 1) % R) * d.field;
+        a.out = wk.lam + (long)((k - 1) % R) * d.field;
+        with_rec_inject(a, t, r, g->nt, k);
+        HIPCHK(launch_step(a, d.TX, kModePlain, st));
+      }
     }
     HIPCHK(launch_ext_scatter(coef, eg, -1, wk.lam, d.field, wk.er, d.field, pl.ring_stride, Sb, nk, st, R, n0, R,
                               n0));
-    for (int k = n1; k >= n0 + 1; --k) {
-      StepArgs a = batch_args(c, Sb, pl.ring_stride);
-      a.cur = wk.rho + (long)(k % R) * d.field;
-      a.prev = wk.rho + (long)((k + 1) % R) * d.field;
-      a.out = wk.rho + (long)((k - 1) % R) * d.field;
-      a.nu.em = wk.er + (long)((k - 1) % R) * d.field;
-      a.nu.e0 = wk.er + (long)(k % R) * d.field;
-      a.nu.ep = wk.er + (long)((k + 1) % R) * d.field;
-      a.nu.sstride = pl.ring_stride;
-      HIPCHK(launch_step(a, d.TX, kModeNu, st));
+    auto er_slot = [&](int k) { return wk.er + (long)(k % R) * d.field; };
+    if (two) {
+      rc = march2_back_ring(ctx, c, wk.rho, pl.ring_stride, R, Sb, n0, n1, kModeNu, [&](Step2Args &p, int k, int kk) {
+        p.a.nu = NuSource{er_slot(k - 1), er_slot(k), er_slot(k + 1), pl.ring_stride};
+        if (kk == 2) p.nu2 = NuSource{er_slot(k - 2), er_slot(k - 1), er_slot(k), pl.ring_stride};
+      }, st);
+      if (rc) return rc;
+    } else {
+      for (int k = n1; k >= n0 + 1; --k) {
+        StepArgs a = batch_args(c, Sb, pl.ring_stride);
+        a.cur = wk.rho + (long)(k % R) * d.field;
+        a.prev = wk.rho + (long)((k + 1) % R) * d.field;
+        a.out = wk.rho + (long)((k - 1) % R) * d.field;
+        a.nu = NuSource{er_slot(k - 1), er_slot(k), er_slot(k + 1), pl.ring_stride};
+        HIPCHK(launch_step(a, d.TX, kModeNu, st));
+      }
     }
     HIPCHK(launch_ext_image(wk.t2u, d.field, pl.seg_stride, wk.lam, d.field, pl.ring_stride, R, n0, Sb, nk, eg, acc,
                             st));
@@ -928,12 +1274,13 @@ int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, co
   return FWIME_OK;
 }
 
-long grad_work_per_shot(const Dims &d, const GradPlan &pl) {
-  return (4L + 2L * pl.K + 3L * pl.R) * d.field * 4;
+// the two-step path keeps four field buffers per wavefield (u and du~)
+long grad_work_per_shot(const Dims &d, const GradPlan &pl, bool two) {
+  return ((two ? 8L : 4L) + 2L * pl.K + 3L * pl.R) * d.field * 4;
 }
 
-void carve_work(Carve &cv, GradWork &wk, const Dims &d, const GradPlan &pl, int S) {
-  cv.add(&wk.pairs, 4 * d.field * S);
+void carve_work(Carve &cv, GradWork &wk, const Dims &d, const GradPlan &pl, int S, bool two) {
+  cv.add(&wk.pairs, (two ? 8 : 4) * d.field * S);
   cv.add(&wk.t2u, (long)pl.K * d.field * S);
   cv.add(&wk.t2d, (long)pl.K * d.field * S);
   cv.add(&wk.lam, (long)pl.R * d.field * S);
@@ -989,11 +1336,12 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   const GradPlan pl = grad_plan(d, g->nt);
   const long img = (long)nh * d.nx * d.nz;
   const long nrt = (long)geo->nrec * g->nt;
-  const long per_shot = grad_work_per_shot(d, pl) + 2 * pl.ck_stride * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const long per_shot =
+      grad_work_per_shot(d, pl, ctx->two_step) + 2 * pl.ck_stride * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
   const size_t fixed = (size_t)d.field * 12 + (size_t)img * 12;
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
-  TableSet ts = build_table_set(d, geo, batches);
+  TableSet ts = build_table_set(d, geo, batches, ctx->two_step);
 
   float *coef = nullptr, *acc = nullptr, *imgs = nullptr, *gacc = nullptr, *uck = nullptr, *dck = nullptr,
         *drec = nullptr, *ddrec = nullptr, *e2d2 = nullptr;
@@ -1012,7 +1360,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   cv.add(&gacc, d.field);
   cv.add(&uck, pl.ck_stride * S);
   cv.add(&dck, pl.ck_stride * S);
-  carve_work(cv, wk, d, pl, S);
+  carve_work(cv, wk, d, pl, S, ctx->two_step);
   cv.add(&drec, nrt * S);
   cv.add(&ddrec, nrt * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -1082,11 +1430,11 @@ int fwime_forward_tape(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   const long img = (long)nh * d.nx * d.nz;
   const long nrt = (long)geo->nrec * g->nt;
   // checkpoints of every shot live in the tape; working fields in the arena
-  const long per_shot = grad_work_per_shot(d, pl) + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const long per_shot = grad_work_per_shot(d, pl, ctx->two_step) + 2 * nrt * 4 + (long)geo->nrec * 64;
   const size_t tape_fixed = (size_t)(2 * pl.ck_stride * 4) * geo->nshots;
   const int S = choose_batch(ctx, per_shot, tape_fixed + (size_t)d.field * 8, geo->nshots);
   tp->batches = split_batches(geo->nshots, S);
-  tp->ts = build_table_set(d, geo, tp->batches);
+  tp->ts = build_table_set(d, geo, tp->batches, ctx->two_step);
 
   Carve tc;   // tape memory
   tc.add(&tp->V, d.field);
@@ -1140,7 +1488,7 @@ int fwime_forward_tape(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   float *drec = nullptr, *ddrec = nullptr;
   GradWork wk;
   Carve cv;
-  carve_work(cv, wk, d, pl, S);
+  carve_work(cv, wk, d, pl, S, ctx->two_step);
   cv.add(&drec, nrt * S);
   cv.add(&ddrec, nrt * S);
   if ((rc = arena_get(ctx, cv))) return fail(rc);
@@ -1192,7 +1540,7 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
   cv.add(&acc, img);
   cv.add(&imgs, img);
   cv.add(&gacc, d.field);
-  carve_work(cv, wk, d, pl, S);
+  carve_work(cv, wk, d, pl, S, ctx->two_step);
   if ((rc = arena_get(ctx, cv))) return rc;
   Common c;
   c.d = d;
@@ -1222,25 +1570,33 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
 namespace {
 
 // ---------------------------------------------------------------------------
-// Many modeling jobs of different grids in one launch per time step.
+// Many modeling jobs of different grids in one launch per time step (two
+// time steps per launch by default).
 //
-// Every job keeps its own padded velocity, taper, receiver tables and two
-// field buffers per shot; a device array of BatchJob descriptors lets one
-// k_step_multi launch advance all of them.  The time loop is recorded once as
-// a graph of G (stencil, step-counter bump) node pairs on a private capture
-// stream and replayed on the caller's stream until the longest job is done.
+// Every job keeps its own padded velocity, taper, receiver tables and four
+// (two with one step per launch) field buffers per shot; a device array of
+// job descriptors lets one k_step2_multi (k_step_multi) launch advance all of
+// them.  The time loop is recorded once as a graph of G (stencil, step-counter
+// bump) node pairs on a private capture stream and replayed on the caller's
+// stream until the longest job is done.
 // The tile width comes from an autotuner: for a batch signature not seen
 // before, each candidate width is timed on scratch fields (zero initial
 // state, real velocity and sources) and the fastest is cached in the context.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
+  bool two = false;              // two time steps per launch (k_step2_multi)
   std::vector<int> order;        // position k in the launch -> caller's job index
   std::vector<Common> com;       // per position
   std::vector<TableSet> ts;
-  std::vector<BatchJob> jobs;
+  std::vector<BatchJob> jobs;    // one-step descriptors
+  std::vector<BatchJob2> jobs2;  // two-step descriptors
   std::vector<int> prefix;       // tiles before position k
   int total = 0;
   int nt_max = 0;
+  int stride() const { return two ? 2 : 1; }
+  // launches until the longest job has sampled its last time
+  long launches() const { return two ? (nt_max - 1) / 2 + 1 : nt_max; }
+  int nt_at(int k) const { return two ? jobs2[k].nt : jobs[k].nt; }
 };
 
 // Jobs are laid out in order of decreasing time-axis length, so the jobs still
@@ -1248,14 +1604,15 @@ struct BatchPlan {
 // prefix's last tile.
 int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, BatchPlan &bp,
                std::vector<std::pair<void **, size_t>> *) {
-  (void)ctx;
+  bp.two = ctx->two_step;
   bp.order.resize(njobs);
   for (int j = 0; j < njobs; ++j) bp.order[j] = j;
   std::stable_sort(bp.order.begin(), bp.order.end(),
                    [&](int a, int b) { return jobs[a].grid.nt > jobs[b].grid.nt; });
   bp.com.assign(njobs, Common());
   bp.ts.clear();
-  bp.jobs.assign(njobs, BatchJob());
+  bp.jobs.assign(bp.two ? 0 : njobs, BatchJob());
+  bp.jobs2.assign(bp.two ? njobs : 0, BatchJob2());
   bp.prefix.assign(njobs + 1, 0);
   bp.total = 0;
   bp.nt_max = 0;
@@ -1263,11 +1620,18 @@ int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, Bat
     const int j = bp.order[k];
     bp.com[k].d = make_dims(&jobs[j].grid, tx);
     const Dims &d = bp.com[k].d;
-    bp.ts.push_back(build_table_set(d, &jobs[j].geom, {{0, jobs[j].geom.nshots}}));
-    bp.jobs[k].tile_begin = bp.total;
-    bp.jobs[k].t0 = 0;
-    bp.jobs[k].nt = jobs[j].grid.nt;
-    bp.total += d.ntz * d.ntx * jobs[j].geom.nshots;
+    bp.ts.push_back(build_table_set(d, &jobs[j].geom, {{0, jobs[j].geom.nshots}}, bp.two));
+    if (bp.two) {
+      bp.jobs2[k].tile_begin = bp.total;
+      bp.jobs2[k].t0 = 0;
+      bp.jobs2[k].nt = jobs[j].grid.nt;
+      bp.total += d.ntz2 * d.ntx * jobs[j].geom.nshots;
+    } else {
+      bp.jobs[k].tile_begin = bp.total;
+      bp.jobs[k].t0 = 0;
+      bp.jobs[k].nt = jobs[j].grid.nt;
+      bp.total += d.ntz * d.ntx * jobs[j].geom.nshots;
+    }
     bp.prefix[k + 1] = bp.total;
     bp.nt_max = std::max(bp.nt_max, jobs[j].grid.nt);
   }
@@ -1277,14 +1641,25 @@ int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, Bat
 // tiles of the jobs whose time index n is still within [0, nt - 1]
 int batch_active_tiles(const BatchPlan &bp, long n) {
   int k = 0;
-  while (k < (int)bp.jobs.size() && n <= bp.jobs[k].nt - 1) ++k;
+  const int nj = (int)bp.order.size();
+  while (k < nj && n <= bp.nt_at(k) - 1) ++k;
   return bp.prefix[k];
 }
 
-int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, BatchPlan &bp, BatchJob **djobs,
+// one multi-job launch (one or two time steps) and the step-counter bump
+hipError_t batch_launch(const BatchPlan &bp, const void *djobs, int tiles, int *dstep, int tx, hipStream_t st) {
+  const int nj = (int)bp.order.size();
+  hipError_t e = bp.two ? launch_step2_multi((const BatchJob2 *)djobs, nj, tiles, dstep, tx, st)
+                        : launch_step_multi((const BatchJob *)djobs, nj, tiles, dstep, tx, st);
+  if (e != hipSuccess) return e;
+  return launch_bump(dstep, bp.stride(), st);
+}
+
+int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, BatchPlan &bp, void **djobs,
                           int **dstep, hipStream_t st) {
   Carve cv;
   std::vector<float *> fields(njobs);
+  const int nf = bp.two ? 4 : 2;
   for (int k = 0; k < njobs; ++k) {
     const int j = bp.order[k];
     const Dims &d = bp.com[k].d;
@@ -1292,9 +1667,11 @@ int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, 
     cv.add(&bp.com[k].gz, d.LZ);
     cv.add(&bp.com[k].gx, d.NX + kGxPad);
     cv.add(&bp.com[k].tables, table_set_ints(bp.ts[k]) + 64 * 8);
-    cv.add(&fields[k], 2 * d.field * jobs[j].geom.nshots);
+    cv.add(&fields[k], nf * d.field * jobs[j].geom.nshots);
   }
-  cv.add(djobs, njobs);
+  const size_t jb_bytes = bp.two ? sizeof(BatchJob2) : sizeof(BatchJob);
+  char *dj = nullptr;
+  cv.add(&dj, jb_bytes * njobs);
   cv.add(dstep, 1);
   int rc = arena_get(ctx, cv);
   if (rc) return rc;
@@ -1304,16 +1681,28 @@ int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, 
     const int S = jobs[j].geom.nshots;
     if ((rc = upload_tables(ctx, bp.ts[k], bp.com[k].tables, st))) return rc;
     if ((rc = setup_common(ctx, bp.com[k], &jobs[j].grid, jobs[j].vel, st))) return rc;
-    HIPCHK(launch_zero(fields[k], 2 * d.field * S, st));
-    BatchJob &bj = bp.jobs[k];
-    bj.a = batch_args(bp.com[k], S, d.field);
-    with_src(bj.a, bp.ts[k].dev[0], &jobs[j].geom, &jobs[j].grid, 0, 0);
-    with_rec_extract(bj.a, bp.ts[k].dev[0], jobs[j].data, jobs[j].grid.nt, 0);
-    bj.bufA = fields[k];
-    bj.bufB = fields[k] + d.field * S;
+    HIPCHK(launch_zero(fields[k], nf * d.field * S, st));
+    const DevTables &t = bp.ts[k].dev[0];
+    if (bp.two) {
+      BatchJob2 &bj = bp.jobs2[k];
+      bj.p.a = batch_args(bp.com[k], S, d.field);
+      bj.p.a.ntz = d.ntz2;
+      with_src2(bj.p, t, jobs[j].geom.wavelet, &jobs[j].grid, 0);
+      with_rec_extract(bj.p.a, t, jobs[j].data, jobs[j].grid.nt, 0);
+      for (int q = 0; q < 4; ++q) bj.buf[q] = fields[k] + q * d.field * S;
+    } else {
+      BatchJob &bj = bp.jobs[k];
+      bj.a = batch_args(bp.com[k], S, d.field);
+      with_src(bj.a, t, &jobs[j].geom, &jobs[j].grid, 0, 0);
+      with_rec_extract(bj.a, t, jobs[j].data, jobs[j].grid.nt, 0);
+      bj.bufA = fields[k];
+      bj.bufB = fields[k] + d.field * S;
+    }
   }
-  HIPCHK(hipMemcpyAsync(*djobs, bp.jobs.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice, st));
+  const void *host = bp.two ? (const void *)bp.jobs2.data() : (const void *)bp.jobs.data();
+  HIPCHK(hipMemcpyAsync(dj, host, jb_bytes * njobs, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+  *djobs = dj;
   return FWIME_OK;
 }
 
@@ -1338,14 +1727,16 @@ int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStre
   int rc = FWIME_OK;
   for (int tx : cand) {
     BatchPlan bp;
-    BatchJob *dj = nullptr;
+    void *dj = nullptr;
     int *dstep = nullptr;
     if ((rc = batch_plan(ctx, njobs, jobs, tx, bp, nullptr))) break;
+    if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) break;
     // scratch run: receivers off, time kept below every job's last step
     for (auto &jb : bp.jobs) jb.a.ext.ptr = nullptr;
-    if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) break;
-    for (int k = 0; k < njobs; ++k) bp.jobs[k].a.ext.ptr = nullptr;
-    if (hipMemcpyAsync(dj, bp.jobs.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice, st) != hipSuccess ||
+    for (auto &jb : bp.jobs2) jb.p.a.ext.ptr = nullptr;
+    const void *host = bp.two ? (const void *)bp.jobs2.data() : (const void *)bp.jobs.data();
+    const size_t jb_bytes = bp.two ? sizeof(BatchJob2) : sizeof(BatchJob);
+    if (hipMemcpyAsync(dj, host, jb_bytes * njobs, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemsetAsync(dstep, 0, sizeof(int), st) != hipSuccess) {
       rc = set_err(ctx, FWIME_EHIP, "autotune setup failed");
       break;
@@ -1353,8 +1744,7 @@ int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStre
     const int warm = 2, timed = 8;
     for (int i = 0; i < warm + timed; ++i) {
       if (i == warm) (void)hipEventRecord(e0, st);
-      if (launch_step_multi(dj, njobs, bp.total, dstep, tx, st) != hipSuccess ||
-          launch_bump(dstep, 1, st) != hipSuccess) {
+      if (batch_launch(bp, dj, bp.total, dstep, tx, st) != hipSuccess) {
         rc = set_err(ctx, FWIME_EHIP, "autotune launch failed");
         break;
       }
@@ -1412,7 +1802,7 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   ctx->last_batch_tile = tx;
 
   BatchPlan bp;
-  BatchJob *dj = nullptr;
+  void *dj = nullptr;
   int *dstep = nullptr;
   if ((rc = batch_plan(ctx, njobs, jobs, tx, bp, nullptr))) return rc;
   if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) return rc;
@@ -1423,11 +1813,9 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   // only (launch latency is negligible next to the step).  Small batches:
   // replay a captured graph of G full-width steps (idle jobs exit at once).
   const bool use_graph = !std::getenv("FWIME_NO_GRAPH") && bp.total <= kGraphMaxTiles;
+  const long L = bp.launches();
   if (!use_graph) {
-    for (long n = 0; n < bp.nt_max; ++n) {
-      HIPCHK(launch_step_multi(dj, njobs, batch_active_tiles(bp, n), dstep, tx, st));
-      HIPCHK(launch_bump(dstep, 1, st));
-    }
+    for (long i = 0; i < L; ++i) HIPCHK(batch_launch(bp, dj, batch_active_tiles(bp, i * bp.stride()), dstep, tx, st));
     return FWIME_OK;
   }
   hipGraph_t graph = nullptr;
@@ -1437,10 +1825,7 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   if (!ctx->capture) HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
   hipError_t cap = hipSuccess;
-  for (int i = 0; i < G && cap == hipSuccess; ++i) {
-    cap = launch_step_multi(dj, njobs, bp.total, dstep, tx, ctx->capture);
-    if (cap == hipSuccess) cap = launch_bump(dstep, 1, ctx->capture);
-  }
+  for (int i = 0; i < G && cap == hipSuccess; ++i) cap = batch_launch(bp, dj, bp.total, dstep, tx, ctx->capture);
   hipError_t endc = hipStreamEndCapture(ctx->capture, &graph);
   if (cap != hipSuccess || endc != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -1450,7 +1835,7 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
     (void)hipGraphDestroy(graph);
     return set_err(ctx, FWIME_EHIP, "graph instantiation failed");
   }
-  const long replays = (bp.nt_max + G - 1) / G;
+  const long replays = (L + G - 1) / G;
   hipError_t le = hipSuccess;
   for (long r = 0; r < replays && le == hipSuccess; ++r) le = hipGraphLaunch(exec, st);
   ctx->graph = graph;          // kept until the replays have certainly finished
@@ -1467,12 +1852,13 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
   const long nrt = (long)nrec * g->nt * 4;
   const GradPlan pl = grad_plan(d, g->nt);
   long per_shot = 0, fixed = fb + (long)(d.NX + d.LZ) * 4;
+  // field buffers of the two-step path (the larger of the two paths)
   switch (op) {
-    case FWIME_OP_MODEL: per_shot = 2 * fb; break;
-    case FWIME_OP_BORN_FWD: per_shot = (4 + 2 * 16) * fb; fixed += img; break;
-    case FWIME_OP_BORN_ADJ: per_shot = (2 + 2L * pl.nseg + pl.K + pl.R) * fb; fixed += img; break;
+    case FWIME_OP_MODEL: per_shot = 4 * fb; break;
+    case FWIME_OP_BORN_FWD: per_shot = (8 + 2 * 16 + 2) * fb; fixed += img; break;
+    case FWIME_OP_BORN_ADJ: per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + pl.nseg) * fb; fixed += img; break;
     case FWIME_OP_GRADIENT:
-      per_shot = grad_work_per_shot(d, pl) + 2 * pl.ck_stride * 4 + 2 * nrt;
+      per_shot = grad_work_per_shot(d, pl, true) + 2 * pl.ck_stride * 4 + 2 * nrt;
       fixed += 3 * img;
       break;
     default: return FWIME_EINVAL;
