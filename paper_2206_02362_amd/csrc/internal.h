@@ -12,6 +12,32 @@ constexpr int kR = 4;          // stencil radius (8th-order second derivative)
 constexpr int kWaves = 4;      // wavefronts per stencil workgroup
 constexpr int kTZ2 = 56;       // output rows per tile of the two-step kernel (64 lanes = rows z0-4 .. z0+59)
 
+// Order of the stencil tiles of one launch (S shots, ntz x ntx tiles each).
+// Columns of tiles are taken kTileGroupX x-strips at a time; inside a group
+// one shot's tiles come together (z fastest), then the next shot's tiles of
+// the same group.  Consecutive workgroups are thus spatial neighbours of one
+// shot (their shared halo columns and rows are still in L2) and the velocity
+// tile of the group is reused by every shot while it is cached.
+constexpr int kTileGroupX = 4;
+
+__host__ __device__ inline long tile_index(int txi, int tzi, int s, int ntz, int ntx, int S) {
+  const int xg = txi / kTileGroupX, txl = txi - xg * kTileGroupX;
+  const int ngx = min(kTileGroupX, ntx - xg * kTileGroupX);
+  return (long)xg * kTileGroupX * ntz * S + ((long)s * ngx + txl) * ntz + tzi;
+}
+
+__host__ __device__ inline void tile_coords(int logical, int ntz, int ntx, int S, int &txi, int &tzi, int &s) {
+  const int per_group = kTileGroupX * ntz * S;
+  const int xg = logical / per_group;
+  const int rem = logical - xg * per_group;
+  const int ngx = min(kTileGroupX, ntx - xg * kTileGroupX);
+  s = rem / (ngx * ntz);
+  const int r2 = rem - s * ngx * ntz;
+  const int txl = r2 / ntz;
+  tzi = r2 - txl * ntz;
+  txi = xg * kTileGroupX + txl;
+}
+
 // Per-tile injection list (compressed rows over tile*kWaves + wave).
 // An entry {(j << 6) | lz, idx} adds  val[idx * stride_idx + t] * scale  to the
 // source term of the cell in column j (of the wave's columns) and row lz.
@@ -168,9 +194,12 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
                               int in_ring = 0, int in_first = 0, int out_ring = 0, int out_first = 0);
 
 // acc(z,y,h) += sum_s sum_{n<nk} a_n(z, y-h) b_n(z, y+h).  Slot n of a is a + n*a_slot;
-// slot of b is ring index (b_first + n) % b_ring.
+// slot of b is ring index (b_first + n) % b_ring.  parts: scratch for up to
+// kImageGroups partial images ([kImageGroups][nh][nx][nz]) that let the slots
+// be split over more workgroups; null keeps one group.
+constexpr int kImageGroups = 4;
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
-                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc,
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc, float *parts,
                             hipStream_t st);
 
 // gacc(x,z) += sum_s sum_{n<nk} (t2u_n + t2d_n) lam_n + t2u_n rho_n

@@ -307,8 +307,8 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
 // Extended imaging condition:
 //   acc(z, y, h) += sum_s sum_n a_n(z, y - h) b_n(z, y + h)
 // A wavefront owns a YT x HT tile of (y, h) for 64 depths; per time slot it
-// loads YT + HT - 1 source-side and receiver-side columns into registers and
-// performs YT * HT multiply-adds.
+// reads YT + HT - 1 source-side and receiver-side columns and performs
+// YT * HT multiply-adds.
 // ---------------------------------------------------------------------------
 constexpr int kImgYT = 8;
 constexpr int kImgHT = 8;
@@ -317,69 +317,15 @@ struct ImageArgs {
   const float *a;
   const float *b;
   float *acc;
+  float *parts;        // groups > 1: partial images, one per slot group
   long a_slot, b_slot, a_sstride, b_sstride;
   int b_ring, b_first;
   int nshots, nk;
   int nz, nx, nb, NX, LZ, nh, H;
   int nzs, nyt, nht;
+  int nhb;             // offset blocks (blockIdx.y = group * nhb + offset block)
+  int groups, slots_per_group;
 };
-
-__global__ void __launch_bounds__(256) k_ext_image(const ImageArgs p) {
-  constexpr int NA = kImgYT + kImgHT - 1;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int total = p.nzs * p.nyt * p.nht;
-  if (wave >= total) return;
-  const int zs = wave % p.nzs;
-  const int r = wave / p.nzs;
-  const int yt = r % p.nyt;
-  const int ht = r / p.nyt;
-  const int ya = yt * kImgYT;
-  const int ib0 = -p.H + ht * kImgHT;
-  const int z = zs * 64 + lane;
-  const bool zin = z < p.nz;
-  const int zp = p.nb + z;
-  const int ca = p.nb + ya - ib0 - (kImgHT - 1);   // padded column of a[0]
-  const int cbb = p.nb + ya + ib0;                  // padded column of b[0]
-
-  float acc[kImgYT][kImgHT];
-#pragma unroll
-  for (int yy = 0; yy < kImgYT; ++yy)
-#pragma unroll
-    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
-
-  for (int s = 0; s < p.nshots; ++s) {
-    for (int n = 0; n < p.nk; ++n) {
-      const float *an = p.a + (long)s * p.a_sstride + (long)n * p.a_slot;
-      const float *bn = p.b + (long)s * p.b_sstride + (long)((p.b_first + n) % p.b_ring) * p.b_slot;
-      float va[NA], vb[NA];
-#pragma unroll
-      for (int m = 0; m < NA; ++m) {
-        const int xa = ca + m;
-        const int xb = cbb + m;
-        va[m] = (zin && (unsigned)xa < (unsigned)p.NX) ? an[(long)xa * p.LZ + zp] : 0.f;
-        vb[m] = (zin && (unsigned)xb < (unsigned)p.NX) ? bn[(long)xb * p.LZ + zp] : 0.f;
-      }
-#pragma unroll
-      for (int yy = 0; yy < kImgYT; ++yy)
-#pragma unroll
-        for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
-    }
-  }
-  if (!zin) return;
-#pragma unroll
-  for (int yy = 0; yy < kImgYT; ++yy) {
-    const int y = ya + yy;
-    if (y >= p.nx) continue;
-#pragma unroll
-    for (int hh = 0; hh < kImgHT; ++hh) {
-      const int ih = ib0 + hh;
-      if (ih > p.H) continue;
-      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
-      p.acc[o] += acc[yy][hh];
-    }
-  }
-}
 
 // LDS-staged, pipelined version.  A workgroup of 16 wavefronts covers one
 // depth strip, YB = 8 NYT model columns and 8 NHT offsets of the group
@@ -388,6 +334,10 @@ __global__ void __launch_bounds__(256) k_ext_image(const ImageArgs p) {
 // receiver-side window (y + h), each YB + 8 NHT - 1 columns wide, are staged in
 // a 3-deep LDS ring: slot q is consumed while slot q + 1 is written from
 // registers and the loads of slot q + 2 are in flight (one barrier per slot).
+// With several slot groups (enough workgroups to fill the device when the
+// tiles alone do not), group g stores its partial image and a second kernel
+// adds the partials to the accumulator in group order, so the result does not
+// depend on scheduling.
 template <int NYT, int NHT>
 __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   constexpr int NA = kImgYT + kImgHT - 1;
@@ -407,7 +357,8 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   const int zs = tile % p.nzs;
   const int yblk = tile / p.nzs;
   const int yb = yblk * YB;
-  const int hlo = -p.H + HSPAN * blockIdx.y;
+  const int grp = blockIdx.y / p.nhb;
+  const int hlo = -p.H + HSPAN * (blockIdx.y - grp * p.nhb);
   const int hhi = min(p.H, hlo + HSPAN - 1);
   const int z = zs * 64 + lane;
   const bool zin = z < p.nz;
@@ -428,7 +379,8 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
 #pragma unroll
     for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
 
-  const int total = p.nshots * p.nk;
+  const int q0 = grp * p.slots_per_group;
+  const int total = min(p.nshots * p.nk, q0 + p.slots_per_group);
   // thread (w, lane) stages rows w + 16 r at depth lane; out-of-grid columns
   // read as zero through the bounds-checked buffer loads
   const unsigned slot_bytes = (unsigned)((long)p.NX * p.LZ * 4);
@@ -454,15 +406,14 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
       if (c < ROWS) ring[rbuf][c * 64 + lane] = pre[r];
     }
   };
-  if (total <= 0) return;
   float p1[PER], p2[PER];
-  fetch(0, p1);
+  fetch(q0, p1);
   put(0, p1);
-  fetch(1, p1);
-  fetch(2, p2);
+  fetch(q0 + 1, p1);
+  fetch(q0 + 2, p2);
   __syncthreads();
   int rb = 0;
-  for (int q = 0; q < total; ++q) {
+  for (int q = q0; q < total; ++q) {
     if (active) {
       const float *win = ring[rb];
       float va[NA], vb[NA];
@@ -494,19 +445,30 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
       const int ih = h0 + hh;
       if (ih > hhi) continue;
       const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
-      p.acc[o] += acc[yy][hh];
+      if (p.groups > 1) p.parts[(long)grp * p.nh * p.nx * p.nz + o] = acc[yy][hh];
+      else p.acc[o] += acc[yy][hh];
     }
   }
 }
 
+// acc += sum over g of parts[g], in group order
+__global__ void k_image_reduce(float *acc, const float *parts, long n, int groups) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float s = parts[i];
+    for (int g = 1; g < groups; ++g) s += parts[(long)g * n + i];
+    acc[i] += s;
+  }
+}
+
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
-                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc,
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc, float *parts,
                             hipStream_t st) {
   if (nk <= 0 || nshots <= 0) return hipSuccess;
   ImageArgs p;
   p.a = a;
   p.b = b;
   p.acc = acc;
+  p.parts = parts;
   p.a_slot = a_slot;
   p.b_slot = b_slot;
   p.a_sstride = a_sstride;
@@ -523,15 +485,28 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.nh = g.nh;
   p.H = g.H;
   p.nzs = (g.nz + 63) / 64;
-  if (g.nh > 16) {
-    const int ntile = p.nzs * ((g.nx + 31) / 32);
-    const dim3 grid((unsigned)((ntile + 7) / 8 * 8), (unsigned)((g.nh + 31) / 32));
-    k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
-  } else {
-    const int ntile = p.nzs * ((g.nx + 63) / 64);
-    const dim3 grid((unsigned)((ntile + 7) / 8 * 8), 1u);
-    k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
-  }
+  const bool wide = g.nh > 16;
+  const int ntile = p.nzs * ((g.nx + (wide ? 31 : 63)) / (wide ? 32 : 64));
+  const int nblk = (ntile + 7) / 8 * 8;
+  p.nhb = wide ? (g.nh + 31) / 32 : 1;
+  // one workgroup fits a CU: split the slots into groups until there are
+  // about eight workgroups per CU, so the last round of workgroups leaves
+  // little of the device idle (at most kImageGroups partial images)
+  const int total = nshots * nk;
+  const int want = (2048 + nblk * p.nhb - 1) / (nblk * p.nhb);
+  int groups = parts ? std::min(kImageGroups, std::max(1, want)) : 1;
+  groups = std::min(groups, total);
+  p.slots_per_group = (total + groups - 1) / groups;
+  p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
+  const dim3 grid((unsigned)nblk, (unsigned)(p.nhb * p.groups));
+  if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
+  else k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.groups == 1) return e;
+  const long n = (long)g.nh * g.nx * g.nz;
+  long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_image_reduce<<<(unsigned)blocks, 256, 0, st>>>(acc, parts, n, p.groups);
   return hipGetLastError();
 }
 

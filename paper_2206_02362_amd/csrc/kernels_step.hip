@@ -19,9 +19,9 @@
 // barrier, so their latency overlaps the tile load.
 //
 // Workgroups are mapped XCD-aware: hardware workgroup b runs on XCD b % 8, and
-// the logical tile order (x-chunk, z-strip, shot) is split into 8 contiguous
-// ranges, one per XCD, so halo columns and the shared V tile are re-read from
-// the XCD's own L2.
+// the logical tile order (tile_index: groups of x-strips, one shot at a time
+// inside a group) is split into 8 contiguous ranges, one per XCD, so halo
+// columns and the shared V tile are re-read from the XCD's own L2.
 //
 // Point sources / receiver injections come as per-(tile, wave) lists sorted by
 // column, consumed by a wave-uniform loop inside the column march.  Receiver
@@ -38,8 +38,8 @@ struct StepTile {
   float v[HC][HZ];
 };
 
-// One 64 x TX tile of one shot.  `logical` enumerates (x-chunk, z-strip, shot)
-// with the shot fastest.  With extract_only the kernel only samples the
+// One 64 x TX tile of one shot; `logical` is the tile's position in the
+// launch order of tile_index.  With extract_only the kernel only samples the
 // receivers of the input field (the last time sample of a job).
 template <int TX, int MODE>
 __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTile<TX> &sh, bool extract_only) {
@@ -47,10 +47,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
   constexpr int HC = TX + 2 * kR;
   constexpr int HZ = kTZ + 2 * kR;
   auto &tile = sh.v;
-  const int tile_id = logical / a.nshots;
-  const int s = logical - tile_id * a.nshots;
-  const int txi = tile_id / a.ntz;
-  const int tzi = tile_id - txi * a.ntz;
+  int txi, tzi, s;
+  tile_coords(logical, a.ntz, a.ntx, a.nshots, txi, tzi, s);
   const int z0 = tzi * kTZ;
   const int x0 = txi * TX;
   const int NZ = a.NZ, NX = a.NX, LZ = a.LZ;

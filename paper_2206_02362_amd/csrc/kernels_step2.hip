@@ -66,8 +66,47 @@ __device__ __forceinline__ float df_update(float g, float c, float cl, float pv,
   return hi;
 }
 
-// One 56 x TX tile of one shot; `logical` enumerates (x-chunk, z-strip, shot)
-// with the shot fastest.  extract_only: only sample u^n.  ext_next: sample
+// Raw buffer access: per-lane 32-bit byte offset (the row) plus a wave-uniform
+// byte offset (the column) that lives in a scalar register, so no 64-bit
+// address arithmetic is spent per access.  Every access below is guarded, so
+// the hardware range check is not relied on.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ unsigned short ld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+}
+__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, unsigned short v, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
+}
+
+// Adds a wavefront's point sources to its per-column source registers, in list
+// order (the order in which the one-step kernel adds them).  Done before the
+// column march so that the march itself has no loop inside.
+template <int W>
+__device__ __forceinline__ void fold_sources(const Inject &inj, int logical, int w, int lane, float (&src)[W]) {
+  if (inj.ptr == nullptr) return;
+  const int e1 = inj.ptr[logical * kWaves + w + 1];
+  for (int e = inj.ptr[logical * kWaves + w]; e < e1; ++e) {   // wave-uniform
+    const int2 en = inj.ent[e];
+    const float val = inj.val[(long)en.y * inj.stride_idx + inj.t] * inj.scale;
+    const int j = en.x >> 6;
+    if ((en.x & 63) == lane) {
+#pragma unroll
+      for (int jj = 0; jj < W; ++jj)
+        if (jj == j) src[jj] += val;
+    }
+  }
+}
+
+// One 56 x TX tile of one shot; `logical` is the tile's position in the
+// launch order of tile_index.  extract_only: only sample u^n.  ext_next: sample
 // u^{n+1} after the first step even when no second step follows.
 template <int TX, int MODE>
 __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
@@ -81,19 +120,20 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   constexpr int ROWS = Step2Tile<TX>::ROWS;
   constexpr int W1 = (TX + 8) / kWaves;      // step-1 columns per wave
   constexpr int W2 = TX / kWaves;            // step-2 columns per wave
-  static_assert((TX + 8) % kWaves == 0 && TX % kWaves == 0, "tile width");
+  static_assert((TX + 8) % kWaves == 0 && TX % kWaves == 0 && C0 % kWaves == 0, "tile width");
   const StepArgs &a = p.a;
-  const int tile_id = logical / a.nshots;
-  const int s = logical - tile_id * a.nshots;
-  const int txi = tile_id / a.ntz;
-  const int tzi = tile_id - txi * a.ntz;
+  int txi, tzi, s;
+  tile_coords(logical, a.ntz, a.ntx, a.nshots, txi, tzi, s);
   const int z0 = tzi * kTZ2;
   const int x0 = txi * TX;
   const int NZ = a.NZ, NX = a.NX, LZ = a.LZ;
+  const int CB = LZ * 4;                      // bytes per column
+  const unsigned FB = (unsigned)NX * (unsigned)CB;
 
   const long soff = (long)s * a.sstride;
-  const float *u0g = a.cur + soff;
-  const float *um = a.prev + soff;
+  const auto r_cur = rsrc(a.cur + soff, FB);
+  const auto r_prev = rsrc(a.prev + soff, FB);
+  const auto r_V = rsrc(a.V, FB);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -101,71 +141,102 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   const int z = z0 - kR + lane;
   const bool zin = z >= 0 && z < NZ;
   const bool zown = lane >= kR && lane < kR + kTZ2;
+  const int vz = z * 4;                       // byte offset of this lane's row
   const int xs1 = x0 - kR + w * W1;          // first step-1 column of this wave
   const int xs2 = x0 + w * W2;               // first step-2 column
 
   // Own-row operands of both steps; their latency hides behind the tile load.
-  float pv[W1], vv1[W1], vv2[W2], ds1[W1], ds2[W2], pl[W1];
+  float pv[W1], vv1[W1], vv2[W2], ds1[W1], ds2[W2], pl[W1], gx1[W1], gx2[W2];
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t r_ds1, r_ds2, r_lprev, r_lcur;
+  if constexpr (DS) {
+    r_ds1 = rsrc(a.dsrc + (long)s * a.dsrc_sstride, FB);
+    r_ds2 = rsrc(p.two ? p.dsrc2 + (long)s * a.dsrc_sstride : a.dsrc, FB);
+  }
+  if constexpr (DF) {
+    r_lprev = rsrc(p.lo_prev + soff, FB / 2);
+    r_lcur = rsrc(p.lo_cur + soff, FB / 2);
+  }
 #pragma unroll
   for (int j = 0; j < W1; ++j) {
     const int x = xs1 + j;
-    const bool in = zin && x >= 0 && x < NX;
-    const long idx = (long)x * LZ + z;
-    pv[j] = in ? um[idx] : 0.f;
-    pl[j] = 0.f;
-    if constexpr (DF) pl[j] = in ? bf16_f32(p.lo_prev[soff + idx]) : 0.f;
-    vv1[j] = in ? a.V[idx] : 0.f;
-    ds1[j] = 0.f;
-    if constexpr (DS) ds1[j] = in ? a.dsrc[(long)s * a.dsrc_sstride + idx] : 0.f;
+    const bool xin = x >= 0 && x < NX;
+    pv[j] = vv1[j] = ds1[j] = pl[j] = 0.f;
+    gx1[j] = a.gx[xin ? x : 0];
+    if (xin && zin) {
+      pv[j] = ld(r_prev, vz, x * CB);
+      vv1[j] = ld(r_V, vz, x * CB);
+      if constexpr (DS) ds1[j] = ld(r_ds1, vz, x * CB);
+      if constexpr (DF) pl[j] = bf16_f32(ld16(r_lprev, z * 2, x * (CB / 2)));
+    }
   }
 #pragma unroll
   for (int j = 0; j < W2; ++j) {
     const int x = xs2 + j;
-    const bool in = zin && x < NX;
-    const long idx = (long)x * LZ + z;
-    vv2[j] = in ? a.V[idx] : 0.f;
-    ds2[j] = 0.f;
-    if constexpr (DS) ds2[j] = (in && p.two) ? p.dsrc2[(long)s * a.dsrc_sstride + idx] : 0.f;
+    const bool xin = x < NX;
+    vv2[j] = ds2[j] = 0.f;
+    gx2[j] = a.gx[xin ? x : 0];
+    if (xin && zin) {
+      vv2[j] = ld(r_V, vz, x * CB);
+      if constexpr (DS) {
+        if (p.two) ds2[j] = ld(r_ds2, vz, x * CB);
+      }
+    }
   }
   const float gzv = zin ? a.gz[z] : 0.f;
   if constexpr (NU) {
     // transposed second time difference of the e ring: step 1 reads slots
     // (k-1, k, k+1) on the halo, step 2 slots (k-2, k-1, k) on the tile
     const long so = (long)s * a.nu.sstride;
+    const auto rm = rsrc(a.nu.em + so, FB), r0 = rsrc(a.nu.e0 + so, FB), rp = rsrc(a.nu.ep + so, FB);
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
       const int x = xs1 + j;
-      if (zin && x >= 0 && x < NX) {
-        const long idx = so + (long)x * LZ + z;
+      if (x >= 0 && x < NX && zin) {
         const float g = gzv * a.gx[x];
-        ds1[j] += a.nu.em[idx] / g - 2.f * a.nu.e0[idx] + g * a.nu.ep[idx];
+        ds1[j] += ld(rm, vz, x * CB) / g - 2.f * ld(r0, vz, x * CB) + g * ld(rp, vz, x * CB);
       }
     }
     if (p.two) {
+      const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
 #pragma unroll
       for (int j = 0; j < W2; ++j) {
         const int x = xs2 + j;
-        if (zin && x < NX) {
-          const long idx = so + (long)x * LZ + z;
+        if (x < NX && zin) {
           const float g = gzv * a.gx[x];
-          ds2[j] += p.nu2.em[idx] / g - 2.f * p.nu2.e0[idx] + g * p.nu2.ep[idx];
+          ds2[j] += ld(rm2, vz, x * CB) / g - 2.f * ld(r02, vz, x * CB) + g * ld(rp2, vz, x * CB);
         }
       }
     }
   }
 
-  for (int i = tid; i < C0 * ROWS; i += 256) {
-    const int c = i / ROWS;
-    const int r = i - c * ROWS;
-    const int x = x0 - 2 * kR + c;
-    const int zg = z0 - 2 * kR + r;
-    float v = 0.f;
-    if ((unsigned)x < (unsigned)NX && (unsigned)zg < (unsigned)NZ) v = u0g[(long)x * LZ + zg];
-    sh.u0[c][r] = v;
-    if constexpr (DF) {
-      unsigned short l = 0;
-      if ((unsigned)x < (unsigned)NX && (unsigned)zg < (unsigned)NZ) l = p.lo_cur[soff + (long)x * LZ + zg];
-      sh.l0[c][r] = l;
+  // u^n tile, one column per wavefront access: lane = row z0 - 8 + lane, and
+  // lanes 0..7 also row z0 + 56 + lane
+  {
+    const int zt = z0 - 2 * kR + lane;
+    const bool zt_in = zt >= 0 && zt < NZ;
+    const bool zt2_in = lane < 2 * kR && zt + 64 < NZ;
+#pragma unroll
+    for (int i = 0; i < C0 / kWaves; ++i) {
+      const int c = w + kWaves * i;
+      const int x = x0 - 2 * kR + c;
+      float v = 0.f, v2 = 0.f;
+      unsigned short l = 0, l2 = 0;
+      if (x >= 0 && x < NX) {
+        if (zt_in) {
+          v = ld(r_cur, zt * 4, x * CB);
+          if constexpr (DF) l = ld16(r_lcur, zt * 2, x * (CB / 2));
+        }
+        if (zt2_in) {
+          v2 = ld(r_cur, (zt + 64) * 4, x * CB);
+          if constexpr (DF) l2 = ld16(r_lcur, (zt + 64) * 2, x * (CB / 2));
+        }
+      }
+      sh.u0[c][lane] = v;
+      if constexpr (DF) sh.l0[c][lane] = l;
+      if (lane < 2 * kR) {
+        sh.u0[c][64 + lane] = v2;
+        if constexpr (DF) sh.l0[c][64 + lane] = l2;
+      }
     }
   }
   __syncthreads();
@@ -182,73 +253,60 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   const int lz = lane + kR;                  // LDS row of this lane's row
   // ---- step 1: u^{n+1} on the tile plus a 4-cell halo --------------------
   {
-    int q0 = 0, qend = 0;
-    if (a.inj.ptr != nullptr) {
-      q0 = a.inj.ptr[logical * kWaves + w];
-      qend = a.inj.ptr[logical * kWaves + w + 1];
-    }
-    float *out = a.out + soff;
-    const int cb = w * W1 + kR;              // u0 column of the wave's first column
-    float q[2 * kR + 1], ql[2 * kR + 1];
-#pragma unroll
-    for (int k = 0; k < 2 * kR; ++k) {
-      q[k] = sh.u0[cb - kR + k][lz];
-      if constexpr (DF) ql[k] = bf16_f32(sh.l0[cb - kR + k][lz]);
-    }
+    fold_sources<W1>(a.inj, logical, w, lane, ds1);
+    const auto r_out = rsrc(a.out + soff, FB);
+    [[maybe_unused]] __amdgpu_buffer_rsrc_t r_t2, r_lout;
+    if constexpr (T2) r_t2 = rsrc(a.t2 + (long)s * a.t2_sstride, FB);
+    if constexpr (DF) r_lout = rsrc(p.lo_out + soff, FB / 2);
+    // all 17 stencil operands come straight from LDS at fixed offsets from
+    // one per-lane base (a register queue along x costs a move per operand)
+    const float *base = &sh.u0[w * W1 + kR][lz];                   // u0 column of the wave's first column
+    [[maybe_unused]] const unsigned short *basel = nullptr;
+    if constexpr (DF) basel = &sh.l0[w * W1 + kR][lz];
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
-      q[2 * kR] = sh.u0[cb + j + kR][lz];
-      const float c = q[kR];
-      const float *col = &sh.u0[cb + j][lz];
+      const float *col = base + j * ROWS;
+      const float c = col[0];
       float lap = 0.f;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
         lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * ((q[kR - k] - c) + (q[kR + k] - c));
+        lap += a.cx[k - 1] * ((col[-k * ROWS] - c) + (col[k * ROWS] - c));
       }
       float cl = 0.f;
       if constexpr (DF) {
-        ql[2 * kR] = bf16_f32(sh.l0[cb + j + kR][lz]);
-        cl = ql[kR];
-        const unsigned short *cll = &sh.l0[cb + j][lz];
+        const unsigned short *cll = basel + j * ROWS;
+        cl = bf16_f32(cll[0]);
         float lapl = 0.f;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
           lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * ((ql[kR - k] - cl) + (ql[kR + k] - cl));
+          lapl += a.cx[k - 1] * ((bf16_f32(cll[-k * ROWS]) - cl) + (bf16_f32(cll[k * ROWS]) - cl));
         }
         lap += lapl;
       }
-      float src = ds1[j];
-      while (q0 < qend) {   // wave-uniform
-        const int2 en = a.inj.ent[q0];
-        if ((en.x >> 6) != j) break;
-        const float val = a.inj.val[(long)en.y * a.inj.stride_idx + a.inj.t] * a.inj.scale;
-        if ((en.x & 63) == lane) src += val;
-        ++q0;
-      }
       const int x = xs1 + j;
-      float u1 = 0.f;
+      const bool xin = x >= 0 && x < NX;     // wave-uniform
+      // computed for every lane; cells outside the grid are set to zero
+      const float g = gzv * gx1[j];
+      const float r = vv1[j] * (lap + ds1[j]);
       unsigned short u1l = 0;
-      if (zin && x >= 0 && x < NX) {
-        const float g = gzv * a.gx[x];
-        const float r = vv1[j] * (lap + src);
-        if constexpr (DF) u1 = df_update(g, c, cl, pv[j], pl[j], r, u1l);
-        else u1 = g * (2.f * c - g * pv[j] + r);
-        if (zown && x >= x0 && x < x0 + TX) {
-          const long idx = (long)x * LZ + z;
-          out[idx] = u1;
-          if constexpr (DF) p.lo_out[soff + idx] = u1l;
-          if constexpr (T2) a.t2[(long)s * a.t2_sstride + idx] = r;
+      float u1;
+      if constexpr (DF) u1 = df_update(g, c, cl, pv[j], pl[j], r, u1l);
+      else u1 = g * (2.f * c - g * pv[j] + r);
+      if (!(xin && zin)) {
+        u1 = 0.f;
+        u1l = 0;
+      }
+      if (xin && x >= x0 && x < x0 + TX) {   // wave-uniform
+        if (zin && zown) {
+          st(r_out, u1, vz, x * CB);
+          if constexpr (DF) st16(r_lout, u1l, z * 2, x * (CB / 2));
+          if constexpr (T2) st(r_t2, r, vz, x * CB);
         }
       }
       sh.u1[w * W1 + j][lz] = u1;
       if constexpr (DF) sh.l1[w * W1 + j][lz] = u1l;
-#pragma unroll
-      for (int k = 0; k < 2 * kR; ++k) {
-        q[k] = q[k + 1];
-        if constexpr (DF) ql[k] = ql[k + 1];
-      }
     }
   }
   if (!p.two && !ext_next) return;
@@ -263,70 +321,56 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
 
   // ---- step 2: u^{n+2} on the tile ----------------------------------------
   {
-    int q0 = 0, qend = 0;
-    if (p.inj2.ptr != nullptr) {
-      q0 = p.inj2.ptr[logical * kWaves + w];
-      qend = p.inj2.ptr[logical * kWaves + w + 1];
-    }
-    float *out = p.out2 + soff;
+    fold_sources<W2>(p.inj2, logical, w, lane, ds2);
+    const auto r_out = rsrc(p.out2 + soff, FB);
+    [[maybe_unused]] __amdgpu_buffer_rsrc_t r_t2, r_lout;
+    if constexpr (T2) r_t2 = rsrc(p.t2b + (long)s * a.t2_sstride, FB);
+    if constexpr (DF) r_lout = rsrc(p.lo_out2 + soff, FB / 2);
     const int cb = w * W2 + kR;              // u1 column of the wave's first column
-    float q[2 * kR + 1], ql[2 * kR + 1];
-#pragma unroll
-    for (int k = 0; k < 2 * kR; ++k) {
-      q[k] = sh.u1[cb - kR + k][lz];
-      if constexpr (DF) ql[k] = bf16_f32(sh.l1[cb - kR + k][lz]);
+    const float *base = &sh.u1[cb][lz];
+    const float *base0 = &sh.u0[cb + kR][lz];                      // u^n at the wave's first column
+    [[maybe_unused]] const unsigned short *basel = nullptr, *basel0 = nullptr;
+    if constexpr (DF) {
+      basel = &sh.l1[cb][lz];
+      basel0 = &sh.l0[cb + kR][lz];
     }
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
-      q[2 * kR] = sh.u1[cb + j + kR][lz];
-      const float c = q[kR];
-      const float *col = &sh.u1[cb + j][lz];
+      const float *col = base + j * ROWS;
+      const float c = col[0];
       float lap = 0.f;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
         lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * ((q[kR - k] - c) + (q[kR + k] - c));
+        lap += a.cx[k - 1] * ((col[-k * ROWS] - c) + (col[k * ROWS] - c));
       }
       float cl = 0.f;
       if constexpr (DF) {
-        ql[2 * kR] = bf16_f32(sh.l1[cb + j + kR][lz]);
-        cl = ql[kR];
-        const unsigned short *cll = &sh.l1[cb + j][lz];
+        const unsigned short *cll = basel + j * ROWS;
+        cl = bf16_f32(cll[0]);
         float lapl = 0.f;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
           lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * ((ql[kR - k] - cl) + (ql[kR + k] - cl));
+          lapl += a.cx[k - 1] * ((bf16_f32(cll[-k * ROWS]) - cl) + (bf16_f32(cll[k * ROWS]) - cl));
         }
         lap += lapl;
       }
-      float src = ds2[j];
-      while (q0 < qend) {   // wave-uniform
-        const int2 en = p.inj2.ent[q0];
-        if ((en.x >> 6) != j) break;
-        const float val = p.inj2.val[(long)en.y * p.inj2.stride_idx + p.inj2.t] * p.inj2.scale;
-        if ((en.x & 63) == lane) src += val;
-        ++q0;
-      }
       const int x = xs2 + j;
-      if (zown && zin && x < NX) {
-        const float g = gzv * a.gx[x];
-        const float un = sh.u0[cb + j + kR][lz];
-        const float r = vv2[j] * (lap + src);
-        const long idx = (long)x * LZ + z;
-        if constexpr (DF) {
-          unsigned short l;
-          out[idx] = df_update(g, c, cl, un, bf16_f32(sh.l0[cb + j + kR][lz]), r, l);
-          p.lo_out2[soff + idx] = l;
-        } else {
-          out[idx] = g * (2.f * c - g * un + r);
+      const bool xin = x < NX;               // wave-uniform
+      const float g = gzv * gx2[j];
+      const float un = base0[j * ROWS];
+      const float r = vv2[j] * (lap + ds2[j]);
+      unsigned short u2l = 0;
+      float u2;
+      if constexpr (DF) u2 = df_update(g, c, cl, un, bf16_f32(basel0[j * ROWS]), r, u2l);
+      else u2 = g * (2.f * c - g * un + r);
+      if (xin) {
+        if (zown && zin) {
+          st(r_out, u2, vz, x * CB);
+          if constexpr (DF) st16(r_lout, u2l, z * 2, x * (CB / 2));
+          if constexpr (T2) st(r_t2, r, vz, x * CB);
         }
-        if constexpr (T2) p.t2b[(long)s * a.t2_sstride + idx] = r;
-      }
-#pragma unroll
-      for (int k = 0; k < 2 * kR; ++k) {
-        q[k] = q[k + 1];
-        if constexpr (DF) ql[k] = ql[k + 1];
       }
     }
   }

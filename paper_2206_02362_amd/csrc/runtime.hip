@@ -275,7 +275,7 @@ HostTables build_tables(const Dims &d, const fwime_geom_t *geo, int s0, int S) {
   const long ntiles = (long)d.ntz * d.ntx * S;
   auto locate = [&](int s, int px, int pz, long &tile, int &lx, int &lz) {
     const int txi = px / d.TX, tzi = pz / kTZ;
-    tile = ((long)txi * d.ntz + tzi) * S + s;
+    tile = tile_index(txi, tzi, s, d.ntz, d.ntx, S);
     lx = px - txi * d.TX;
     lz = pz - tzi * kTZ;
   };
@@ -309,7 +309,7 @@ HostTables build_tables2(const Dims &d, const fwime_geom_t *geo, int s0, int S) 
   HostTables t;
   const int W1 = (d.TX + 2 * kR) / kWaves, W2 = d.TX / kWaves;
   const long ntiles = (long)d.ntz2 * d.ntx * S;
-  auto tile_of = [&](int s, int txi, int tzi) { return ((long)txi * d.ntz2 + tzi) * S + s; };
+  auto tile_of = [&](int s, int txi, int tzi) { return tile_index(txi, tzi, s, d.ntz2, d.ntx, S); };
   std::vector<std::pair<long, int2>> src1, src2, rext, rinj1, rinj2;
   auto add_inject = [&](int s, int px, int pz, int idx, std::vector<std::pair<long, int2>> &l1,
                         std::vector<std::pair<long, int2>> &l2) {
@@ -941,7 +941,7 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   // two-step path: BF16 low parts of the four work fields and the checkpoints
   const long per_shot = (nf + 2L * nseg + K + R + (two ? 2L + nseg : 0L)) * d.field * 4 + (long)geo->nrec * 64;
   const long img = (long)nh * d.nx * d.nz;
-  const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4;
+  const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4 * (1 + kImageGroups);
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, two);
@@ -953,7 +953,9 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   unsigned short *lows = nullptr, *ckpt_lo = nullptr;
+  float *parts = nullptr;
   cv.add(&acc, img);
+  cv.add(&parts, kImageGroups * img);
   cv.add(&pairs, nf * d.field * S);
   cv.add(&ckpt, 2L * nseg * d.field * S);
   if (two) {
@@ -1011,7 +1013,7 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
         }, st, &wl);
         if (rc) return rc;
         if ((rc = march2_back_lambda(ctx, c, ring, ring_stride, R, Sb, n0, n1, t, data_b, g->nt, st))) return rc;
-        HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
+        HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, parts, st));
       }
       continue;
     }
@@ -1058,7 +1060,7 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
         with_rec_inject(a, t, data_b, g->nt, k);
         HIPCHK(launch_step(a, d.TX, kModePlain, st));
       }
-      HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, st));
+      HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, parts, st));
     }
   }
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, ptilde_out, st));
@@ -1098,8 +1100,9 @@ GradPlan grad_plan(const Dims &d, int nt) {
   return p;
 }
 
-struct GradWork {       // per-batch working fields
+struct GradWork {       // per-batch working fields (+ partial images of the imaging kernel)
   float *pairs, *t2u, *t2d, *lam, *er, *rho;
+  float *parts = nullptr;
 };
 
 int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
@@ -1267,7 +1270,7 @@ int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, co
       }
     }
     HIPCHK(launch_ext_image(wk.t2u, d.field, pl.seg_stride, wk.lam, d.field, pl.ring_stride, R, n0, Sb, nk, eg, acc,
-                            st));
+                            wk.parts, st));
     HIPCHK(launch_grad_accum(wk.t2u, wk.t2d, d.field, pl.seg_stride, wk.lam, wk.rho, d.field, pl.ring_stride, R, n0,
                              Sb, nk, d.NZ, d.NX, d.LZ, gacc, st));
   }
@@ -1338,7 +1341,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   const long nrt = (long)geo->nrec * g->nt;
   const long per_shot =
       grad_work_per_shot(d, pl, ctx->two_step) + 2 * pl.ck_stride * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
-  const size_t fixed = (size_t)d.field * 12 + (size_t)img * 12;
+  const size_t fixed = (size_t)d.field * 12 + (size_t)img * 4 * (3 + kImageGroups);
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, ctx->two_step);
@@ -1361,6 +1364,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   cv.add(&uck, pl.ck_stride * S);
   cv.add(&dck, pl.ck_stride * S);
   carve_work(cv, wk, d, pl, S, ctx->two_step);
+  cv.add(&wk.parts, kImageGroups * img);
   cv.add(&drec, nrt * S);
   cv.add(&ddrec, nrt * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -1541,6 +1545,7 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
   cv.add(&imgs, img);
   cv.add(&gacc, d.field);
   carve_work(cv, wk, d, pl, S, ctx->two_step);
+  cv.add(&wk.parts, kImageGroups * img);
   if ((rc = arena_get(ctx, cv))) return rc;
   Common c;
   c.d = d;
@@ -1856,10 +1861,13 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
   switch (op) {
     case FWIME_OP_MODEL: per_shot = 4 * fb; break;
     case FWIME_OP_BORN_FWD: per_shot = (8 + 2 * 16 + 2) * fb; fixed += img; break;
-    case FWIME_OP_BORN_ADJ: per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + pl.nseg) * fb; fixed += img; break;
+    case FWIME_OP_BORN_ADJ:
+      per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + pl.nseg) * fb;
+      fixed += (1 + kImageGroups) * img;
+      break;
     case FWIME_OP_GRADIENT:
       per_shot = grad_work_per_shot(d, pl, true) + 2 * pl.ck_stride * 4 + 2 * nrt;
-      fixed += 3 * img;
+      fixed += (3 + kImageGroups) * img;
       break;
     default: return FWIME_EINVAL;
   }
