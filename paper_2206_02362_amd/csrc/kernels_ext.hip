@@ -17,13 +17,39 @@ namespace fw {
 // Raw buffer access: a load whose byte offset falls outside [0, bytes) of the
 // resource returns 0 in hardware (negative offsets wrap to large unsigned
 // values).  Window staging relies on this to drop the terms whose column lies
-// outside the padded grid without any per-element test.
+// outside the padded grid without any per-element test, so the whole offset
+// goes in the vector operand: the scalar offset is not range-checked.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const float *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)bytes, 0x00020000);
 }
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
+
+// (shot, slot, ring position) of consecutive flat slot indices q = s nk + n,
+// advanced without an integer division per slot.  ring == 0: position = n;
+// otherwise position = (first + n) mod ring (slots n < nk <= ring).
+struct SlotCursor {
+  int s, n, r, nk, ring, f0;
+  __device__ void init(int q, int nk_, int first, int ring_) {
+    nk = nk_;
+    ring = ring_;
+    s = q / nk;
+    n = q - s * nk;
+    f0 = ring ? first % ring : 0;
+    r = ring ? (f0 + n) % ring : n;
+  }
+  __device__ void next() {
+    if (++n == nk) {
+      n = 0;
+      ++s;
+      r = f0;
+      return;
+    }
+    ++r;
+    if (ring && r == ring) r = 0;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // c(z,y,h) = 2 p~(z,y,h) / (v(z,y)^3 dt^2), model grid, [nh][nx][nz]
@@ -135,6 +161,8 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs
   const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
   const int off0 = ((col0 + w) * a.LZ + zp) * 4;
   const int rstep = 8 * a.LZ * 4;
+  // (slot indices are recomputed per slot here: cursors held in scalar
+  // registers push this register-bound kernel into spills)
   auto fetch = [&](int q, float (&pre)[PER]) {
     if (q >= q1) return;
     const int s = q / a.nk, n = q - s * a.nk;
@@ -333,8 +361,8 @@ struct ImageArgs {
 // (NYT NHT = 16).  Per time slot the source-side window (y - h) and the
 // receiver-side window (y + h), each YB + 8 NHT - 1 columns wide, are staged in
 // a 3-deep LDS ring: slot q is consumed while slot q + 1 is written from
-// registers and the loads of slot q + 2 are in flight (one barrier per slot).
-// With several slot groups (enough workgroups to fill the device when the
+// registers and the loads of slots q + 2 and q + 3 are in flight (one barrier
+// per slot).  With several slot groups (enough workgroups to fill the device when the
 // tiles alone do not), group g stores its partial image and a second kernel
 // adds the partials to the accumulator in group order, so the result does not
 // depend on scheduling.
@@ -384,19 +412,22 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   // thread (w, lane) stages rows w + 16 r at depth lane; out-of-grid columns
   // read as zero through the bounds-checked buffer loads
   const unsigned slot_bytes = (unsigned)((long)p.NX * p.LZ * 4);
+  const int zoff = zp * 4;                          // per lane
+  const int CBy = p.LZ * 4;                         // bytes per column
+  SlotCursor fc;                                    // fetch walks q0, q0 + 1, ... once, in order
+  fc.init(q0, p.nk, p.b_first, p.b_ring);
   auto fetch = [&](int q, float (&pre)[PER]) {
     if (q >= total) return;
-    const int s = q / p.nk, n = q - s * p.nk;
-    const auto ra = slot_rsrc(p.a + (long)s * p.a_sstride + (long)n * p.a_slot, slot_bytes);
-    const auto rbb = slot_rsrc(p.b + (long)s * p.b_sstride + (long)((p.b_first + n) % p.b_ring) * p.b_slot,
-                               slot_bytes);
+    const auto ra = slot_rsrc(p.a + (long)fc.s * p.a_sstride + (long)fc.n * p.a_slot, slot_bytes);
+    const auto rbb = slot_rsrc(p.b + (long)fc.s * p.b_sstride + (long)fc.r * p.b_slot, slot_bytes);
+    fc.next();
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int c = w + 16 * r;
       if (c < WW)
-        pre[r] = bload(ra, ((xa0 + c) * p.LZ + zp) * 4);
+        pre[r] = bload(ra, zoff + (xa0 + c) * CBy);
       else
-        pre[r] = bload(rbb, ((xb0 + c - WW) * p.LZ + zp) * 4);
+        pre[r] = bload(rbb, zoff + (xb0 + c - WW) * CBy);
     }
   };
   auto put = [&](int rbuf, const float (&pre)[PER]) {
@@ -406,35 +437,45 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
       if (c < ROWS) ring[rbuf][c * 64 + lane] = pre[r];
     }
   };
-  float p1[PER], p2[PER];
-  fetch(q0, p1);
-  put(0, p1);
-  fetch(q0 + 1, p1);
-  fetch(q0 + 2, p2);
+  auto consume = [&](int rbuf) {
+    if (!active) return;
+    const float *win = ring[rbuf];
+    float va[NA], vb[NA];
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+      va[m] = win[(ia + m) * 64 + lane];
+      vb[m] = win[(ib + m) * 64 + lane];
+    }
+#pragma unroll
+    for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+      for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
+  };
+  // ring[rb] holds slot q; pA / pB hold the two following slots (unrolled by
+  // two so the staging registers alternate instead of being copied)
+  float pA[PER], pB[PER];
+  fetch(q0, pA);
+  put(0, pA);
+  fetch(q0 + 1, pA);
+  fetch(q0 + 2, pB);
   __syncthreads();
   int rb = 0;
-  for (int q = q0; q < total; ++q) {
-    if (active) {
-      const float *win = ring[rb];
-      float va[NA], vb[NA];
-#pragma unroll
-      for (int m = 0; m < NA; ++m) {
-        va[m] = win[(ia + m) * 64 + lane];
-        vb[m] = win[(ib + m) * 64 + lane];
-      }
-#pragma unroll
-      for (int yy = 0; yy < kImgYT; ++yy)
-#pragma unroll
-        for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
-    }
-    const int nb1 = rb == 2 ? 0 : rb + 1;
-    if (q + 1 < total) put(nb1, p1);
-#pragma unroll
-    for (int r = 0; r < PER; ++r) p1[r] = p2[r];
-    fetch(q + 3, p2);
+  int q = q0;
+  for (; q + 1 < total; q += 2) {   // pairs of slots; no exit in between
+    int nb1 = rb == 2 ? 0 : rb + 1;
+    consume(rb);
+    put(nb1, pA);
+    fetch(q + 3, pA);
+    __syncthreads();
+    rb = nb1;
+    nb1 = rb == 2 ? 0 : rb + 1;
+    consume(rb);
+    if (q + 2 < total) put(nb1, pB);
+    fetch(q + 4, pB);
     __syncthreads();
     rb = nb1;
   }
+  if (q < total) consume(rb);       // odd last slot, already staged
   if (!active || !zin) return;
 #pragma unroll
   for (int yy = 0; yy < kImgYT; ++yy) {

@@ -68,8 +68,9 @@ __device__ __forceinline__ float df_update(float g, float c, float cl, float pv,
 
 // Raw buffer access: per-lane 32-bit byte offset (the row) plus a wave-uniform
 // byte offset (the column) that lives in a scalar register, so no 64-bit
-// address arithmetic is spent per access.  Every access below is guarded, so
-// the hardware range check is not relied on.
+// address arithmetic is spent per access.  The scalar offset is not part of
+// the hardware range check, so every access below is guarded: its column is
+// inside [0, NX) and its row inside the grid.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
@@ -146,12 +147,11 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   const int xs2 = x0 + w * W2;               // first step-2 column
 
   // Own-row operands of both steps; their latency hides behind the tile load.
-  float pv[W1], vv1[W1], vv2[W2], ds1[W1], ds2[W2], pl[W1], gx1[W1], gx2[W2];
-  [[maybe_unused]] __amdgpu_buffer_rsrc_t r_ds1, r_ds2, r_lprev, r_lcur;
-  if constexpr (DS) {
-    r_ds1 = rsrc(a.dsrc + (long)s * a.dsrc_sstride, FB);
-    r_ds2 = rsrc(p.two ? p.dsrc2 + (long)s * a.dsrc_sstride : a.dsrc, FB);
-  }
+  // (the second step's operands are loaded after the first step, to keep the
+  // register footprint of the first step small)
+  float pv[W1], vv1[W1], ds1[W1], pl[W1], gx1[W1];
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t r_ds1, r_lprev, r_lcur;
+  if constexpr (DS) r_ds1 = rsrc(a.dsrc + (long)s * a.dsrc_sstride, FB);
   if constexpr (DF) {
     r_lprev = rsrc(p.lo_prev + soff, FB / 2);
     r_lcur = rsrc(p.lo_cur + soff, FB / 2);
@@ -169,19 +169,6 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       if constexpr (DF) pl[j] = bf16_f32(ld16(r_lprev, z * 2, x * (CB / 2)));
     }
   }
-#pragma unroll
-  for (int j = 0; j < W2; ++j) {
-    const int x = xs2 + j;
-    const bool xin = x < NX;
-    vv2[j] = ds2[j] = 0.f;
-    gx2[j] = a.gx[xin ? x : 0];
-    if (xin && zin) {
-      vv2[j] = ld(r_V, vz, x * CB);
-      if constexpr (DS) {
-        if (p.two) ds2[j] = ld(r_ds2, vz, x * CB);
-      }
-    }
-  }
   const float gzv = zin ? a.gz[z] : 0.f;
   if constexpr (NU) {
     // transposed second time difference of the e ring: step 1 reads slots
@@ -194,17 +181,6 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       if (x >= 0 && x < NX && zin) {
         const float g = gzv * a.gx[x];
         ds1[j] += ld(rm, vz, x * CB) / g - 2.f * ld(r0, vz, x * CB) + g * ld(rp, vz, x * CB);
-      }
-    }
-    if (p.two) {
-      const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
-#pragma unroll
-      for (int j = 0; j < W2; ++j) {
-        const int x = xs2 + j;
-        if (x < NX && zin) {
-          const float g = gzv * a.gx[x];
-          ds2[j] += ld(rm2, vz, x * CB) / g - 2.f * ld(r02, vz, x * CB) + g * ld(rp2, vz, x * CB);
-        }
       }
     }
   }
@@ -321,6 +297,30 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
 
   // ---- step 2: u^{n+2} on the tile ----------------------------------------
   {
+    float vv2[W2], ds2[W2], gx2[W2];
+#pragma unroll
+    for (int j = 0; j < W2; ++j) {
+      const int x = xs2 + j;
+      const bool xin = x < NX;
+      vv2[j] = ds2[j] = 0.f;
+      gx2[j] = a.gx[xin ? x : 0];
+      if (xin && zin) {
+        vv2[j] = ld(r_V, vz, x * CB);
+        if constexpr (DS) ds2[j] = ld(rsrc(p.dsrc2 + (long)s * a.dsrc_sstride, FB), vz, x * CB);
+      }
+    }
+    if constexpr (NU) {
+      const long so = (long)s * a.nu.sstride;
+      const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
+#pragma unroll
+      for (int j = 0; j < W2; ++j) {
+        const int x = xs2 + j;
+        if (x < NX && zin) {
+          const float g = gzv * a.gx[x];
+          ds2[j] += ld(rm2, vz, x * CB) / g - 2.f * ld(r02, vz, x * CB) + g * ld(rp2, vz, x * CB);
+        }
+      }
+    }
     fold_sources<W2>(p.inj2, logical, w, lane, ds2);
     const auto r_out = rsrc(p.out2 + soff, FB);
     [[maybe_unused]] __amdgpu_buffer_rsrc_t r_t2, r_lout;
