@@ -239,6 +239,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     const float *base = &sh.u0[w * W1 + kR][lz];                   // u0 column of the wave's first column
     [[maybe_unused]] const unsigned short *basel = nullptr;
     if constexpr (DF) basel = &sh.l0[w * W1 + kR][lz];
+    // forward x-differences d[k][j] = u(j + k) - u(j): the backward one of
+    // column j, u(j - k) - u(j), is -d[k][j - k] (exact), so each difference
+    // along x is formed once
+    float dxf[kR][W1], dxl[kR][W1];
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
       const float *col = base + j * ROWS;
@@ -246,8 +250,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       float lap = 0.f;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
+        dxf[k - 1][j] = col[k * ROWS] - c;
+        const float back = j >= k ? -dxf[k - 1][j - k] : col[-k * ROWS] - c;
         lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * ((col[-k * ROWS] - c) + (col[k * ROWS] - c));
+        lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
       }
       float cl = 0.f;
       if constexpr (DF) {
@@ -256,8 +262,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
         float lapl = 0.f;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
+          dxl[k - 1][j] = bf16_f32(cll[k * ROWS]) - cl;
+          const float back = j >= k ? -dxl[k - 1][j - k] : bf16_f32(cll[-k * ROWS]) - cl;
           lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * ((bf16_f32(cll[-k * ROWS]) - cl) + (bf16_f32(cll[k * ROWS]) - cl));
+          lapl += a.cx[k - 1] * (back + dxl[k - 1][j]);
         }
         lap += lapl;
       }
@@ -334,6 +342,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       basel = &sh.l1[cb][lz];
       basel0 = &sh.l0[cb + kR][lz];
     }
+    float dxf[kR][W2], dxl[kR][W2];          // forward x-differences, as in step 1
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
       const float *col = base + j * ROWS;
@@ -341,8 +350,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       float lap = 0.f;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
+        dxf[k - 1][j] = col[k * ROWS] - c;
+        const float back = j >= k ? -dxf[k - 1][j - k] : col[-k * ROWS] - c;
         lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * ((col[-k * ROWS] - c) + (col[k * ROWS] - c));
+        lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
       }
       float cl = 0.f;
       if constexpr (DF) {
@@ -351,8 +362,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
         float lapl = 0.f;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
+          dxl[k - 1][j] = bf16_f32(cll[k * ROWS]) - cl;
+          const float back = j >= k ? -dxl[k - 1][j - k] : bf16_f32(cll[-k * ROWS]) - cl;
           lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * ((bf16_f32(cll[-k * ROWS]) - cl) + (bf16_f32(cll[k * ROWS]) - cl));
+          lapl += a.cx[k - 1] * (back + dxl[k - 1][j]);
         }
         lap += lapl;
       }
