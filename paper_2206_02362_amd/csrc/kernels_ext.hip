@@ -11,6 +11,8 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstdlib>
+#include <string>
 
 namespace fw {
 
@@ -223,6 +225,128 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs
   }
 }
 
+// Same operator, input windows brought in by direct global-to-LDS loads
+// (buffer loads with the LDS as destination) into a 4-deep ring: three slots
+// are in flight while one is consumed, and no registers are spent on
+// staging.  Before the barrier that publishes slot q each wavefront waits
+// until its own loads of slot q have landed; the loads of the two younger
+// slots may still be outstanding (vector memory operations complete in
+// order).  The barrier is a bare s_barrier: a fenced one would wait for every
+// outstanding load.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int HMAX, int SG>
+__global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArgs a) {
+  constexpr int NH = 2 * HMAX + 1;
+  constexpr int WMAX = kScJB + 4 * HMAX;                          // staged columns
+  constexpr int PER = WMAX / 8;                                   // staged columns per wavefront
+  static_assert(WMAX % 8 == 0 && 2 * PER <= 63, "window");
+  __shared__ float b0[WMAX * 64], b1[WMAX * 64], b2[WMAX * 64], b3[WMAX * 64];
+
+  const int nblk_j = (a.nj + kScJB - 1) / kScJB;
+  const int ntile = a.nzs * nblk_j;
+  const int per = (ntile + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntile) return;
+  const int zs = tile % a.nzs;
+  const int jbk = tile / a.nzs;
+  const int jb = a.j0 + jbk * kScJB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int z = zs * 64 + lane;
+  const bool zin = z < a.nz;
+  const int zp = a.nb + z;
+  const int H = a.H;
+  const int col0 = jb - 2 * HMAX;
+  const int ja = jb + (w & 1) + 4 * (w >> 1);
+  const int jc = ja + 2;
+  const int jend = a.j0 + a.nj;
+
+  float ca[NH], cb[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int ih = k - HMAX;
+    float va = 0.f, vb = 0.f;
+    if (ih >= -H && ih <= H && zin) {
+      const int ya = ja - SG * ih - a.nb, yc = jc - SG * ih - a.nb;
+      const long hb = (long)(ih + H) * a.nx;
+      if (ya >= 0 && ya < a.nx) va = a.coef[(hb + ya) * a.nz + z];
+      if (yc >= 0 && yc < a.nx) vb = a.coef[(hb + yc) * a.nz + z];
+    }
+    ca[k] = va;
+    cb[k] = vb;
+  }
+
+  const int total = a.nshots * a.nk;
+  const int q0 = blockIdx.y * a.slots_per_block;
+  const int q1 = min(total, q0 + a.slots_per_block);
+  if (q0 >= q1) return;
+  const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
+  const int off0 = ((col0 + w) * a.LZ + zp) * 4;
+  const int rstep = 8 * a.LZ * 4;
+
+  // slots are issued and consumed in increasing order: one cursor each
+  SlotCursor ic, oc;
+  ic.init(q0, a.nk, a.in_first, a.in_ring);
+  oc.init(q0, a.nk, a.out_first, a.out_ring);
+  // wavefront w brings columns w + 8 r of slot q into buf (lane = depth)
+  auto issue = [&](int q, float *buf) {
+    if (q >= q1) return;
+    const auto rs = slot_rsrc(a.in + (long)ic.s * a.sstride + (long)ic.r * a.in_slot, slot_bytes);
+    ic.next();
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&buf[(w + 8 * r) * 64], 4, off0 + r * rstep, 0, 0,
+                                                0);
+  };
+  // this wavefront's loads of slot q have landed; younger slots may be in flight
+  auto ready = [&](int q) {
+    constexpr int kExpLgkm = (7 << 4) | (15 << 8);
+    if (q + 2 < q1) __builtin_amdgcn_s_waitcnt(((2 * PER) & 15) | (((2 * PER) >> 4) << 14) | kExpLgkm);
+    else if (q + 1 < q1) __builtin_amdgcn_s_waitcnt((PER & 15) | ((PER >> 4) << 14) | kExpLgkm);
+    else __builtin_amdgcn_s_waitcnt(kExpLgkm);
+  };
+  auto consume = [&](int q, const float *buf) {
+    const float *row = &buf[(ja - col0) * 64 + lane];
+    float oa = 0.f, ob = 0.f;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const int ih = k - HMAX;
+      oa += ca[k] * row[-2 * SG * ih * 64];
+      ob += cb[k] * row[(2 - 2 * SG * ih) * 64];
+    }
+    float *dst = a.out + (long)oc.s * a.sstride + (long)oc.r * a.out_slot;
+    oc.next();
+    if (zin) {
+      if (ja < jend) dst[(long)ja * a.LZ + zp] = oa;
+      if (jc < jend) dst[(long)jc * a.LZ + zp] = ob;
+    }
+  };
+  // slot q sits in buffer q mod 4; the slot loaded in its place is q + 3,
+  // whose buffer held slot q - 1 (everyone is past it once the barrier passed)
+  auto step = [&](int q, const float *cur, float *nxt) {
+    asm volatile("" ::: "memory");        // the barrier is no memory operation to the compiler:
+    ready(q);                             // keep LDS accesses on their side of it
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(q + 3, nxt);
+    consume(q, cur);
+  };
+  issue(q0, b0);
+  issue(q0 + 1, b1);
+  issue(q0 + 2, b2);
+  for (int q = q0; q < q1; q += 4) {
+    step(q, b0, b3);
+    if (q + 1 >= q1) break;
+    step(q + 1, b1, b0);
+    if (q + 2 >= q1) break;
+    step(q + 2, b2, b1);
+    if (q + 3 >= q1) break;
+    step(q + 3, b3, b2);
+  }
+}
+
 // Generic fallback (any H): one thread per (z, j), coefficient reused over up
 // to kScatterKC slots held in registers.
 constexpr int kScatterKC = 16;
@@ -307,25 +431,38 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
   a.nzs = (g.nz + 63) / 64;
   a.nk = nk;
   a.nshots = nshots;
+  const int total = nshots * nk;
+  // FWIME_SCATTER_KERNEL=ws selects the register-staged ring for
+  // comparisons; the default is the ring fed by direct global-to-LDS loads
+  static const bool staged = [] {
+    const char *e = std::getenv("FWIME_SCATTER_KERNEL");
+    return e && std::string(e) == "ws";
+  }();
+#define FW_SCATTER(K, GRID, THREADS)                                                                    \
+  if (g.H <= 8)                                                                                         \
+    sg > 0 ? K<8, 1><<<GRID, THREADS, 0, st>>>(a) : K<8, -1><<<GRID, THREADS, 0, st>>>(a);              \
+  else if (g.H <= 16)                                                                                   \
+    sg > 0 ? K<16, 1><<<GRID, THREADS, 0, st>>>(a) : K<16, -1><<<GRID, THREADS, 0, st>>>(a);            \
+  else if (g.H <= 24)                                                                                   \
+    sg > 0 ? K<24, 1><<<GRID, THREADS, 0, st>>>(a) : K<24, -1><<<GRID, THREADS, 0, st>>>(a);            \
+  else                                                                                                  \
+    sg > 0 ? K<30, 1><<<GRID, THREADS, 0, st>>>(a) : K<30, -1><<<GRID, THREADS, 0, st>>>(a);
   if (g.H <= 30) {
     // spread the slots over enough workgroups to fill the device
     const int ntile = a.nzs * ((a.nj + kScJB - 1) / kScJB);
     const int nblk = (ntile + 7) / 8 * 8;
-    const int total = nshots * nk;
     int groups = std::max(1, std::min(total, (2048 + nblk - 1) / nblk));
     a.slots_per_block = (total + groups - 1) / groups;
     groups = (total + a.slots_per_block - 1) / a.slots_per_block;
     const dim3 grid((unsigned)nblk, (unsigned)groups);
-    if (g.H <= 8)
-      sg > 0 ? k_ext_scatter_ws<8, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<8, -1><<<grid, kScThreads, 0, st>>>(a);
-    else if (g.H <= 16)
-      sg > 0 ? k_ext_scatter_ws<16, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<16, -1><<<grid, kScThreads, 0, st>>>(a);
-    else if (g.H <= 24)
-      sg > 0 ? k_ext_scatter_ws<24, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<24, -1><<<grid, kScThreads, 0, st>>>(a);
-    else
-      sg > 0 ? k_ext_scatter_ws<30, 1><<<grid, kScThreads, 0, st>>>(a) : k_ext_scatter_ws<30, -1><<<grid, kScThreads, 0, st>>>(a);
+    if (staged) {
+      FW_SCATTER(k_ext_scatter_ws, grid, kScThreads)
+    } else {
+      FW_SCATTER(k_ext_scatter_dma, grid, kScThreads)
+    }
     return hipGetLastError();
   }
+#undef FW_SCATTER
   const long waves = (long)nshots * a.nzs * a.nj;
   k_ext_scatter<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a);
   return hipGetLastError();

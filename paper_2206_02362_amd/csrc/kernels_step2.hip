@@ -227,6 +227,15 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   if (extract_only) return;
 
   const int lz = lane + kR;                  // LDS row of this lane's row
+  // The low part of the extended-precision field is a rounding residual
+  // (below 2^-24 of the field): its Laplacian needs only a few correct
+  // digits, so it is summed directly, sum_k w_k (l(-k) + l(k)) + w_0 l, with
+  // w_0 = -2 sum_k w_k, instead of in difference form.
+  [[maybe_unused]] float c0l = 0.f;
+  if constexpr (DF) {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) c0l -= 2.f * (a.cz[k] + a.cx[k]);
+  }
   // ---- step 1: u^{n+1} on the tile plus a 4-cell halo --------------------
   {
     fold_sources<W1>(a.inj, logical, w, lane, ds1);
@@ -242,7 +251,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     // forward x-differences d[k][j] = u(j + k) - u(j): the backward one of
     // column j, u(j - k) - u(j), is -d[k][j - k] (exact), so each difference
     // along x is formed once
-    float dxf[kR][W1], dxl[kR][W1];
+    float dxf[kR][W1];
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
       const float *col = base + j * ROWS;
@@ -259,13 +268,11 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       if constexpr (DF) {
         const unsigned short *cll = basel + j * ROWS;
         cl = bf16_f32(cll[0]);
-        float lapl = 0.f;
+        float lapl = c0l * cl;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
-          dxl[k - 1][j] = bf16_f32(cll[k * ROWS]) - cl;
-          const float back = j >= k ? -dxl[k - 1][j - k] : bf16_f32(cll[-k * ROWS]) - cl;
-          lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * (back + dxl[k - 1][j]);
+          lapl += a.cz[k - 1] * (bf16_f32(cll[-k]) + bf16_f32(cll[k]));
+          lapl += a.cx[k - 1] * (bf16_f32(cll[-k * ROWS]) + bf16_f32(cll[k * ROWS]));
         }
         lap += lapl;
       }
@@ -342,7 +349,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       basel = &sh.l1[cb][lz];
       basel0 = &sh.l0[cb + kR][lz];
     }
-    float dxf[kR][W2], dxl[kR][W2];          // forward x-differences, as in step 1
+    float dxf[kR][W2];                       // forward x-differences, as in step 1
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
       const float *col = base + j * ROWS;
@@ -359,13 +366,11 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       if constexpr (DF) {
         const unsigned short *cll = basel + j * ROWS;
         cl = bf16_f32(cll[0]);
-        float lapl = 0.f;
+        float lapl = c0l * cl;
 #pragma unroll
         for (int k = 1; k <= kR; ++k) {
-          dxl[k - 1][j] = bf16_f32(cll[k * ROWS]) - cl;
-          const float back = j >= k ? -dxl[k - 1][j - k] : bf16_f32(cll[-k * ROWS]) - cl;
-          lapl += a.cz[k - 1] * ((bf16_f32(cll[-k]) - cl) + (bf16_f32(cll[k]) - cl));
-          lapl += a.cx[k - 1] * (back + dxl[k - 1][j]);
+          lapl += a.cz[k - 1] * (bf16_f32(cll[-k]) + bf16_f32(cll[k]));
+          lapl += a.cx[k - 1] * (bf16_f32(cll[-k * ROWS]) + bf16_f32(cll[k * ROWS]));
         }
         lap += lapl;
       }
@@ -440,6 +445,7 @@ hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles,
   switch (tile_x) {
     case 16: k_step2_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 32: k_step2_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 48: k_step2_multi<48><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 64: k_step2_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     default: return hipErrorInvalidValue;
   }
@@ -466,6 +472,7 @@ hipError_t launch_step2(const Step2Args &p, int tile_x, int mode, hipStream_t st
   switch (tile_x) {
     case 16: return launch_step2_tx<16>(p, mode, st);
     case 32: return launch_step2_tx<32>(p, mode, st);
+    case 48: return launch_step2_tx<48>(p, mode, st);
     case 64: return launch_step2_tx<64>(p, mode, st);
     default: return hipErrorInvalidValue;
   }

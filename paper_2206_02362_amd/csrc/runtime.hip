@@ -1757,7 +1757,7 @@ std::string batch_signature(int njobs, const fwime_job_t *jobs) {
 }
 
 int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStream_t st, int *best_tx) {
-  const int cand[3] = {16, 32, 64};
+  const int cand[4] = {16, 32, 48, 64};
   float best = 1e30f;
   *best_tx = ctx->tile_x;
   hipEvent_t e0, e1;
