@@ -148,7 +148,10 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
 
   // Own-row operands of both steps; their latency hides behind the tile load.
   // (the second step's operands are loaded after the first step, to keep the
-  // register footprint of the first step small)
+  // register footprint of the first step small).  They only feed cells whose
+  // results are stored, or zeroed when outside the grid, so they are read
+  // unconditionally at the nearest cell inside the grid: no guard, no branch.
+  const int vzc = min(max(z, 0), NZ - 1) * 4;                     // clamped row
   float pv[W1], vv1[W1], ds1[W1], pl[W1], gx1[W1];
   [[maybe_unused]] __amdgpu_buffer_rsrc_t r_ds1, r_lprev, r_lcur;
   if constexpr (DS) r_ds1 = rsrc(a.dsrc + (long)s * a.dsrc_sstride, FB);
@@ -158,16 +161,13 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   }
 #pragma unroll
   for (int j = 0; j < W1; ++j) {
-    const int x = xs1 + j;
-    const bool xin = x >= 0 && x < NX;
-    pv[j] = vv1[j] = ds1[j] = pl[j] = 0.f;
-    gx1[j] = a.gx[xin ? x : 0];
-    if (xin && zin) {
-      pv[j] = ld(r_prev, vz, x * CB);
-      vv1[j] = ld(r_V, vz, x * CB);
-      if constexpr (DS) ds1[j] = ld(r_ds1, vz, x * CB);
-      if constexpr (DF) pl[j] = bf16_f32(ld16(r_lprev, z * 2, x * (CB / 2)));
-    }
+    const int xc = min(max(xs1 + j, 0), NX - 1);                 // clamped column
+    gx1[j] = a.gx[xc];
+    pv[j] = ld(r_prev, vzc, xc * CB);
+    vv1[j] = ld(r_V, vzc, xc * CB);
+    ds1[j] = pl[j] = 0.f;
+    if constexpr (DS) ds1[j] = ld(r_ds1, vzc, xc * CB);
+    if constexpr (DF) pl[j] = bf16_f32(ld16(r_lprev, vzc / 2, xc * (CB / 2)));
   }
   const float gzv = zin ? a.gz[z] : 0.f;
   if constexpr (NU) {
@@ -175,13 +175,12 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     // (k-1, k, k+1) on the halo, step 2 slots (k-2, k-1, k) on the tile
     const long so = (long)s * a.nu.sstride;
     const auto rm = rsrc(a.nu.em + so, FB), r0 = rsrc(a.nu.e0 + so, FB), rp = rsrc(a.nu.ep + so, FB);
+    const float gzc = a.gz[vzc / 4];         // taper at the clamped row (nonzero)
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
-      const int x = xs1 + j;
-      if (x >= 0 && x < NX && zin) {
-        const float g = gzv * a.gx[x];
-        ds1[j] += ld(rm, vz, x * CB) / g - 2.f * ld(r0, vz, x * CB) + g * ld(rp, vz, x * CB);
-      }
+      const int xc = min(max(xs1 + j, 0), NX - 1);
+      const float g = gzc * gx1[j];
+      ds1[j] += ld(rm, vzc, xc * CB) / g - 2.f * ld(r0, vzc, xc * CB) + g * ld(rp, vzc, xc * CB);
     }
   }
 
@@ -315,25 +314,21 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     float vv2[W2], ds2[W2], gx2[W2];
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
-      const int x = xs2 + j;
-      const bool xin = x < NX;
-      vv2[j] = ds2[j] = 0.f;
-      gx2[j] = a.gx[xin ? x : 0];
-      if (xin && zin) {
-        vv2[j] = ld(r_V, vz, x * CB);
-        if constexpr (DS) ds2[j] = ld(rsrc(p.dsrc2 + (long)s * a.dsrc_sstride, FB), vz, x * CB);
-      }
+      const int xc = min(xs2 + j, NX - 1);                         // as in step 1
+      gx2[j] = a.gx[xc];
+      vv2[j] = ld(r_V, vzc, xc * CB);
+      ds2[j] = 0.f;
+      if constexpr (DS) ds2[j] = ld(rsrc(p.dsrc2 + (long)s * a.dsrc_sstride, FB), vzc, xc * CB);
     }
     if constexpr (NU) {
       const long so = (long)s * a.nu.sstride;
       const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
+      const float gzc = a.gz[vzc / 4];
 #pragma unroll
       for (int j = 0; j < W2; ++j) {
-        const int x = xs2 + j;
-        if (x < NX && zin) {
-          const float g = gzv * a.gx[x];
-          ds2[j] += ld(rm2, vz, x * CB) / g - 2.f * ld(r02, vz, x * CB) + g * ld(rp2, vz, x * CB);
-        }
+        const int xc = min(xs2 + j, NX - 1);
+        const float g = gzc * gx2[j];
+        ds2[j] += ld(rm2, vzc, xc * CB) / g - 2.f * ld(r02, vzc, xc * CB) + g * ld(rp2, vzc, xc * CB);
       }
     }
     fold_sources<W2>(p.inj2, logical, w, lane, ds2);
