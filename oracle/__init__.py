@@ -31,4 +31,6 @@ from .fd import (  # noqa: F401
     born_ext_adj,
     objective,
     gradient,
+    vp_objective,
+    vp_solve,
 )

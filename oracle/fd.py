@@ -511,3 +511,52 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
     grad_pt = img_scaled + eps ** 2 * (dso ** 2)[:, None, None] * ptilde
     obj = misfit + 0.5 * eps ** 2 * float(np.sum((dso[:, None, None] * ptilde) ** 2))
     return obj, grad_vel, grad_pt
+
+
+# ----------------------------------------------------------------------------
+# Variable-projection step (eqs. vp.obj, pert.opt, vp.pseudo.inv)
+# ----------------------------------------------------------------------------
+
+def vp_objective(g: Grid, vel, geom: Geometry, ptilde, dres, eps: float, dso) -> float:
+    """Phi_eps,m(p~) = 1/2 || B~ p~ - dres ||^2 + eps^2/2 || D p~ ||^2, dres = d_obs - f(m) (eq. vp.obj)."""
+    r = born_ext_fwd(g, vel, geom, ptilde) - np.asarray(dres, dtype=np.float64)
+    dso = np.asarray(dso, dtype=np.float64)
+    return 0.5 * float(np.sum(r * r)) + 0.5 * eps ** 2 * float(np.sum((dso[:, None, None] * ptilde) ** 2))
+
+
+def vp_solve(g: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
+    """Variable-projection step by linear conjugate gradient.
+
+    The minimizer of eq. vp.obj solves the normal equation
+    (B~* B~ + eps^2 D* D) p~ = B~* (d_obs - f(m)) (eqs. pert.opt and
+    vp.pseudo.inv); Section 2 minimizes it with linear conjugate gradient.
+    Here: plain CG on that symmetric system from p~ = 0, niter iterations
+    (stopping early only if the search direction has zero curvature).
+    Returns p~ and Phi_eps,m at p~_0 = 0, p~_1, ..., each evaluated from its
+    definition (one extra application of B~ per iterate).
+    """
+    dres = np.asarray(dobs, dtype=np.float64) - model(g, vel, geom)
+    d2 = (eps * np.asarray(dso, dtype=np.float64)) ** 2
+
+    def normal(x):
+        return born_ext_adj(g, vel, geom, born_ext_fwd(g, vel, geom, x), nh) + d2[:, None, None] * x
+
+    b = born_ext_adj(g, vel, geom, dres, nh)
+    p = np.zeros_like(b)
+    r = b.copy()
+    s = r.copy()
+    rr = float(np.sum(r * r))
+    phis = [0.5 * float(np.sum(dres * dres))]
+    for _ in range(niter):
+        q = normal(s)
+        curv = float(np.sum(s * q))
+        if curv <= 0.0:
+            break
+        alpha = rr / curv
+        p = p + alpha * s
+        r = r - alpha * q
+        rr_new = float(np.sum(r * r))
+        s = r + (rr_new / rr) * s
+        rr = rr_new
+        phis.append(vp_objective(g, vel, geom, p, dres, eps, dso))
+    return p, phis
