@@ -119,6 +119,27 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                    const float *dobs, double eps, const double *dso,
                    double *obj, float *grad_vel, float *grad_ptilde, void *stream);
 
+/* Variable-projection step of FWIME (Section 2, eqs. vp.obj, pert.opt and
+ * vp.pseudo.inv): niter iterations of linear conjugate gradient on the normal
+ * equation (B~* B~ + eps^2 D* D) p~ = B~* (dobs - f(m)), starting from p~ = 0,
+ * where D is the diagonal DSO operator with weight dso[h] on offset plane h.
+ * Each iteration applies B~ and B~* once (four propagations per shot).
+ * dobs: DEVICE [nshots][nrec][nt]; dso: HOST double [nh];
+ * ptilde_out: DEVICE [nh][nx][nz], the last iterate;
+ * phi_out: HOST double [niter + 1], the objective of eq. vp.obj at p~_0 = 0
+ * and after each iteration (tracked from the CG residual, no extra
+ * propagations).  If a search direction has no positive curvature the
+ * iteration stops and the remaining phi_out entries repeat the last value.
+ * The call synchronizes `stream` once per inner product.  The solver's
+ * vectors (4 model-size and 2 data-size arrays) stay in the context until
+ * fwime_ctx_trim or fwime_ctx_destroy, and count against its HBM budget.
+ * Argument errors (FWIME_EINVAL) are reported before anything is written; a
+ * failure during the iteration leaves ptilde_out and phi_out unspecified. */
+int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                   const fwime_geom_t *geom, int32_t nh, const float *dobs, double eps,
+                   const double *dso, int32_t niter, float *ptilde_out, double *phi_out,
+                   void *stream);
+
 /* ---- Batched modeling of jobs with different grids ----------------------
  * One job = one call's worth of fwime_model (grid, velocity, shots).  All
  * jobs advance together: every time step is one launch over the tiles of all

@@ -226,4 +226,17 @@ hipError_t launch_grad_finalize(const float *gacc, const float *V, const float *
 hipError_t launch_objective(const double *sumsq, const float *ptilde, const float *eps2d2, const ExtGeom &g,
                             double *obj, hipStream_t st);
 
+// Vector kernels of the variable-projection solver (kernels_vec.hip).
+// out = a - b
+hipError_t launch_sub(const float *a, const float *b, float *out, long n, hipStream_t st);
+// *out = sum_i x[i] y[i] in FP64, fixed reduction order; part holds dot_partials() doubles
+hipError_t launch_dot(const float *x, const float *y, long n, double *part, double *out, hipStream_t st);
+int dot_partials();
+// p += alpha s, r -= alpha q
+hipError_t launch_cg_step(float *p, float *r, const float *s, const float *q, float alpha, long n, hipStream_t st);
+// s = r + beta s
+hipError_t launch_cg_dir(float *s, const float *r, float beta, long n, hipStream_t st);
+// q[h] += e2d2[h] s[h] per offset plane of `plane` cells
+hipError_t launch_add_diag(float *q, const float *s, const float *e2d2, long plane, int nh, hipStream_t st);
+
 }  // namespace fw

@@ -46,6 +46,8 @@ struct fwime_ctx {
   int graph_steps = 64;                   // steps per captured graph
   hipGraph_t graph = nullptr;             // last batch graph, released after the
   hipGraphExec_t graph_exec = nullptr;    // next stream synchronization
+  void *vp = nullptr;                     // variable-projection solver vectors
+  size_t vp_bytes = 0;
 };
 
 static void release_graph(fwime_ctx_t *ctx) {
@@ -112,6 +114,14 @@ struct Carve {
     size_t bytes = (count * sizeof(T) + 255) / 256 * 256;
     items.push_back({(void **)p, bytes});
     total += bytes;
+  }
+  // point every piece into `base` (at least `total` bytes)
+  void assign(void *base) const {
+    char *p = (char *)base;
+    for (const auto &it : items) {
+      *it.first = p;
+      p += it.second;
+    }
   }
 };
 
@@ -752,6 +762,9 @@ int fwime_ctx_trim(fwime_ctx_t *ctx, void *stream) {
   ctx->arena = nullptr;
   ctx->arena_bytes = 0;
   ctx->last_arena_request = 0;
+  if (ctx->vp && hipFree(ctx->vp) != hipSuccess) return FWIME_EHIP;
+  ctx->vp = nullptr;
+  ctx->vp_bytes = 0;
   return FWIME_OK;
 }
 
@@ -772,6 +785,7 @@ void fwime_ctx_destroy(fwime_ctx_t *ctx) {
   release_graph(ctx);
   if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->vp) (void)hipFree(ctx->vp);
   if (ctx->host_red) (void)hipHostFree(ctx->host_red);
   delete ctx;
 }
@@ -1349,6 +1363,112 @@ struct fwime_tape {
 extern "C" {
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Variable-projection step (eqs. vp.obj, pert.opt, vp.pseudo.inv): linear
+// conjugate gradient on (B~* B~ + eps^2 D* D) p~ = B~* (d_obs - f(m)) from
+// p~ = 0.  Each iteration applies B~ and B~* once (four propagations per
+// shot); the objective is tracked without further propagations as
+// Phi_k = 1/2 ||d_obs - f(m)||^2 - 1/2 (b + r_k) . p~_k, which holds for any
+// p~ with r = b - H p~ (b = B~* (d_obs - f(m)), H the normal matrix).
+int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                   int32_t nh, const float *dobs, double eps, const double *dso, int32_t niter,
+                   float *ptilde_out, double *phi_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if (!dobs || !dso || !ptilde_out || !phi_out) return set_err(ctx, FWIME_EINVAL, "null pointer argument");
+  if (niter < 0) return set_err(ctx, FWIME_EINVAL, "niter must be >= 0");
+  if (!std::isfinite(eps)) return set_err(ctx, FWIME_EINVAL, "eps must be finite");
+  for (int h = 0; h < nh; ++h)
+    if (!std::isfinite(dso[h])) return set_err(ctx, FWIME_EINVAL, "dso must be finite");
+  HIPCHK(hipSetDevice(ctx->device));
+  const long ndata = (long)geo->nshots * geo->nrec * g->nt;
+  const long plane = (long)g->nx * g->nz;
+  const long img = (long)nh * plane;
+  if ((rc = check_inputs(ctx, g, vel, geo, {{dobs, ndata}}, st))) return rc;
+
+  // solver vectors, kept in the context between calls
+  float *r = nullptr, *sdir = nullptr, *q = nullptr, *b = nullptr, *dres = nullptr, *dtmp = nullptr,
+        *e2d2 = nullptr;
+  double *part = nullptr, *res = nullptr;
+  Carve cv;
+  cv.add(&r, img);
+  cv.add(&sdir, img);
+  cv.add(&q, img);
+  cv.add(&b, img);
+  cv.add(&dres, ndata);
+  cv.add(&dtmp, ndata);
+  cv.add(&e2d2, nh);
+  cv.add(&part, dot_partials());
+  cv.add(&res, 1);
+  if (cv.total > ctx->vp_bytes) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->vp) HIPCHK(hipFree(ctx->vp));
+    ctx->vp = nullptr;
+    ctx->vp_bytes = 0;
+    if (hipMalloc(&ctx->vp, cv.total) != hipSuccess) {
+      ctx->vp = nullptr;
+      (void)hipGetLastError();
+      return set_err(ctx, FWIME_ENOMEM, "cannot allocate the solver vectors");
+    }
+    ctx->vp_bytes = cv.total;
+  }
+  cv.assign(ctx->vp);
+  // the operators below size their shot batches from what is left of the budget
+  struct BudgetGuard {
+    fwime_ctx_t *c;
+    size_t saved;
+    ~BudgetGuard() { c->budget = saved; }
+  } guard{ctx, ctx->budget};
+  if (ctx->budget) ctx->budget = ctx->budget > ctx->vp_bytes ? ctx->budget - ctx->vp_bytes : 1;
+
+  auto dot = [&](const float *x, const float *y, long n, double &out) -> int {
+    HIPCHK(launch_dot(x, y, n, part, res, st));
+    HIPCHK(hipMemcpyAsync(ctx->host_red, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out = ctx->host_red[0];
+    return FWIME_OK;
+  };
+  std::vector<float> e2(nh);
+  for (int h = 0; h < nh; ++h) e2[h] = (float)(eps * eps * dso[h] * dso[h]);
+  HIPCHK(hipMemcpyAsync(e2d2, e2.data(), nh * sizeof(float), hipMemcpyHostToDevice, st));
+
+  // residual of the background model and the right-hand side
+  if ((rc = fwime_model(ctx, g, vel, geo, dtmp, stream))) return rc;
+  HIPCHK(launch_sub(dobs, dtmp, dres, ndata, st));
+  double c0 = 0.0, rr = 0.0;
+  if ((rc = dot(dres, dres, ndata, c0))) return rc;
+  c0 *= 0.5;
+  if ((rc = fwime_born_ext_adj(ctx, g, vel, geo, nh, dres, b, stream))) return rc;
+  HIPCHK(hipMemsetAsync(ptilde_out, 0, img * sizeof(float), st));
+  HIPCHK(hipMemcpyAsync(r, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(sdir, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if ((rc = dot(r, r, img, rr))) return rc;
+  phi_out[0] = c0;
+  int k = 0;
+  for (; k < niter; ++k) {
+    // q = (B~* B~ + eps^2 D* D) s
+    if ((rc = fwime_born_ext_fwd(ctx, g, vel, geo, nh, sdir, dtmp, stream))) return rc;
+    if ((rc = fwime_born_ext_adj(ctx, g, vel, geo, nh, dtmp, q, stream))) return rc;
+    HIPCHK(launch_add_diag(q, sdir, e2d2, plane, nh, st));
+    double curv = 0.0;
+    if ((rc = dot(sdir, q, img, curv))) return rc;
+    if (!(curv > 0.0) || !std::isfinite(curv)) break;    // no curvature left along s: p~ is final
+    const double alpha = rr / curv;
+    HIPCHK(launch_cg_step(ptilde_out, r, sdir, q, (float)alpha, img, st));
+    double rr_new = 0.0, bp = 0.0, rp = 0.0;
+    if ((rc = dot(r, r, img, rr_new)) || (rc = dot(b, ptilde_out, img, bp)) || (rc = dot(r, ptilde_out, img, rp)))
+      return rc;
+    phi_out[k + 1] = c0 - 0.5 * (bp + rp);
+    HIPCHK(launch_cg_dir(sdir, r, (float)(rr_new / rr), img, st));
+    rr = rr_new;
+  }
+  for (int j = k + 1; j <= niter; ++j) phi_out[j] = phi_out[k];
+  return FWIME_OK;
+}
+
 int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo, int32_t nh,
                    const float *ptilde, const float *dobs, double eps, const double *dso, double *obj,
                    float *grad_vel, float *grad_ptilde, void *stream) {

@@ -1,0 +1,96 @@
+"""Variable-projection step on the GPU (fwime_vp_solve) against the oracle.
+
+The iterates of linear conjugate gradient on the normal equation of eq.
+vp.obj and the objective history must match the FP64 oracle's CG to 1e-4
+relative (the trace/image tolerance), with eps = 0 (the paper's first
+variable-projection step) and with a DSO penalty.  At the benchmark's full
+size (300 x 1700, 100 shots, nt = 5000, nh = 61), where the oracle cannot
+run, the objective must decrease at every iteration (a property of CG on a
+symmetric positive semi-definite system).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _helpers import gpu_problem, oracle_problem_f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2206_02362_amd as fw
+    c = fw.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda:0")
+
+
+def _case():
+    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5, seed=31)
+    g, geo, vel = oracle_problem_f32(w)
+    true = vel * (1.0 + 0.04 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 32, 60.0))
+    dobs = oracle.model(g, true, geo).astype(np.float32)
+    return w, g, geo, vel, dobs
+
+
+@pytest.mark.parametrize("penalty", [False, True])
+def test_vp_solve_matches_oracle(ctx, penalty):
+    w, g, geo, vel, dobs = _case()
+    dso = synth.dso_weights(w.nh)
+    eps = 0.0
+    if penalty:
+        # a penalty of the order of the normal matrix's scale along b = B~* dres
+        dres = dobs.astype(np.float64) - oracle.model(g, vel, geo)
+        b = oracle.born_ext_adj(g, vel, geo, dres, w.nh)
+        hb = oracle.born_ext_adj(g, vel, geo, oracle.born_ext_fwd(g, vel, geo, b), w.nh)
+        eps = float(np.sqrt(0.3 * np.sum(b * hb) / np.sum(b * b)))
+    niter = 4
+    say(f"case: vp_solve 24x32 nb8 nt160 nh5, eps {eps:.3e}, {niter} iterations")
+    p_ref, phi_ref = oracle.vp_solve(g, vel, geo, dobs.astype(np.float64), w.nh, eps, dso, niter)
+    grid, tv, tg = gpu_problem(w)
+    p, phi = ctx.vp_solve(grid, tv, tg, _dev(dobs), w.nh, eps, dso, niter)
+    e_p = rel_l2(p.double().cpu().numpy(), p_ref)
+    e_phi = max(abs(a - b) / abs(b) for a, b in zip(phi, phi_ref))
+    say("  rel-L2 p~", e_p, "objective", e_phi, "phi", list(phi))
+    assert len(phi_ref) == niter + 1
+    assert e_p < TOL and e_phi < TOL
+    assert all(b <= a for a, b in zip(phi, phi[1:]))
+
+
+def test_vp_solve_deterministic_and_zero_iterations(ctx):
+    w, g, geo, vel, dobs = _case()
+    grid, tv, tg = gpu_problem(w)
+    dso = synth.dso_weights(w.nh)
+    d = _dev(dobs)
+    p1, phi1 = ctx.vp_solve(grid, tv, tg, d, w.nh, 0.0, dso, 2)
+    p2, phi2 = ctx.vp_solve(grid, tv, tg, d, w.nh, 0.0, dso, 2)
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy()) and np.array_equal(phi1, phi2)
+    p0, phi0 = ctx.vp_solve(grid, tv, tg, d, w.nh, 0.0, dso, 0)
+    assert not p0.abs().max().item() and phi0[0] == phi1[0]
+
+
+def test_vp_solve_full_size_decreases(ctx):
+    import torch
+    w = synth.marmousi_set(100, 17)
+    say("case: vp_solve 300x1700, 100 shots, nt 5000, nh 61, 3 iterations")
+    grid, tv, tg = gpu_problem(w)
+    true = torch.tensor(w.vel * (1.0 + 0.03 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 33, 300.0)),
+                        dtype=torch.float32, device="cuda:0")
+    dobs = ctx.model(grid, true, tg)
+    p, phi = ctx.vp_solve(grid, tv, tg, dobs, w.nh, 0.0, synth.dso_weights(w.nh), 3)
+    say("  phi", list(phi))
+    assert np.all(np.isfinite(phi)) and torch.isfinite(p).all().item()
+    assert all(b < a for a, b in zip(phi, phi[1:]))
