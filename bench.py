@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--no-batch-compare", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16, help="requests in the serving replay (0: skip)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving replay")
+    ap.add_argument("--vp-iters", type=int, default=2,
+                    help="CG iterations of the variable-projection step to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -333,6 +335,30 @@ def main():
     if not args.no_batch_compare:
         batch = batch_compare(ctx)
 
+    vp = None
+    if args.vp_iters > 0:
+        # variable-projection step (eq. vp.obj): model + B~* once, then B~ and
+        # B~* per CG iteration; timed as a whole and per iteration
+        outs.clear()
+        log(f"variable-projection step: {args.vp_iters} CG iterations")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, phi = ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, 0)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t
+        t = time.perf_counter()
+        _, phi = ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, args.vp_iters)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t
+        per_iter = (t_all - t_setup) / args.vp_iters
+        vp = {"iterations": args.vp_iters, "eps": 0.0, "s_total": t_all, "s_setup": t_setup,
+              "s_per_iteration": per_iter,
+              "cell_updates_per_s": 4 * per_prop / per_iter,
+              "note": "setup = f(m) and B~* once (3 propagations/shot); each CG iteration = B~ + B~* "
+                      "(4 propagations/shot counted)",
+              "objective": [float(x) for x in phi]}
+        log(f"vp: {per_iter:.2f} s per CG iteration, objective {vp['objective']}")
+
     serving = None
     if args.serve_requests > 0:
         # give the device memory of the step back to the server's budget
@@ -367,6 +393,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
+        "vp_step": vp,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
