@@ -213,6 +213,7 @@ hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, c
   const dim3 grid((unsigned)(per * 8));
   switch (tile_x) {
     case 16: k_step_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 24: k_step_multi<24><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 32: k_step_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 48: k_step_multi<48><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 64: k_step_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
@@ -226,7 +227,7 @@ hipError_t launch_bump(int *step, int by, hipStream_t st) {
   return hipGetLastError();
 }
 
-int step_tile_x_supported(int tx) { return tx == 16 || tx == 32 || tx == 48 || tx == 64; }
+int step_tile_x_supported(int tx) { return tx == 16 || tx == 24 || tx == 32 || tx == 48 || tx == 64; }
 
 template <int TX>
 static hipError_t launch_step_tx(const StepArgs &a, int mode, hipStream_t st) {
@@ -247,6 +248,7 @@ static hipError_t launch_step_tx(const StepArgs &a, int mode, hipStream_t st) {
 hipError_t launch_step(const StepArgs &a, int tile_x, int mode, hipStream_t st) {
   switch (tile_x) {
     case 16: return launch_step_tx<16>(a, mode, st);
+    case 24: return launch_step_tx<24>(a, mode, st);
     case 32: return launch_step_tx<32>(a, mode, st);
     case 48: return launch_step_tx<48>(a, mode, st);
     case 64: return launch_step_tx<64>(a, mode, st);

@@ -439,6 +439,7 @@ hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles,
   const dim3 grid((unsigned)(per * 8));
   switch (tile_x) {
     case 16: k_step2_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 24: k_step2_multi<24><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 32: k_step2_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 48: k_step2_multi<48><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
     case 64: k_step2_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
@@ -466,6 +467,7 @@ static hipError_t launch_step2_tx(const Step2Args &p, int mode, hipStream_t st) 
 hipError_t launch_step2(const Step2Args &p, int tile_x, int mode, hipStream_t st) {
   switch (tile_x) {
     case 16: return launch_step2_tx<16>(p, mode, st);
+    case 24: return launch_step2_tx<24>(p, mode, st);
     case 32: return launch_step2_tx<32>(p, mode, st);
     case 48: return launch_step2_tx<48>(p, mode, st);
     case 64: return launch_step2_tx<64>(p, mode, st);

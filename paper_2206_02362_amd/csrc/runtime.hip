@@ -1877,7 +1877,7 @@ std::string batch_signature(int njobs, const fwime_job_t *jobs) {
 }
 
 int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStream_t st, int *best_tx) {
-  const int cand[4] = {16, 32, 48, 64};
+  const int cand[5] = {16, 24, 32, 48, 64};
   float best = 1e30f;
   *best_tx = ctx->tile_x;
   hipEvent_t e0, e1;

@@ -72,13 +72,13 @@ def test_model_plain_small(ctx):
 def test_model_tile_widths_bitwise(ctx):
     # The per-cell arithmetic does not depend on the tile shape.
     import paper_2206_02362_amd as fw
-    say("case: model tile widths 16/32/48/64")
+    say("case: model tile widths 16/24/32/48/64")
     w = synth.tiny(nz=70, nx=90, nb=6, nt=120, nshots=2)
     grid, tv, tg = gpu_problem(w)
     outs = []
     old = os.environ.get("FWIME_TILE_X")
     try:
-        for tx in ("16", "32", "48", "64"):
+        for tx in ("16", "24", "32", "48", "64"):
             os.environ["FWIME_TILE_X"] = tx
             c = fw.Context(0)
             outs.append(t2n(c.model(grid, tv, tg)))

@@ -60,7 +60,7 @@ def _boundary_workload(nt, tile_x, seed):
     return w
 
 
-@pytest.mark.parametrize("tile_x", [16, 32, 48, 64])
+@pytest.mark.parametrize("tile_x", [16, 24, 32, 48, 64])
 @pytest.mark.parametrize("nt", [201, 202])
 def test_two_step_model_bitwise(tile_x, nt):
     say(f"case: two-step vs one-step model, TX {tile_x}, nt {nt}")
