@@ -133,6 +133,12 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
  * The call synchronizes `stream` once per inner product.  The solver's
  * vectors (4 model-size and 2 data-size arrays) stay in the context until
  * fwime_ctx_trim or fwime_ctx_destroy, and count against its HBM budget.
+ * When they fit in half of the free memory (and of the budget), the
+ * background checkpoints of every shot (6 bytes x 2 ceil((nt-1)/K) padded
+ * fields per shot, K = ceil(sqrt(nt))) are kept for the whole call, so each
+ * B~* after the first skips its background forward pass; the results are the
+ * same bit for bit either way (FWIME_VP_NOCACHE=1 in the environment turns
+ * the cache off).
  * Argument errors (FWIME_EINVAL) are reported before anything is written; a
  * failure during the iteration leaves ptilde_out and phi_out unspecified. */
 int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,

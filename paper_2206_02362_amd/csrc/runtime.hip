@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -970,8 +971,26 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
 }
 
 // ---------------------------------------------------------------------------
+// Background checkpoints of the extended-precision adjoint kept across calls
+// with the same model and shots (the variable-projection step): per shot
+// 2 nseg fields (FP32 and BF16 low parts) in shot order.  `valid` once a call
+// has filled them; later calls skip their forward pass.
+struct AdjCache {
+  float *ckpt = nullptr;
+  unsigned short *ckpt_lo = nullptr;
+  bool valid = false;
+};
+
+static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                            int32_t nh, const float *data, float *ptilde_out, void *stream, AdjCache *cache);
+
 int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
                        int32_t nh, const float *data, float *ptilde_out, void *stream) {
+  return born_ext_adj_run(ctx, g, vel, geo, nh, data, ptilde_out, stream, nullptr);
+}
+
+static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                            int32_t nh, const float *data, float *ptilde_out, void *stream, AdjCache *cache) {
   if (!ctx) return FWIME_EINVAL;
   ctx->err.clear();
   hipStream_t st = (hipStream_t)stream;
@@ -990,8 +1009,11 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   const int R = K + 2;
   const bool two = ctx->two_step;
   const int nf = two ? 4 : 2;
+  if (!two) cache = nullptr;                    // the one-step path recomputes inside its checkpoints
   // two-step path: BF16 low parts of the four work fields and the checkpoints
-  const long per_shot = (nf + 2L * nseg + K + R + (two ? 2L + nseg : 0L)) * d.field * 4 + (long)geo->nrec * 64;
+  // (cached checkpoints live outside the arena)
+  const long ck_fields = cache ? 0L : 2L * nseg + (two ? nseg : 0L);
+  const long per_shot = (nf + K + R + (two ? 2L : 0L) + ck_fields) * d.field * 4 + (long)geo->nrec * 64;
   const long img = (long)nh * d.nx * d.nz;
   const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4 * (1 + kImageGroups);
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
@@ -1009,10 +1031,10 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   cv.add(&acc, img);
   cv.add(&parts, kImageGroups * img);
   cv.add(&pairs, nf * d.field * S);
-  cv.add(&ckpt, 2L * nseg * d.field * S);
+  if (!cache) cv.add(&ckpt, 2L * nseg * d.field * S);
   if (two) {
     cv.add(&lows, 4 * d.field * S);
-    cv.add(&ckpt_lo, 2L * nseg * d.field * S);
+    if (!cache) cv.add(&ckpt_lo, 2L * nseg * d.field * S);
   }
   cv.add(&t2, (long)K * d.field * S);
   cv.add(&ring, (long)R * d.field * S);
@@ -1031,13 +1053,17 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
     if (two) {
       const float *wav_b = geo->wavelet + (long)s0 * g->nt;
       auto src = [&](Step2Args &p, int n, int) { with_src2(p, t, wav_b, g, n); };
+      if (cache) {                              // this batch's shots in the cached checkpoints
+        ckpt = cache->ckpt + (long)s0 * ck_stride;
+        ckpt_lo = cache->ckpt_lo + (long)s0 * ck_stride;
+      }
       // forward pass (extended precision) storing (u^{n0-1}, u^{n0}) at every
-      // segment start
+      // segment start, unless the cached checkpoints already hold them
       HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
       HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
       Ring4 fu(pairs, d.field * Sb);
       Ring4L lu(lows, d.field * Sb);
-      for (int j = 0; j < nseg; ++j) {
+      for (int j = 0; j < nseg && !(cache && cache->valid); ++j) {
         const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1);
         HIPCHK(launch_copy_fields(ckpt + (2L * j) * d.field, ck_stride, fu.prev(), d.field, Sb, d.field, st));
         HIPCHK(launch_copy_fields(ckpt + (2L * j + 1) * d.field, ck_stride, fu.cur(), d.field, Sb, d.field, st));
@@ -1116,6 +1142,7 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
     }
   }
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, ptilde_out, st));
+  if (cache) cache->valid = true;
   return FWIME_OK;
 }
 
@@ -1389,11 +1416,33 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   const long img = (long)nh * plane;
   if ((rc = check_inputs(ctx, g, vel, geo, {{dobs, ndata}}, st))) return rc;
 
+  // the background does not change during the step: the extended-precision
+  // adjoint's checkpoints (2 nseg fields and their low parts per shot) are
+  // kept for all shots when they fit, so every B~* after the first skips its
+  // forward pass (FWIME_VP_NOCACHE=1 turns this off)
+  const Dims dd = make_dims(g, ctx->tile_x);
+  const int K = seg_len(g->nt);
+  const long nseg = (g->nt - 1 + K - 1) / K;
+  const long ck_elems = 2L * nseg * dd.field * geo->nshots;
+  bool use_cache = ctx->two_step;
+  if (const char *e = std::getenv("FWIME_VP_NOCACHE")) use_cache = use_cache && std::atoi(e) == 0;
+  if (use_cache) {
+    size_t avail = 0, total = 0;
+    if (hipMemGetInfo(&avail, &total) != hipSuccess) avail = 0;
+    // the solver's own buffer (possibly already holding a cache) counts as free here
+    const size_t need = (size_t)ck_elems * 6;
+    use_cache = need < (size_t)((avail + ctx->vp_bytes) * 0.5) && (!ctx->budget || need < ctx->budget / 2);
+  }
   // solver vectors, kept in the context between calls
   float *r = nullptr, *sdir = nullptr, *q = nullptr, *b = nullptr, *dres = nullptr, *dtmp = nullptr,
         *e2d2 = nullptr;
   double *part = nullptr, *res = nullptr;
+  AdjCache cache;
   Carve cv;
+  if (use_cache) {
+    cv.add(&cache.ckpt, ck_elems);
+    cv.add(&cache.ckpt_lo, ck_elems);
+  }
   cv.add(&r, img);
   cv.add(&sdir, img);
   cv.add(&q, img);
@@ -1441,7 +1490,8 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   double c0 = 0.0, rr = 0.0;
   if ((rc = dot(dres, dres, ndata, c0))) return rc;
   c0 *= 0.5;
-  if ((rc = fwime_born_ext_adj(ctx, g, vel, geo, nh, dres, b, stream))) return rc;
+  AdjCache *cp = use_cache ? &cache : nullptr;
+  if ((rc = born_ext_adj_run(ctx, g, vel, geo, nh, dres, b, stream, cp))) return rc;
   HIPCHK(hipMemsetAsync(ptilde_out, 0, img * sizeof(float), st));
   HIPCHK(hipMemcpyAsync(r, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(sdir, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -1451,7 +1501,7 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   for (; k < niter; ++k) {
     // q = (B~* B~ + eps^2 D* D) s
     if ((rc = fwime_born_ext_fwd(ctx, g, vel, geo, nh, sdir, dtmp, stream))) return rc;
-    if ((rc = fwime_born_ext_adj(ctx, g, vel, geo, nh, dtmp, q, stream))) return rc;
+    if ((rc = born_ext_adj_run(ctx, g, vel, geo, nh, dtmp, q, stream, cp))) return rc;
     HIPCHK(launch_add_diag(q, sdir, e2d2, plane, nh, st));
     double curv = 0.0;
     if ((rc = dot(sdir, q, img, curv))) return rc;

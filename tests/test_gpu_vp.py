@@ -82,6 +82,18 @@ def test_vp_solve_deterministic_and_zero_iterations(ctx):
     assert not p0.abs().max().item() and phi0[0] == phi1[0]
 
 
+def test_vp_solve_checkpoint_cache_is_exact(ctx, monkeypatch):
+    # the cached background checkpoints give the same iterates bit for bit
+    w, g, geo, vel, dobs = _case()
+    grid, tv, tg = gpu_problem(w)
+    dso = synth.dso_weights(w.nh)
+    d = _dev(dobs)
+    p1, phi1 = ctx.vp_solve(grid, tv, tg, d, w.nh, 1e-4, dso, 3)
+    monkeypatch.setenv("FWIME_VP_NOCACHE", "1")
+    p2, phi2 = ctx.vp_solve(grid, tv, tg, d, w.nh, 1e-4, dso, 3)
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy()) and np.array_equal(phi1, phi2)
+
+
 def test_vp_solve_full_size_decreases(ctx):
     import torch
     w = synth.marmousi_set(100, 17)
