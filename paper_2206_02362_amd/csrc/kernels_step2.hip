@@ -185,32 +185,44 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   }
 
   // u^n tile, one column per wavefront access: lane = row z0 - 8 + lane, and
-  // lanes 0..7 also row z0 + 56 + lane
+  // lanes 0..7 also row z0 + 56 + lane.  No branch: a cell outside the grid
+  // gets a per-lane offset past the end of the buffer (the whole offset is in
+  // the per-lane register, which the range check covers), so it reads as
+  // zero, and every load of the tile is in flight before the first LDS write
+  // waits for one.
   {
+    constexpr int NC = C0 / kWaves;
+    constexpr int kOut = (int)0x80000000u;    // beyond any field (FB < 2^31)
     const int zt = z0 - 2 * kR + lane;
     const bool zt_in = zt >= 0 && zt < NZ;
     const bool zt2_in = lane < 2 * kR && zt + 64 < NZ;
+    float v[NC], v2[NC];
+    [[maybe_unused]] unsigned short l[NC], l2[NC];
 #pragma unroll
-    for (int i = 0; i < C0 / kWaves; ++i) {
-      const int c = w + kWaves * i;
-      const int x = x0 - 2 * kR + c;
-      float v = 0.f, v2 = 0.f;
-      unsigned short l = 0, l2 = 0;
-      if (x >= 0 && x < NX) {
-        if (zt_in) {
-          v = ld(r_cur, zt * 4, x * CB);
-          if constexpr (DF) l = ld16(r_lcur, zt * 2, x * (CB / 2));
-        }
-        if (zt2_in) {
-          v2 = ld(r_cur, (zt + 64) * 4, x * CB);
-          if constexpr (DF) l2 = ld16(r_lcur, (zt + 64) * 2, x * (CB / 2));
-        }
+    for (int i = 0; i < NC; ++i) {
+      const int x = x0 - 2 * kR + w + kWaves * i;
+      const bool xin = x >= 0 && x < NX;      // wave-uniform
+      const int o1 = xin && zt_in ? x * CB + zt * 4 : kOut;
+      const int o2 = xin && zt2_in ? x * CB + (zt + 64) * 4 : kOut;
+      v[i] = ld(r_cur, o1, 0);
+      v2[i] = ld(r_cur, o2, 0);
+      if constexpr (DF) {
+        l[i] = ld16(r_lcur, o1 == kOut ? kOut : o1 / 2, 0);
+        l2[i] = ld16(r_lcur, o2 == kOut ? kOut : o2 / 2, 0);
       }
-      sh.u0[c][lane] = v;
-      if constexpr (DF) sh.l0[c][lane] = l;
-      if (lane < 2 * kR) {
-        sh.u0[c][64 + lane] = v2;
-        if constexpr (DF) sh.l0[c][64 + lane] = l2;
+    }
+    // Lanes 8..63 put their (zero) second value into this wave's own column
+    // of the u^{n+1} tile, which step 1 overwrites after the barrier: a write
+    // without a branch keeps the compiler from moving those loads into one.
+    const bool lo8 = lane < 2 * kR;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int c = w + kWaves * i;
+      sh.u0[c][lane] = v[i];
+      *(lo8 ? &sh.u0[c][64 + lane] : &sh.u1[w][lane]) = v2[i];
+      if constexpr (DF) {
+        sh.l0[c][lane] = l[i];
+        *(lo8 ? &sh.l0[c][64 + lane] : &sh.l1[w][lane]) = l2[i];
       }
     }
   }
