@@ -12,6 +12,31 @@ constexpr int kR = 4;          // stencil radius (8th-order second derivative)
 constexpr int kWaves = 4;      // wavefronts per stencil workgroup
 constexpr int kTZ2 = 56;       // output rows per tile of the two-step kernel (64 lanes = rows z0-4 .. z0+59)
 
+// Raw buffer access: per-lane 32-bit byte offset (the row) plus a wave-uniform
+// byte offset (the column) that lives in a scalar register, so no 64-bit
+// address arithmetic is spent per access.  The hardware range check covers
+// the per-lane offset only (offset >= the buffer's byte size reads as zero and
+// drops a store), not the scalar one: an access whose column comes in the
+// scalar offset is guarded, or clamped into the grid; one that folds the
+// column into the per-lane offset can instead be sent past the end with
+// kOutOfRange to read zero without a branch.
+constexpr int kOutOfRange = (int)0x80000000u;   // beyond any field (fields are < 2 GiB)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ unsigned short ld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+}
+__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, unsigned short v, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
+}
+
 // Order of the stencil tiles of one launch (S shots, ntz x ntx tiles each).
 // Columns of tiles are taken kTileGroupX x-strips at a time; inside a group
 // one shot's tiles come together (z fastest), then the next shot's tiles of

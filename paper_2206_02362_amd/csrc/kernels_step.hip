@@ -36,6 +36,7 @@ struct StepTile {
   static constexpr int HC = TX + 2 * kR;
   static constexpr int HZ = kTZ + 2 * kR;
   float v[HC][HZ];
+  float sink[kWaves][kTZ];   // target of the halo-row writes of lanes 8..63 (never read)
 };
 
 // One 64 x TX tile of one shot; `logical` is the tile's position in the
@@ -54,9 +55,12 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
   const int NZ = a.NZ, NX = a.NX, LZ = a.LZ;
 
   const long soff = (long)s * a.sstride;
-  const float *cur = a.cur + soff;
-  const float *prev = a.prev + soff;
   float *out = a.out + soff;
+  const int CB = LZ * 4;                      // bytes per column
+  const unsigned FB = (unsigned)NX * (unsigned)CB;
+  const auto r_cur = rsrc(a.cur + soff, FB);
+  const auto r_prev = rsrc(a.prev + soff, FB);
+  const auto r_V = rsrc(a.V, FB);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -65,42 +69,60 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
   const bool zin = z < NZ;
   const int xs = x0 + w * CPW;
 
-  // Own-cell operands first: their latency hides behind the tile load.
-  float pv[CPW], vv[CPW], ds[CPW];
+  // Own-cell operands first: their latency hides behind the tile load.  A
+  // cell outside the grid gets an offset past the end of the buffer and reads
+  // zero, so no load sits behind a branch (the compiler would wait for each).
+  float pv[CPW], vv[CPW], ds[CPW], gx[CPW];
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t r_ds;
+  if constexpr ((MODE & kModeDsrc) != 0) r_ds = rsrc(a.dsrc + (long)s * a.dsrc_sstride, FB);
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int x = xs + j;
-    const bool in = zin && x < NX;
-    const long idx = (long)x * LZ + z;
-    pv[j] = in ? prev[idx] : 0.f;
-    vv[j] = in ? a.V[idx] : 0.f;
+    const int o = zin && x < NX ? x * CB + z * 4 : kOutOfRange;
+    gx[j] = a.gx[min(x, NX - 1)];
+    pv[j] = ld(r_prev, o, 0);
+    vv[j] = ld(r_V, o, 0);
     ds[j] = 0.f;
-    if constexpr ((MODE & kModeDsrc) != 0) {
-      ds[j] = in ? a.dsrc[(long)s * a.dsrc_sstride + idx] : 0.f;
-    }
+    if constexpr ((MODE & kModeDsrc) != 0) ds[j] = ld(r_ds, o, 0);
   }
   const float gzv = zin ? a.gz[z] : 0.f;
   if constexpr ((MODE & kModeNu) != 0) {
     const long so = (long)s * a.nu.sstride;
+    const auto rm = rsrc(a.nu.em + so, FB), r0 = rsrc(a.nu.e0 + so, FB), rp = rsrc(a.nu.ep + so, FB);
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int x = xs + j;
-      if (zin && x < NX) {
-        const long idx = so + (long)x * LZ + z;
-        const float g = gzv * a.gx[x];
-        ds[j] += a.nu.em[idx] / g - 2.f * a.nu.e0[idx] + g * a.nu.ep[idx];
-      }
+      const bool in = zin && x < NX;
+      const int o = in ? x * CB + z * 4 : kOutOfRange;
+      const float g = gzv * gx[j];
+      const float e = ld(rm, o, 0) / g - 2.f * ld(r0, o, 0) + g * ld(rp, o, 0);
+      if (in) ds[j] += e;   // a select: nothing is loaded under it
     }
   }
 
-  for (int i = tid; i < HC * HZ; i += 256) {
-    const int c = i / HZ;
-    const int zz = i - c * HZ;
-    const int x = x0 - kR + c;
-    const int zg = z0 - kR + zz;
-    float v = 0.f;
-    if ((unsigned)x < (unsigned)NX && (unsigned)zg < (unsigned)NZ) v = cur[(long)x * LZ + zg];
-    tile[c][zz] = v;
+  // input tile plus a 4-cell halo: lane = row z0 - 4 + lane, lanes 0..7 also
+  // row z0 + 60 + lane; every load of it is in flight before the first wait
+  {
+    constexpr int NC = HC / kWaves;
+    static_assert(HC % kWaves == 0 && HZ == kTZ + 2 * kR, "tile shape");
+    const int zg = z0 - kR + lane;
+    const bool zg_in = zg >= 0 && zg < NZ;
+    const bool zg2_in = lane < 2 * kR && zg + kTZ < NZ;
+    float v[NC], v2[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int x = x0 - kR + w + kWaves * i;
+      const bool xin = x >= 0 && x < NX;      // wave-uniform
+      v[i] = ld(r_cur, xin && zg_in ? x * CB + zg * 4 : kOutOfRange, 0);
+      v2[i] = ld(r_cur, xin && zg2_in ? x * CB + (zg + kTZ) * 4 : kOutOfRange, 0);
+    }
+    const bool lo8 = lane < 2 * kR;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int c = w + kWaves * i;
+      tile[c][lane] = v[i];
+      *(lo8 ? &tile[c][kTZ + lane] : &sh.sink[w][lane]) = v2[i];
+    }
   }
   __syncthreads();
 
@@ -150,7 +172,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
     }
     const int x = xs + j;
     if (zin && x < NX) {
-      const float g = gzv * a.gx[x];
+      const float g = gzv * gx[j];
       const float r = vv[j] * (lap + src);
       const long idx = (long)x * LZ + z;
       out[idx] = g * (2.f * c - g * pv[j] + r);

@@ -66,27 +66,6 @@ __device__ __forceinline__ float df_update(float g, float c, float cl, float pv,
   return hi;
 }
 
-// Raw buffer access: per-lane 32-bit byte offset (the row) plus a wave-uniform
-// byte offset (the column) that lives in a scalar register, so no 64-bit
-// address arithmetic is spent per access.  The scalar offset is not part of
-// the hardware range check, so every access below is guarded: its column is
-// inside [0, NX) and its row inside the grid.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-}
-__device__ __forceinline__ unsigned short ld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
-}
-__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, unsigned short v, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
-}
-
 // Adds a wavefront's point sources to its per-column source registers, in list
 // order (the order in which the one-step kernel adds them).  Done before the
 // column march so that the march itself has no loop inside.
@@ -192,7 +171,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   // waits for one.
   {
     constexpr int NC = C0 / kWaves;
-    constexpr int kOut = (int)0x80000000u;    // beyond any field (FB < 2^31)
+    constexpr int kOut = kOutOfRange;
     const int zt = z0 - 2 * kR + lane;
     const bool zt_in = zt >= 0 && zt < NZ;
     const bool zt2_in = lane < 2 * kR && zt + 64 < NZ;
