@@ -257,15 +257,13 @@ int check_inputs(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, cons
 // step-2 lists on the tile, src1 / rinj1 the step-1 lists over the tile plus
 // a 4-cell halo, rext per tile.
 struct HostTables {
-  std::vector<int> src_ptr, rext_ptr, rinj_ptr, cells, src1_ptr, rinj1_ptr, rext64_ptr;
-  std::vector<int2> src_ent, rext_ent, rinj_ent, src1_ent, rinj1_ent, rext64_ent;
+  std::vector<int> src_ptr, rext_ptr, rinj_ptr, cells, src1_ptr, rinj1_ptr;
+  std::vector<int2> src_ent, rext_ent, rinj_ent, src1_ent, rinj1_ent;
 };
 
-// rext64: receiver lists of the one-step tiling, also built with the
-// two-step tables for the propagations that stay one step per launch
 struct DevTables {
-  int *src_ptr, *rext_ptr, *rinj_ptr, *cells, *src1_ptr, *rinj1_ptr, *rext64_ptr;
-  int2 *src_ent, *rext_ent, *rinj_ent, *src1_ent, *rinj1_ent, *rext64_ent;
+  int *src_ptr, *rext_ptr, *rinj_ptr, *cells, *src1_ptr, *rinj1_ptr;
+  int2 *src_ent, *rext_ent, *rinj_ent, *src1_ent, *rinj1_ent;
 };
 
 void csr_build(std::vector<int> &ptr, std::vector<int2> &ent, long nbucket,
@@ -323,7 +321,7 @@ HostTables build_tables2(const Dims &d, const fwime_geom_t *geo, int s0, int S) 
   const int W1 = (d.TX + 2 * kR) / kWaves, W2 = d.TX / kWaves;
   const long ntiles = (long)d.ntz2 * d.ntx * S;
   auto tile_of = [&](int s, int txi, int tzi) { return tile_index(txi, tzi, s, d.ntz2, d.ntx, S); };
-  std::vector<std::pair<long, int2>> src1, src2, rext, rinj1, rinj2, rext64;
+  std::vector<std::pair<long, int2>> src1, src2, rext, rinj1, rinj2;
   auto add_inject = [&](int s, int px, int pz, int idx, std::vector<std::pair<long, int2>> &l1,
                         std::vector<std::pair<long, int2>> &l2) {
     const int txi = px / d.TX, tzi = pz / kTZ2;
@@ -348,11 +346,6 @@ HostTables build_tables2(const Dims &d, const fwime_geom_t *geo, int s0, int S) 
       const int px = geo->rec_ix[ir] + d.nb, pz = geo->rec_iz[ir] + d.nb;
       const int txi = px / d.TX, tzi = pz / kTZ2;
       rext.push_back({tile_of(s, txi, tzi), make_int2(((px - txi * d.TX) << 6) | (pz - tzi * kTZ2), il)});
-      {
-        const int t64 = pz / kTZ;
-        rext64.push_back({tile_index(txi, t64, s, d.ntz, d.ntx, S),
-                          make_int2(((px - txi * d.TX) << 6) | (pz - t64 * kTZ), il)});
-      }
       add_inject(s, px, pz, il, rinj1, rinj2);
       t.cells.push_back(px * d.LZ + pz);
     }
@@ -362,16 +355,14 @@ HostTables build_tables2(const Dims &d, const fwime_geom_t *geo, int s0, int S) 
   csr_build(t.rext_ptr, t.rext_ent, ntiles, rext);
   csr_build(t.rinj1_ptr, t.rinj1_ent, ntiles * kWaves, rinj1);
   csr_build(t.rinj_ptr, t.rinj_ent, ntiles * kWaves, rinj2);
-  csr_build(t.rext64_ptr, t.rext64_ent, (long)d.ntz * d.ntx * S, rext64);
   return t;
 }
 
 size_t tables_ints(const HostTables &t) {
   return t.src_ptr.size() + t.rext_ptr.size() + t.rinj_ptr.size() + t.cells.size() + t.src1_ptr.size() +
-         t.rinj1_ptr.size() + t.rext64_ptr.size() +
-         2 * (t.src_ent.size() + t.rext_ent.size() + t.rinj_ent.size() + t.src1_ent.size() + t.rinj1_ent.size() +
-              t.rext64_ent.size()) +
-         13 * 64;
+         t.rinj1_ptr.size() +
+         2 * (t.src_ent.size() + t.rext_ent.size() + t.rinj_ent.size() + t.src1_ent.size() + t.rinj1_ent.size()) +
+         11 * 64;
 }
 
 // Lay out all batch tables into one host blob and one device buffer.
@@ -418,8 +409,6 @@ int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
     o.push_back(put(t.src1_ent.data(), 2 * t.src1_ent.size()));
     o.push_back(put(t.rinj1_ptr.data(), t.rinj1_ptr.size()));
     o.push_back(put(t.rinj1_ent.data(), 2 * t.rinj1_ent.size()));
-    o.push_back(put(t.rext64_ptr.data(), t.rext64_ptr.size()));
-    o.push_back(put(t.rext64_ent.data(), 2 * t.rext64_ent.size()));
     offs.push_back(o);
   }
   for (auto &o : offs) {
@@ -435,8 +424,6 @@ int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
     dt.src1_ent = (int2 *)(dev + o[8]);
     dt.rinj1_ptr = dev + o[9];
     dt.rinj1_ent = (int2 *)(dev + o[10]);
-    dt.rext64_ptr = dev + o[11];
-    dt.rext64_ent = (int2 *)(dev + o[12]);
     ts.dev.push_back(dt);
   }
   // The blob is copied synchronously (pageable memory): the call owns no
@@ -611,33 +598,12 @@ int march2(fwime_ctx_t *ctx, const Common &c, Ring4 &f, int S, int n0, int n1, i
   return FWIME_OK;
 }
 
-// Dense-source propagation over steps n0 .. n1 - 1, one step per launch (for
-// this mode the one-step kernel is faster): fields ping-pong between
-// f.prev() and f.cur() (out overwrites prev), so the ring keeps its meaning
-// (prev = f[i], cur = f[i + 1]) after every step.  The source of step n is
-// dsrc(n); receivers of the input field are sampled into rec (if non-null)
-// with the one-step lists of the two-step tables.
-template <class Dsrc>
-int march1_dsrc(fwime_ctx_t *ctx, const Common &c, Ring4 &f, int S, int n0, int n1, Dsrc dsrc, long dsrc_sstride,
-                const DevTables &t, float *rec, int nt, hipStream_t st) {
-  for (int n = n0; n < n1; ++n) {
-    StepArgs a = batch_args(c, S, c.d.field);
-    a.cur = f.cur();
-    a.prev = f.prev();
-    a.out = f.prev();
-    a.dsrc = dsrc(n);
-    a.dsrc_sstride = dsrc_sstride;
-    if (rec) {
-      a.ext.ptr = t.rext64_ptr;
-      a.ext.ent = t.rext64_ent;
-      a.ext.out = rec;
-      a.ext.stride_idx = nt;
-      a.ext.t = n;
-    }
-    HIPCHK(launch_step(a, c.d.TX, kModeDsrc, st));
-    std::swap(f.f[f.i & 3], f.f[(f.i + 1) & 3]);   // new field is cur; old cur is prev
-  }
-  return FWIME_OK;
+// dense source of a two-step launch: slot `first` for its first step, the
+// next slot (`slot` elements on) for its second; per-shot stride sstride
+void with_dsrc2(Step2Args &p, const float *first, long slot, int k, long sstride) {
+  p.a.dsrc = first;
+  p.dsrc2 = k == 2 ? first + slot : nullptr;
+  p.a.dsrc_sstride = sstride;
 }
 
 // BF16 arrays copied as 32-bit words (fields hold an even number of cells)
@@ -927,8 +893,10 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
         }, st, &lu);
         if (rc) return rc;
         HIPCHK(launch_ext_scatter(coef, eg, +1, t2, d.field, sc, d.field, chunk_stride, Sb, nk, st));
-        rc = march1_dsrc(ctx, c, fw, Sb, c0, c0 + nk, [&](int n) { return sc + (long)(n - c0) * d.field; },
-                         chunk_stride, t, out_b, g->nt, st);
+        rc = march2(ctx, c, fw, Sb, c0, c0 + nk, kModeDsrc, [&](Step2Args &p, int n, int k) {
+          with_dsrc2(p, sc + (long)(n - c0) * d.field, d.field, k, chunk_stride);
+          with_rec_extract(p.a, t, out_b, g->nt, n);
+        }, st);
         if (rc) return rc;
       }
       HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
@@ -1209,8 +1177,10 @@ int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, con
       }, st);
       if (rc) return rc;
       HIPCHK(launch_ext_scatter(coef, eg, +1, wk.t2u, d.field, wk.t2d, d.field, pl.seg_stride, Sb, nk, st));
-      rc = march1_dsrc(ctx, c, fw, Sb, n0, n1, [&](int n) { return wk.t2d + (long)(n - n0) * d.field; },
-                       pl.seg_stride, t, ddrec, g->nt, st);
+      rc = march2(ctx, c, fw, Sb, n0, n1, kModeDsrc, [&](Step2Args &p, int n, int k) {
+        with_dsrc2(p, wk.t2d + (long)(n - n0) * d.field, d.field, k, pl.seg_stride);
+        with_rec_extract(p.a, t, ddrec, g->nt, n);
+      }, st);
       if (rc) return rc;
     }
     HIPCHK(launch_gather(fu.cur(), d.field, t.cells, Sb, nrec, drec, g->nt, g->nt - 1, st));
