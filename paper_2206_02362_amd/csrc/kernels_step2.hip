@@ -149,19 +149,23 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     if constexpr (DF) pl[j] = bf16_f32(ld16(r_lprev, vzc / 2, xc * (CB / 2)));
   }
   const float gzv = zin ? a.gz[z] : 0.f;
+  // transposed second time difference of the e ring: step 1 reads slots
+  // (k-1, k, k+1) on the halo, step 2 slots (k-2, k-1, k) on the tile; the
+  // values are combined once every load of the prologue is in flight
+  [[maybe_unused]] float em1[W1], e01[W1], ep1[W1];
   if constexpr (NU) {
-    // transposed second time difference of the e ring: step 1 reads slots
-    // (k-1, k, k+1) on the halo, step 2 slots (k-2, k-1, k) on the tile
     const long so = (long)s * a.nu.sstride;
     const auto rm = rsrc(a.nu.em + so, FB), r0 = rsrc(a.nu.e0 + so, FB), rp = rsrc(a.nu.ep + so, FB);
-    const float gzc = a.gz[vzc / 4];         // taper at the clamped row (nonzero)
 #pragma unroll
     for (int j = 0; j < W1; ++j) {
       const int xc = min(max(xs1 + j, 0), NX - 1);
-      const float g = gzc * gx1[j];
-      ds1[j] += ld(rm, vzc, xc * CB) / g - 2.f * ld(r0, vzc, xc * CB) + g * ld(rp, vzc, xc * CB);
+      em1[j] = ld(rm, vzc, xc * CB);
+      e01[j] = ld(r0, vzc, xc * CB);
+      ep1[j] = ld(rp, vzc, xc * CB);
     }
   }
+
+  float vv2[W2], ds2[W2], gx2[W2];
 
   // u^n tile, one column per wavefront access: lane = row z0 - 8 + lane, and
   // lanes 0..7 also row z0 + 56 + lane.  No branch: a cell outside the grid
@@ -189,6 +193,32 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
         l[i] = ld16(r_lcur, o1 == kOut ? kOut : o1 / 2, 0);
         l2[i] = ld16(r_lcur, o2 == kOut ? kOut : o2 / 2, 0);
       }
+    }
+    if constexpr (NU) {
+      // the e values were issued before the tile: waiting for them here
+      // leaves the tile loads in flight
+      const float gzc = a.gz[vzc / 4];       // taper at the clamped row (nonzero)
+#pragma unroll
+      for (int j = 0; j < W1; ++j) {
+        const float g = gzc * gx1[j];
+        ds1[j] += em1[j] / g - 2.f * e01[j] + g * ep1[j];
+      }
+    }
+    // Step 2's own-row operands, issued now so that their latency hides
+    // behind the tile load and step 1.  Clamped like step 1's; with a single
+    // step the step-1 source stands in for the (absent) second one, so every
+    // address is valid and no load sits behind a branch.
+#pragma unroll
+    for (int j = 0; j < W2; ++j) {
+      const int xc = min(xs2 + j, NX - 1);
+      gx2[j] = a.gx[xc];
+      vv2[j] = ld(r_V, vzc, xc * CB);
+      ds2[j] = 0.f;
+    }
+    if constexpr (DS) {
+      const auto r_ds2 = rsrc((p.two ? p.dsrc2 : a.dsrc) + (long)s * a.dsrc_sstride, FB);
+#pragma unroll
+      for (int j = 0; j < W2; ++j) ds2[j] = ld(r_ds2, vzc, min(xs2 + j, NX - 1) * CB);
     }
     // Lanes 8..63 put their (zero) second value into this wave's own column
     // of the u^{n+1} tile, which step 1 overwrites after the barrier: a write
@@ -302,15 +332,6 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
 
   // ---- step 2: u^{n+2} on the tile ----------------------------------------
   {
-    float vv2[W2], ds2[W2], gx2[W2];
-#pragma unroll
-    for (int j = 0; j < W2; ++j) {
-      const int xc = min(xs2 + j, NX - 1);                         // as in step 1
-      gx2[j] = a.gx[xc];
-      vv2[j] = ld(r_V, vzc, xc * CB);
-      ds2[j] = 0.f;
-      if constexpr (DS) ds2[j] = ld(rsrc(p.dsrc2 + (long)s * a.dsrc_sstride, FB), vzc, xc * CB);
-    }
     if constexpr (NU) {
       const long so = (long)s * a.nu.sstride;
       const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
