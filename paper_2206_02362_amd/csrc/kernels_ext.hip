@@ -228,20 +228,26 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs
 // Same operator, input windows brought in by direct global-to-LDS loads
 // (buffer loads with the LDS as destination) into a 4-deep ring: three slots
 // are in flight while one is consumed, and no registers are spent on
-// staging.  Before the barrier that publishes slot q each wavefront waits
-// until its own loads of slot q have landed; the loads of the two younger
-// slots may still be outstanding (vector memory operations complete in
-// order).  The barrier is a bare s_barrier: a fenced one would wait for every
-// outstanding load.
+// staging.  Each load moves 16 bytes per lane (lane i fills LDS bytes
+// [16 i, 16 i + 16) from M0), i.e. four 64-deep columns per instruction; a
+// wavefront's padding loads, when the window's chunk count is not a multiple
+// of 8, read past the end of the buffer (zeros, no memory traffic) into a
+// sink.  Before the barrier that publishes slot q each wavefront waits until
+// its own loads of slot q have landed; the loads of the two younger slots may
+// still be outstanding (vector memory operations complete in order).  The
+// barrier is a bare s_barrier: a fenced one would wait for every outstanding
+// load.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <int HMAX, int SG>
 __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArgs a) {
   constexpr int NH = 2 * HMAX + 1;
   constexpr int WMAX = kScJB + 4 * HMAX;                          // staged columns
-  constexpr int PER = WMAX / 8;                                   // staged columns per wavefront
-  static_assert(WMAX % 8 == 0 && 2 * PER <= 63, "window");
+  constexpr int NCH = WMAX / 4;                                   // 4-column chunks per slot
+  constexpr int PER = (NCH + 7) / 8;                              // chunk loads per wavefront and slot
+  static_assert(WMAX % 4 == 0 && 2 * PER <= 63, "window");
   __shared__ float b0[WMAX * 64], b1[WMAX * 64], b2[WMAX * 64], b3[WMAX * 64];
+  __shared__ float sink[256];                                     // destination of the padding loads
 
   const int nblk_j = (a.nj + kScJB - 1) / kScJB;
   const int ntile = a.nzs * nblk_j;
@@ -283,22 +289,29 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int q1 = min(total, q0 + a.slots_per_block);
   if (q0 >= q1) return;
   const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
-  const int off0 = ((col0 + w) * a.LZ + zp) * 4;
-  const int rstep = 8 * a.LZ * 4;
+  // lane i of a chunk load: column 4 g + i / 16, depths 4 (i % 16) .. + 3 of
+  // the strip; columns left of the grid give negative offsets, which wrap
+  // past the end of the buffer and read as zero like those right of it
+  const int off0 = (col0 * a.LZ + a.nb + zs * 64) * 4 + ((lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
+  const int gstep = 4 * a.LZ * 4;                                 // bytes per chunk of 4 columns
 
   // slots are issued and consumed in increasing order: one cursor each
   SlotCursor ic, oc;
   ic.init(q0, a.nk, a.in_first, a.in_ring);
   oc.init(q0, a.nk, a.out_first, a.out_ring);
-  // wavefront w brings columns w + 8 r of slot q into buf (lane = depth)
+  // wavefront w brings chunks g = w + 8 r (columns 4 g .. 4 g + 3) of slot q
+  // into buf, column-major with lane = depth
   auto issue = [&](int q, float *buf) {
     if (q >= q1) return;
     const auto rs = slot_rsrc(a.in + (long)ic.s * a.sstride + (long)ic.r * a.in_slot, slot_bytes);
     ic.next();
 #pragma unroll
-    for (int r = 0; r < PER; ++r)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&buf[(w + 8 * r) * 64], 4, off0 + r * rstep, 0, 0,
-                                                0);
+    for (int r = 0; r < PER; ++r) {
+      const int g = w + 8 * r;
+      const bool real = g < NCH;                                  // wave-uniform
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)(real ? &buf[g * 256] : sink), 16,
+                                                real ? off0 + g * gstep : kOutOfRange, 0, 0, 0);
+    }
   };
   // this wavefront's loads of slot q have landed; younger slots may be in flight
   auto ready = [&](int q) {
