@@ -321,13 +321,15 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
     else __builtin_amdgcn_s_waitcnt(kExpLgkm);
   };
   auto consume = [&](int q, const float *buf) {
-    const float *row = &buf[(ja - col0) * 64 + lane];
+    // based at the lowest column read, so that every LDS offset is a
+    // non-negative immediate
+    const float *row = &buf[(ja - col0 - 2 * HMAX) * 64 + lane];
     float oa = 0.f, ob = 0.f;
 #pragma unroll
     for (int k = 0; k < NH; ++k) {
       const int ih = k - HMAX;
-      oa += ca[k] * row[-2 * SG * ih * 64];
-      ob += cb[k] * row[(2 - 2 * SG * ih) * 64];
+      oa += ca[k] * row[(2 * HMAX - 2 * SG * ih) * 64];
+      ob += cb[k] * row[(2 * HMAX + 2 - 2 * SG * ih) * 64];
     }
     float *dst = a.out + (long)oc.s * a.sstride + (long)oc.r * a.out_slot;
     oc.next();
@@ -642,6 +644,130 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   }
 }
 
+// Wide-offset variant with the windows brought in by 16-byte direct
+// global-to-LDS loads into a 4-deep ring (as in k_ext_scatter_dma): three
+// slots in flight while one is consumed, no staging registers.  Each window is
+// padded to 64 columns, 16 chunks of four 64-deep columns, so wavefront w
+// loads chunk w of the source-side and of the receiver-side window; columns
+// outside the grid read as zero through the range check.  Slots are consumed
+// in the same order as in k_ext_image_lds, so both give the same bits.
+template <int NYT, int NHT>
+__global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
+  constexpr int NA = kImgYT + kImgHT - 1;
+  constexpr int YB = 8 * NYT;
+  constexpr int HSPAN = 8 * NHT;
+  constexpr int WW = YB + HSPAN - 1;
+  constexpr int WWP = (WW + 3) / 4 * 4;          // window columns in LDS
+  static_assert(WWP / 4 == 16, "one chunk of each window per wavefront");
+  constexpr int BUF = 2 * WWP * 64;              // a-window columns, then b-window columns
+  __shared__ float b0[BUF], b1[BUF], b2[BUF], b3[BUF];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ntile = p.nzs * ((p.nx + YB - 1) / YB);
+  const int per = (ntile + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-contiguous tiles
+  if (tile >= ntile) return;
+  const int zs = tile % p.nzs;
+  const int yblk = tile / p.nzs;
+  const int yb = yblk * YB;
+  const int grp = blockIdx.y / p.nhb;
+  const int hlo = -p.H + HSPAN * (blockIdx.y - grp * p.nhb);
+  const int hhi = min(p.H, hlo + HSPAN - 1);
+  const int z = zs * 64 + lane;
+  const bool zin = z < p.nz;
+  const int yt = w % NYT, ht = w / NYT;
+  const int y0 = yb + 8 * yt;
+  const int h0 = hlo + 8 * ht;
+  const bool active = h0 <= hhi && y0 < p.nx;
+  const int xa0 = p.nb + yb - (hlo + HSPAN - 1);
+  const int xb0 = p.nb + yb + hlo;
+  const int ia = 8 * yt + (HSPAN - 8 - 8 * ht);  // a-window column of A[0]
+  const int ib = WWP + 8 * yt + 8 * ht;          // b-window column of B[0]
+
+  float acc[kImgYT][kImgHT];
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
+
+  const int q0 = grp * p.slots_per_group;
+  const int total = min(p.nshots * p.nk, q0 + p.slots_per_group);
+  const unsigned slot_bytes = (unsigned)((long)p.NX * p.LZ * 4);
+  const int CBy = p.LZ * 4;
+  // lane i of a chunk: column 4 w + i / 16 of the window, depths 4 (i % 16) .. + 3
+  const int lane_off = (p.nb + zs * 64 + 4 * (lane & 15)) * 4 + (lane >> 4) * CBy;
+  const int offa = lane_off + (xa0 + 4 * w) * CBy;
+  const int offb = lane_off + (xb0 + 4 * w) * CBy;
+  SlotCursor fc;                                 // issue walks q0, q0 + 1, ... once, in order
+  fc.init(q0, p.nk, p.b_first, p.b_ring);
+  auto issue = [&](int q, float *buf) {
+    if (q >= total) return;
+    const auto ra = slot_rsrc(p.a + (long)fc.s * p.a_sstride + (long)fc.n * p.a_slot, slot_bytes);
+    const auto rbb = slot_rsrc(p.b + (long)fc.s * p.b_sstride + (long)fc.r * p.b_slot, slot_bytes);
+    fc.next();
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t *)&buf[w * 256], 16, offa, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rbb, (lds_void_t *)&buf[WWP * 64 + w * 256], 16, offb, 0, 0, 0);
+  };
+  // this wavefront's two loads of slot q have landed; younger slots may be in flight
+  auto ready = [&](int q) {
+    constexpr int kExpLgkm = (7 << 4) | (15 << 8);
+    if (q + 2 < total) __builtin_amdgcn_s_waitcnt(4 | kExpLgkm);
+    else if (q + 1 < total) __builtin_amdgcn_s_waitcnt(2 | kExpLgkm);
+    else __builtin_amdgcn_s_waitcnt(kExpLgkm);
+  };
+  // every wavefront consumes (an inactive one's sums are never stored): a
+  // branch here makes the compiler wait for all outstanding loads first
+  auto consume = [&](const float *win) {
+    float va[NA], vb[NA];
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+      va[m] = win[(ia + m) * 64 + lane];
+      vb[m] = win[(ib + m) * 64 + lane];
+    }
+#pragma unroll
+    for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+      for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] += va[yy - hh + kImgHT - 1] * vb[yy + hh];
+  };
+  // slot q sits in buffer q mod 4; the slot loaded in its place is q + 3,
+  // whose buffer held slot q - 1 (everyone is past it once the barrier passed)
+  auto step = [&](int q, const float *cur, float *nxt) {
+    asm volatile("" ::: "memory");
+    ready(q);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    consume(cur);
+    issue(q + 3, nxt);
+  };
+  issue(q0, b0);
+  issue(q0 + 1, b1);
+  issue(q0 + 2, b2);
+  for (int q = q0; q < total; q += 4) {
+    step(q, b0, b3);
+    if (q + 1 >= total) break;
+    step(q + 1, b1, b0);
+    if (q + 2 >= total) break;
+    step(q + 2, b2, b1);
+    if (q + 3 >= total) break;
+    step(q + 3, b3, b2);
+  }
+  if (!active || !zin) return;
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy) {
+    const int y = y0 + yy;
+    if (y >= p.nx) continue;
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) {
+      const int ih = h0 + hh;
+      if (ih > hhi) continue;
+      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
+      if (p.groups > 1) p.parts[(long)grp * p.nh * p.nx * p.nz + o] = acc[yy][hh];
+      else p.acc[o] += acc[yy][hh];
+    }
+  }
+}
+
 // acc += sum over g of parts[g], in group order
 __global__ void k_image_reduce(float *acc, const float *parts, long n, int groups) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -690,7 +816,14 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.slots_per_group = (total + groups - 1) / groups;
   p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
   const dim3 grid((unsigned)nblk, (unsigned)(p.nhb * p.groups));
-  if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
+  // FWIME_IMAGE_KERNEL=lds selects the register-staged ring for the wide
+  // tiles too (for comparisons)
+  static const bool staged = [] {
+    const char *e = std::getenv("FWIME_IMAGE_KERNEL");
+    return e && std::string(e) == "lds";
+  }();
+  if (wide && !staged) k_ext_image_dma<4, 4><<<grid, 1024, 0, st>>>(p);
+  else if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
   else k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.groups == 1) return e;
