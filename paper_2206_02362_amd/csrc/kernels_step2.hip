@@ -68,19 +68,32 @@ __device__ __forceinline__ float df_update(float g, float c, float cl, float pv,
 
 // Adds a wavefront's point sources to its per-column source registers, in list
 // order (the order in which the one-step kernel adds them).  Done before the
-// column march so that the march itself has no loop inside.
+// column march so that the march itself has no loop inside.  Lane l fetches
+// entry l of each batch of 64 and its sample, so a batch costs two dependent
+// loads however many entries it has; the entries are then broadcast one by
+// one from registers.
 template <int W>
 __device__ __forceinline__ void fold_sources(const Inject &inj, int logical, int w, int lane, float (&src)[W]) {
   if (inj.ptr == nullptr) return;
   const int e1 = inj.ptr[logical * kWaves + w + 1];
-  for (int e = inj.ptr[logical * kWaves + w]; e < e1; ++e) {   // wave-uniform
-    const int2 en = inj.ent[e];
-    const float val = inj.val[(long)en.y * inj.stride_idx + inj.t] * inj.scale;
-    const int j = en.x >> 6;
-    if ((en.x & 63) == lane) {
+  for (int b = inj.ptr[logical * kWaves + w]; b < e1; b += 64) {   // wave-uniform
+    const int cnt = min(64, e1 - b);
+    int key = 0;
+    float val = 0.f;
+    if (lane < cnt) {
+      const int2 en = inj.ent[b + lane];
+      key = en.x;
+      val = inj.val[(long)en.y * inj.stride_idx + inj.t] * inj.scale;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      const int kx = __builtin_amdgcn_readlane(key, k);
+      const float kv = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, val), k));
+      const int j = kx >> 6;
+      if ((kx & 63) == lane) {
 #pragma unroll
-      for (int jj = 0; jj < W; ++jj)
-        if (jj == j) src[jj] += val;
+        for (int jj = 0; jj < W; ++jj)
+          if (jj == j) src[jj] += kv;
+      }
     }
   }
 }
