@@ -242,21 +242,25 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 template <int HMAX, int SG>
 __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArgs a) {
   constexpr int NH = 2 * HMAX + 1;
-  constexpr int WMAX = kScJB + 4 * HMAX;                          // staged columns
-  constexpr int NCH = WMAX / 4;                                   // 4-column chunks per slot
+  constexpr int WMAX = kScJB + 2 * HMAX;                          // staged same-parity columns
+  constexpr int NCH = (WMAX + 3) / 4;                             // 4-column chunks per slot
   constexpr int PER = (NCH + 7) / 8;                              // chunk loads per wavefront and slot
-  static_assert(WMAX % 4 == 0 && 2 * PER <= 63, "window");
-  __shared__ float b0[WMAX * 64], b1[WMAX * 64], b2[WMAX * 64], b3[WMAX * 64];
+  static_assert(2 * PER <= 63, "window");
+  __shared__ float b0[NCH * 256], b1[NCH * 256], b2[NCH * 256], b3[NCH * 256];
   __shared__ float sink[256];                                     // destination of the padding loads
 
-  const int nblk_j = (a.nj + kScJB - 1) / kScJB;
-  const int ntile = a.nzs * nblk_j;
+  // A workgroup owns the 16 output columns of one parity in a 32-column
+  // block: every input column they read has that parity too, so the window
+  // holds only those (m = 0 .. WMAX - 1 <-> padded column col0 + 2 m).
+  const int nblk_j = (a.nj + 2 * kScJB - 1) / (2 * kScJB);
+  const int ntile = a.nzs * nblk_j * 2;
   const int per = (ntile + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
   const int zs = tile % a.nzs;
-  const int jbk = tile / a.nzs;
-  const int jb = a.j0 + jbk * kScJB;
+  const int par = (tile / a.nzs) & 1;
+  const int jbk = tile / a.nzs >> 1;
+  const int jb = a.j0 + jbk * 2 * kScJB + par;                    // first output column
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -265,7 +269,7 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int zp = a.nb + z;
   const int H = a.H;
   const int col0 = jb - 2 * HMAX;
-  const int ja = jb + (w & 1) + 4 * (w >> 1);
+  const int ja = jb + 4 * w;                                      // outputs k = 2 w and 2 w + 1
   const int jc = ja + 2;
   const int jend = a.j0 + a.nj;
 
@@ -289,18 +293,19 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int q1 = min(total, q0 + a.slots_per_block);
   if (q0 >= q1) return;
   const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
-  // lane i of a chunk load: column 4 g + i / 16, depths 4 (i % 16) .. + 3 of
-  // the strip; columns left of the grid give negative offsets, which wrap
-  // past the end of the buffer and read as zero like those right of it
-  const int off0 = (col0 * a.LZ + a.nb + zs * 64) * 4 + ((lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
-  const int gstep = 4 * a.LZ * 4;                                 // bytes per chunk of 4 columns
+  // lane i of a chunk load: window column m = 4 g + i / 16 (padded column
+  // col0 + 2 m), depths 4 (i % 16) .. + 3 of the strip; columns left of the
+  // grid give negative offsets, which wrap past the end of the buffer and
+  // read as zero like those right of it
+  const int off0 = (col0 * a.LZ + a.nb + zs * 64) * 4 + (2 * (lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
+  const int gstep = 8 * a.LZ * 4;                                 // bytes per chunk of 4 window columns
 
   // slots are issued and consumed in increasing order: one cursor each
   SlotCursor ic, oc;
   ic.init(q0, a.nk, a.in_first, a.in_ring);
   oc.init(q0, a.nk, a.out_first, a.out_ring);
-  // wavefront w brings chunks g = w + 8 r (columns 4 g .. 4 g + 3) of slot q
-  // into buf, column-major with lane = depth
+  // wavefront w brings chunks g = w + 8 r (window columns 4 g .. 4 g + 3) of
+  // slot q into buf, column-major with lane = depth
   auto issue = [&](int q, float *buf) {
     if (q >= q1) return;
     const auto rs = slot_rsrc(a.in + (long)ic.s * a.sstride + (long)ic.r * a.in_slot, slot_bytes);
@@ -321,15 +326,15 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
     else __builtin_amdgcn_s_waitcnt(kExpLgkm);
   };
   auto consume = [&](int q, const float *buf) {
-    // based at the lowest column read, so that every LDS offset is a
-    // non-negative immediate
-    const float *row = &buf[(ja - col0 - 2 * HMAX) * 64 + lane];
+    // output k reads window column m = k - SG ih + HMAX; based at m = 2 w so
+    // that every LDS offset is a non-negative immediate
+    const float *row = &buf[2 * w * 64 + lane];
     float oa = 0.f, ob = 0.f;
 #pragma unroll
     for (int k = 0; k < NH; ++k) {
       const int ih = k - HMAX;
-      oa += ca[k] * row[(2 * HMAX - 2 * SG * ih) * 64];
-      ob += cb[k] * row[(2 * HMAX + 2 - 2 * SG * ih) * 64];
+      oa += ca[k] * row[(HMAX - SG * ih) * 64];
+      ob += cb[k] * row[(HMAX + 1 - SG * ih) * 64];
     }
     float *dst = a.out + (long)oc.s * a.sstride + (long)oc.r * a.out_slot;
     oc.next();
@@ -463,8 +468,9 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
   else                                                                                                  \
     sg > 0 ? K<30, 1><<<GRID, THREADS, 0, st>>>(a) : K<30, -1><<<GRID, THREADS, 0, st>>>(a);
   if (g.H <= 30) {
-    // spread the slots over enough workgroups to fill the device
-    const int ntile = a.nzs * ((a.nj + kScJB - 1) / kScJB);
+    // spread the slots over enough workgroups to fill the device (the
+    // direct-load kernel tiles 32-column blocks once per column parity)
+    const int ntile = staged ? a.nzs * ((a.nj + kScJB - 1) / kScJB) : a.nzs * ((a.nj + 2 * kScJB - 1) / (2 * kScJB)) * 2;
     const int nblk = (ntile + 7) / 8 * 8;
     int groups = std::max(1, std::min(total, (2048 + nblk - 1) / nblk));
     a.slots_per_block = (total + groups - 1) / groups;
