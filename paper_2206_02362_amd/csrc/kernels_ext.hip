@@ -53,6 +53,27 @@ struct SlotCursor {
   }
 };
 
+// SlotCursor that also carries the element offset s sstride + r slot of its
+// position, advanced by one add per slot (the products are formed once per
+// shot only).
+struct OffCursor {
+  SlotCursor c;
+  long off, slot, sstride;
+  __device__ void init(int q, int nk, int first, int ring, long slot_, long sstride_) {
+    c.init(q, nk, first, ring);
+    slot = slot_;
+    sstride = sstride_;
+    off = (long)c.s * sstride + (long)c.r * slot;
+  }
+  __device__ void next() {
+    const int s0 = c.s;
+    c.next();
+    if (c.s != s0) off = (long)c.s * sstride + (long)c.r * slot;
+    else if (c.r == 0) off -= (long)(c.ring - 1) * slot;   // ring wrap (ring > 0)
+    else off += slot;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // c(z,y,h) = 2 p~(z,y,h) / (v(z,y)^3 dt^2), model grid, [nh][nx][nz]
 // ---------------------------------------------------------------------------
@@ -239,6 +260,20 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs
 // load.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// s_waitcnt vmcnt(min(n, N)) for a wave-uniform n, other counters untouched
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_at_most(int n) {
+  if constexpr (N > 0) {
+    if (n >= N) {
+      __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+      return;
+    }
+    wait_vmcnt_at_most<N - 1>(n);
+  } else {
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+  }
+}
+
 template <int HMAX, int SG>
 __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArgs a) {
   constexpr int NH = 2 * HMAX + 1;
@@ -301,14 +336,14 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int gstep = 8 * a.LZ * 4;                                 // bytes per chunk of 4 window columns
 
   // slots are issued and consumed in increasing order: one cursor each
-  SlotCursor ic, oc;
-  ic.init(q0, a.nk, a.in_first, a.in_ring);
-  oc.init(q0, a.nk, a.out_first, a.out_ring);
+  OffCursor ic, oc;
+  ic.init(q0, a.nk, a.in_first, a.in_ring, a.in_slot, a.sstride);
+  oc.init(q0, a.nk, a.out_first, a.out_ring, a.out_slot, a.sstride);
   // wavefront w brings chunks g = w + 8 r (window columns 4 g .. 4 g + 3) of
   // slot q into buf, column-major with lane = depth
   auto issue = [&](int q, float *buf) {
     if (q >= q1) return;
-    const auto rs = slot_rsrc(a.in + (long)ic.s * a.sstride + (long)ic.r * a.in_slot, slot_bytes);
+    const auto rs = slot_rsrc(a.in + ic.off, slot_bytes);
     ic.next();
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -318,12 +353,15 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
                                                 real ? off0 + g * gstep : kOutOfRange, 0, 0, 0);
     }
   };
-  // this wavefront's loads of slot q have landed; younger slots may be in flight
+  // This wavefront's loads of slot q have landed.  Issued after them and
+  // possibly still outstanding: the loads of the y younger slots already
+  // issued and the two stores of each of the c slots consumed since; vector
+  // memory operations complete in order, so waiting until no more than
+  // PER y + 2 c remain is exact.
   auto ready = [&](int q) {
-    constexpr int kExpLgkm = (7 << 4) | (15 << 8);
-    if (q + 2 < q1) __builtin_amdgcn_s_waitcnt(((2 * PER) & 15) | (((2 * PER) >> 4) << 14) | kExpLgkm);
-    else if (q + 1 < q1) __builtin_amdgcn_s_waitcnt((PER & 15) | ((PER >> 4) << 14) | kExpLgkm);
-    else __builtin_amdgcn_s_waitcnt(kExpLgkm);
+    const int y = min(2, q1 - 1 - q);
+    const int c = min(3, q - q0);
+    wait_vmcnt_at_most<2 * PER + 6>(PER * y + 2 * c);
   };
   auto consume = [&](int q, const float *buf) {
     // output k reads window column m = k - SG ih + HMAX; based at m = 2 w so
@@ -336,12 +374,12 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
       oa += ca[k] * row[(HMAX - SG * ih) * 64];
       ob += cb[k] * row[(HMAX + 1 - SG * ih) * 64];
     }
-    float *dst = a.out + (long)oc.s * a.sstride + (long)oc.r * a.out_slot;
+    const auto ro = slot_rsrc(a.out + oc.off, slot_bytes);
     oc.next();
-    if (zin) {
-      if (ja < jend) dst[(long)ja * a.LZ + zp] = oa;
-      if (jc < jend) dst[(long)jc * a.LZ + zp] = ob;
-    }
+    // always two store instructions (cells not written go past the end of
+    // the buffer and are dropped), so that ready() can count them
+    st(ro, oa, zin && ja < jend ? (ja * a.LZ + zp) * 4 : kOutOfRange, 0);
+    st(ro, ob, zin && jc < jend ? (jc * a.LZ + zp) * 4 : kOutOfRange, 0);
   };
   // slot q sits in buffer q mod 4; the slot loaded in its place is q + 3,
   // whose buffer held slot q - 1 (everyone is past it once the barrier passed)
@@ -705,13 +743,15 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   const int lane_off = (p.nb + zs * 64 + 4 * (lane & 15)) * 4 + (lane >> 4) * CBy;
   const int offa = lane_off + (xa0 + 4 * w) * CBy;
   const int offb = lane_off + (xb0 + 4 * w) * CBy;
-  SlotCursor fc;                                 // issue walks q0, q0 + 1, ... once, in order
-  fc.init(q0, p.nk, p.b_first, p.b_ring);
+  OffCursor fa, fb;                              // issue walks q0, q0 + 1, ... once, in order
+  fa.init(q0, p.nk, 0, 0, p.a_slot, p.a_sstride);
+  fb.init(q0, p.nk, p.b_first, p.b_ring, p.b_slot, p.b_sstride);
   auto issue = [&](int q, float *buf) {
     if (q >= total) return;
-    const auto ra = slot_rsrc(p.a + (long)fc.s * p.a_sstride + (long)fc.n * p.a_slot, slot_bytes);
-    const auto rbb = slot_rsrc(p.b + (long)fc.s * p.b_sstride + (long)fc.r * p.b_slot, slot_bytes);
-    fc.next();
+    const auto ra = slot_rsrc(p.a + fa.off, slot_bytes);
+    const auto rbb = slot_rsrc(p.b + fb.off, slot_bytes);
+    fa.next();
+    fb.next();
     __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t *)&buf[w * 256], 16, offa, 0, 0, 0);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rbb, (lds_void_t *)&buf[WWP * 64 + w * 256], 16, offb, 0, 0, 0);
   };
