@@ -292,9 +292,12 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int per = (ntile + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
-  const int zs = tile % a.nzs;
-  const int par = (tile / a.nzs) & 1;
-  const int jbk = tile / a.nzs >> 1;
+  // column blocks fastest: the workgroups that run together on one XCD
+  // cover a wide run of columns of one strip, whose overlapping windows
+  // then come from that XCD's L2 rather than from HBM
+  const int jbk = tile % nblk_j;
+  const int par = (tile / nblk_j) & 1;
+  const int zs = tile / nblk_j >> 1;
   const int jb = a.j0 + jbk * 2 * kScJB + par;                    // first output column
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -712,8 +715,11 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   const int per = (ntile + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-contiguous tiles
   if (tile >= ntile) return;
-  const int zs = tile % p.nzs;
-  const int yblk = tile / p.nzs;
+  // column blocks fastest, as in the scatter: neighbouring windows of one
+  // strip are read together and come from the XCD's L2
+  const int nyb = (p.nx + YB - 1) / YB;
+  const int yblk = tile % nyb;
+  const int zs = tile / nyb;
   const int yb = yblk * YB;
   const int grp = blockIdx.y / p.nhb;
   const int hlo = -p.H + HSPAN * (blockIdx.y - grp * p.nhb);
