@@ -494,11 +494,10 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
   a.nshots = nshots;
   const int total = nshots * nk;
   // FWIME_SCATTER_KERNEL=ws selects the register-staged ring for
-  // comparisons; the default is the ring fed by direct global-to-LDS loads
-  static const bool staged = [] {
-    const char *e = std::getenv("FWIME_SCATTER_KERNEL");
-    return e && std::string(e) == "ws";
-  }();
+  // comparisons (read per launch); the default is the ring fed by direct
+  // global-to-LDS loads
+  const char *sel = std::getenv("FWIME_SCATTER_KERNEL");
+  const bool staged = sel && std::string(sel) == "ws";
 #define FW_SCATTER(K, GRID, THREADS)                                                                    \
   if (g.H <= 8)                                                                                         \
     sg > 0 ? K<8, 1><<<GRID, THREADS, 0, st>>>(a) : K<8, -1><<<GRID, THREADS, 0, st>>>(a);              \
@@ -869,11 +868,9 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
   const dim3 grid((unsigned)nblk, (unsigned)(p.nhb * p.groups));
   // FWIME_IMAGE_KERNEL=lds selects the register-staged ring for the wide
-  // tiles too (for comparisons)
-  static const bool staged = [] {
-    const char *e = std::getenv("FWIME_IMAGE_KERNEL");
-    return e && std::string(e) == "lds";
-  }();
+  // tiles too (for comparisons; read per launch)
+  const char *sel = std::getenv("FWIME_IMAGE_KERNEL");
+  const bool staged = sel && std::string(sel) == "lds";
   if (wide && !staged) k_ext_image_dma<4, 4><<<grid, 1024, 0, st>>>(p);
   else if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
   else k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
