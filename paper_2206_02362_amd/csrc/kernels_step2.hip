@@ -101,7 +101,7 @@ __device__ __forceinline__ void fold_sources(const Inject &inj, int logical, int
 // One 56 x TX tile of one shot; `logical` is the tile's position in the
 // launch order of tile_index.  extract_only: only sample u^n.  ext_next: sample
 // u^{n+1} after the first step even when no second step follows.
-template <int TX, int MODE>
+template <int TX, int MODE, bool EARLY2 = true>
 __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
                                            Step2Tile<TX, (MODE & kModeDF) != 0> &sh, bool extract_only,
                                            bool ext_next) {
@@ -114,6 +114,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   constexpr int W1 = (TX + 8) / kWaves;      // step-1 columns per wave
   constexpr int W2 = TX / kWaves;            // step-2 columns per wave
   static_assert((TX + 8) % kWaves == 0 && TX % kWaves == 0 && C0 % kWaves == 0, "tile width");
+  static_assert(EARLY2 || MODE == kModePlain, "late step-2 operand loads: plain mode only");
   const StepArgs &a = p.a;
   int txi, tzi, s;
   tile_coords(logical, a.ntz, a.ntx, a.nshots, txi, tzi, s);
@@ -179,6 +180,15 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   }
 
   float vv2[W2], ds2[W2], gx2[W2];
+  auto load_step2_operands = [&]() {
+#pragma unroll
+    for (int j = 0; j < W2; ++j) {
+      const int xc = min(xs2 + j, NX - 1);
+      gx2[j] = a.gx[xc];
+      vv2[j] = ld(r_V, vzc, xc * CB);
+      ds2[j] = 0.f;
+    }
+  };
 
   // u^n tile, one column per wavefront access: lane = row z0 - 8 + lane, and
   // lanes 0..7 also row z0 + 56 + lane.  No branch: a cell outside the grid
@@ -218,16 +228,11 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       }
     }
     // Step 2's own-row operands, issued now so that their latency hides
-    // behind the tile load and step 1.  Clamped like step 1's; with a single
+    // behind the tile load and step 1 (EARLY2; the multi-job kernel, short of
+    // registers, loads them at step 2).  Clamped like step 1's; with a single
     // step the step-1 source stands in for the (absent) second one, so every
     // address is valid and no load sits behind a branch.
-#pragma unroll
-    for (int j = 0; j < W2; ++j) {
-      const int xc = min(xs2 + j, NX - 1);
-      gx2[j] = a.gx[xc];
-      vv2[j] = ld(r_V, vzc, xc * CB);
-      ds2[j] = 0.f;
-    }
+    if constexpr (EARLY2) load_step2_operands();
     if constexpr (DS) {
       const auto r_ds2 = rsrc((p.two ? p.dsrc2 : a.dsrc) + (long)s * a.dsrc_sstride, FB);
 #pragma unroll
@@ -345,6 +350,7 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
 
   // ---- step 2: u^{n+2} on the tile ----------------------------------------
   {
+    if constexpr (!EARLY2) load_step2_operands();
     if constexpr (NU) {
       const long so = (long)s * a.nu.sstride;
       const auto rm2 = rsrc(p.nu2.em + so, FB), r02 = rsrc(p.nu2.e0 + so, FB), rp2 = rsrc(p.nu2.ep + so, FB);
@@ -455,7 +461,7 @@ __global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int 
   p.a.inj.t = n;
   p.inj2.t = n + 1;
   p.a.ext.t = n;
-  step2_body<TX, kModePlain>(p, logical - jb.tile_begin, sh, n == jb.nt - 1, true);
+  step2_body<TX, kModePlain, false>(p, logical - jb.tile_begin, sh, n == jb.nt - 1, true);
 }
 
 hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int tile_x,
