@@ -1,0 +1,165 @@
+"""Index logic of the kernels, checked on the CPU.
+
+* The slot cursors of the offset kernels (SlotCursor, OffCursor in
+  csrc/kernels_ext.hip) are compiled with g++ straight from the kernel source
+  and walked over random (nk, ring, first, shot stride, slot stride): the
+  running element offset must equal s * sstride + r * slot at every position,
+  with r = (first mod ring + n) mod ring (or n without a ring).
+* The stencil tile order (tile_index / tile_coords in csrc/internal.h) must be
+  a bijection with tile_coords its inverse, and the XCD-contiguous mapping of
+  hardware workgroups to logical tiles must hit every tile exactly once.
+* The scatter's wait before each slot's barrier allows PER * y + 2 c younger
+  vector-memory operations (y younger slots issued, c slots consumed since
+  slot q was issued, two stores each).  A model of the kernel's program order
+  (three slots issued ahead, then per slot: wait, barrier, issue q + 3,
+  consume q) must give exactly that count for every slot of every length.
+"""
+import os
+import random
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2206_02362_amd", "csrc")
+
+
+def _struct(src: str, name: str) -> str:
+    i = src.index(f"struct {name} {{")
+    depth = 0
+    for j in range(i, len(src)):
+        if src[j] == "{":
+            depth += 1
+        elif src[j] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[i:src.index(";", j) + 1]
+    raise ValueError(name)
+
+
+def _function(src: str, signature_start: str) -> str:
+    i = src.index(signature_start)
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        if src[k] == "{":
+            depth += 1
+        elif src[k] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[i:k + 1]
+    raise ValueError(signature_start)
+
+
+def _run_cpp(tmp_path, body: str) -> str:
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    cpp = tmp_path / "t.cpp"
+    exe = tmp_path / "t"
+    cpp.write_text(body)
+    subprocess.run([gxx, "-O1", "-std=c++17", "-o", str(exe), str(cpp)], check=True)
+    return subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+
+
+def test_slot_cursors_match_direct_offsets(tmp_path):
+    src = open(os.path.join(CSRC, "kernels_ext.hip")).read()
+    prog = ("#include <cstdio>\n#include <cstdlib>\n#define __device__\n"
+            + _struct(src, "SlotCursor") + "\n" + _struct(src, "OffCursor") + r"""
+int main() {
+  long bad = 0, n = 0;
+  srand(12345);
+  for (int trial = 0; trial < 20000; ++trial) {
+    const int nk = 1 + rand() % 20;
+    const int ring = (rand() % 3 == 0) ? 0 : nk + rand() % 5;
+    const int first = rand() % 50, nshots = 1 + rand() % 5;
+    const long slot = 1 + rand() % 1000, sstr = 100000 + rand() % 1000;
+    const int total = nk * nshots, q0 = rand() % total;
+    OffCursor c;
+    c.init(q0, nk, first, ring, slot, sstr);
+    for (int q = q0; q < total; ++q) {
+      const int s = q / nk, k = q - s * nk;
+      const long r = ring ? (long)((first % ring) + k) % ring : k;
+      ++n;
+      if (c.off != s * sstr + r * slot || c.c.s != s || c.c.n != k || c.c.r != r) ++bad;
+      c.next();
+    }
+  }
+  printf("%ld %ld\n", n, bad);
+  return 0;
+}
+""")
+    n, bad = map(int, _run_cpp(tmp_path, prog).split())
+    assert n > 100000 and bad == 0
+
+
+def test_tile_order_is_a_bijection(tmp_path):
+    src = open(os.path.join(CSRC, "internal.h")).read()
+    consts = "\n".join(re.findall(r"constexpr int k(?:TileGroupX)\s*=\s*\d+;", src))
+    idx = _function(src, "__host__ __device__ inline long tile_index(")
+    crd = _function(src, "__host__ __device__ inline void tile_coords(")
+    prog = ("#include <cstdio>\n#include <algorithm>\n#include <vector>\nusing std::min;\n"
+            "#define __host__\n#define __device__\n" + consts + "\n" + idx + "\n" + crd + r"""
+int main() {
+  long bad = 0, cases = 0;
+  for (int ntz = 1; ntz <= 9; ntz += 2)
+    for (int ntx = 1; ntx <= 23; ntx += 3)
+      for (int S = 1; S <= 5; S += 2) {
+        const int total = ntz * ntx * S;
+        std::vector<int> seen(total, 0);
+        for (int s = 0; s < S; ++s)
+          for (int tx = 0; tx < ntx; ++tx)
+            for (int tz = 0; tz < ntz; ++tz) {
+              const long l = tile_index(tx, tz, s, ntz, ntx, S);
+              if (l < 0 || l >= total) { ++bad; continue; }
+              seen[l]++;
+              int a, b, c;
+              tile_coords((int)l, ntz, ntx, S, a, b, c);
+              if (a != tx || b != tz || c != s) ++bad;
+            }
+        for (int v : seen) if (v != 1) ++bad;
+        // hardware workgroup b -> logical tile (b & 7) * per + (b >> 3)
+        const int per = (total + 7) >> 3;
+        std::vector<int> hit(total, 0);
+        for (int b = 0; b < per * 8; ++b) {
+          const int l = (b & 7) * per + (b >> 3);
+          if (l < total) hit[l]++;
+        }
+        for (int v : hit) if (v != 1) ++bad;
+        ++cases;
+      }
+  printf("%ld %ld\n", cases, bad);
+  return 0;
+}
+""")
+    cases, bad = map(int, _run_cpp(tmp_path, prog).split())
+    assert cases > 100 and bad == 0
+
+
+@pytest.mark.parametrize("per", [1, 3, 5])
+def test_scatter_wait_counts_are_exact(per):
+    for q0 in range(0, 3):
+        for length in range(1, 14):
+            q1 = q0 + length
+            ops = []                                  # program order of vector-memory operations
+
+            def issue(q):
+                if q < q1:
+                    ops.extend(("load", q) for _ in range(per))
+
+            def consume(q):
+                ops.extend(("store", q) for _ in range(2))
+
+            issue(q0)
+            issue(q0 + 1)
+            issue(q0 + 2)
+            for q in range(q0, q1):
+                last = max(i for i, o in enumerate(ops) if o == ("load", q))
+                younger = len(ops) - 1 - last
+                y = min(2, q1 - 1 - q)
+                c = min(3, q - q0)
+                assert younger == per * y + 2 * c, (q0, q1, q)
+                issue(q + 3)
+                consume(q)
