@@ -29,6 +29,8 @@ from .fd import (  # noqa: F401
     born_adjoint,
     born_ext_fwd,
     born_ext_adj,
+    born_ext_tau_fwd,
+    born_ext_tau_adj,
     objective,
     gradient,
     vp_objective,

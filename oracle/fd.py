@@ -39,6 +39,14 @@ readings are made and used everywhere below:
   model grid; the forward source is
   s_n(z, y+h) += 2 p~(z,y,h) / (v(z,y)^3 dt^2) * T2u_n(z, y-h)
   (terms leaving the padded grid are dropped); at h = 0 this is Born.
+* Time-lag extension (the other extension of Section 2, the paper's choice
+  in four of its five examples; its discretization is not printed either):
+  lag tau_k = k L dt, k in [-K, K], ntau = 2K+1, L a whole number of time
+  steps, symmetric convention (source side t - tau, receiver side t + tau).
+  The extended perturbation p~(z, y, k) lives on the model grid; the
+  scattering source of equation n is
+  s_n(z, y) += 2 p~(z,y,k) / (v(z,y)^3 dt^2) * T2u_{n - 2kL}(z, y)
+  for 0 <= n - 2kL <= nt - 2 (other terms are dropped); at K = 0 this is Born.
 * DSO operator D of eq. fwime.obj: diagonal, weight d_h per offset, supplied
   by the caller.
 """
@@ -428,6 +436,72 @@ def born_ext_adj(g: Grid, vel: np.ndarray, geom: Geometry, data: np.ndarray, nh:
         _, hist = med.forward_record(_point_source(med, geom, s), rx, rz, keep=True)
         lam = med.adjoint(_receiver_injection(med, rx, rz, np.asarray(data[s], dtype=np.float64)))
         acc += _ext_image(med, hs, lambda n: med.t2(hist, n), lam)
+    return acc * 2.0 / (med.vel[None] ** 3 * g.dt ** 2)
+
+
+# ----------------------------------------------------------------------------
+# Extended Born with time lags and its adjoint
+# ----------------------------------------------------------------------------
+
+def _lags(ntau: int) -> np.ndarray:
+    if ntau < 1 or ntau % 2 == 0:
+        raise ValueError("ntau must be odd and positive")
+    K = (ntau - 1) // 2
+    return np.arange(-K, K + 1)
+
+
+def born_ext_tau_fwd(g: Grid, vel: np.ndarray, geom: Geometry, ptau: np.ndarray, lag: int) -> np.ndarray:
+    """B~_tau p~: data of the time-lag scattering source.
+
+    The source of equation n is sum_k c(z,y,k) T2u_{n-2kL}(z,y) on the model
+    grid, c = 2 p~ / (v^3 dt^2), L = lag (time steps per lag unit); terms whose
+    background time falls outside equations 0 .. nt-2 are dropped.
+    """
+    _check(g, vel, geom)
+    if int(lag) < 1:
+        raise ValueError("lag must be a positive number of time steps")
+    med = _Medium(g, vel)
+    ks = _lags(ptau.shape[0])
+    coef = _ext_coef(med, ptau)
+    nb = g.nb
+    zs, ys = slice(nb, nb + g.nz), slice(nb, nb + g.nx)
+    nrec = np.asarray(geom.rec_ix).shape[1]
+    out = np.zeros((geom.nshots, nrec, g.nt))
+    for s in range(geom.nshots):
+        rx, rz = _receivers(med, geom, s)
+        _, hist = med.forward_record(_point_source(med, geom, s), rx, rz, keep=True)
+
+        def source(n):
+            src = np.zeros(med.shape)
+            for i, k in enumerate(ks):
+                m = n - 2 * int(k) * int(lag)
+                if 0 <= m <= g.nt - 2:
+                    src[ys, zs] += coef[i] * med.t2(hist, m)[ys, zs]
+            return src
+
+        out[s], _ = med.forward_record(source, rx, rz)
+    return out
+
+
+def born_ext_tau_adj(g: Grid, vel: np.ndarray, geom: Geometry, data: np.ndarray, ntau: int, lag: int) -> np.ndarray:
+    """B~_tau^T d: p~(z,y,k) = 2/(v^3 dt^2) sum_s sum_n T2u_{n-2kL}(z,y) lambda_n(z,y)."""
+    _check(g, vel, geom)
+    if int(lag) < 1:
+        raise ValueError("lag must be a positive number of time steps")
+    med = _Medium(g, vel)
+    ks = _lags(ntau)
+    nb = g.nb
+    zs, ys = slice(nb, nb + g.nz), slice(nb, nb + g.nx)
+    acc = np.zeros((ntau, g.nx, g.nz))
+    for s in range(geom.nshots):
+        rx, rz = _receivers(med, geom, s)
+        _, hist = med.forward_record(_point_source(med, geom, s), rx, rz, keep=True)
+        lam = med.adjoint(_receiver_injection(med, rx, rz, np.asarray(data[s], dtype=np.float64)))
+        for n in range(g.nt - 1):
+            for i, k in enumerate(ks):
+                m = n - 2 * int(k) * int(lag)
+                if 0 <= m <= g.nt - 2:
+                    acc[i] += med.t2(hist, m)[ys, zs] * lam[n][ys, zs]
     return acc * 2.0 / (med.vel[None] ** 3 * g.dt ** 2)
 
 

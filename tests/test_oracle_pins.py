@@ -440,3 +440,52 @@ def test_vp_objective_at_zero_and_eps_zero(vp_case):
     alpha = float(b @ b) / float(b @ (H0 @ b))
     assert rel_l2(p.ravel(), alpha * b) < 1e-10
     assert phis[1] == pytest.approx(phis[0] - 0.5 * alpha * float(b @ b), rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Extended Born with time lags (the time-lag extension of Section 2)
+# ---------------------------------------------------------------------------
+
+def test_dot_born_time_lag(small):
+    # lags 2kL reach past both ends of the record (nt 120, K 2, L 7: up to 28
+    # steps), so dropped terms are exercised too
+    w, g, geo = small
+    rng = np.random.default_rng(21)
+    pt = rng.standard_normal((5, w.nx, w.nz))
+    d = rng.standard_normal((w.nshots, w.nrec, w.nt))
+    lhs = np.sum(oracle.born_ext_tau_fwd(g, w.vel, geo, pt, 7) * d)
+    rhs = np.sum(pt * oracle.born_ext_tau_adj(g, w.vel, geo, d, 5, 7))
+    assert dot_err(lhs, rhs) < 1e-10
+
+
+def test_time_lag_zero_lag_is_born(small):
+    # one lag (K = 0): the Born operator of the same perturbation, forward and adjoint
+    w, g, geo = small
+    rng = np.random.default_rng(22)
+    dv = rng.standard_normal((w.nx, w.nz))
+    dv_pad = np.zeros((w.nx + 2 * w.nb, w.nz + 2 * w.nb))
+    dv_pad[w.nb:w.nb + w.nx, w.nb:w.nb + w.nz] = dv
+    fwd = oracle.born_ext_tau_fwd(g, w.vel, geo, dv[None], 3)
+    assert rel_l2(fwd, oracle.born(g, w.vel, geo, dv_pad)) < 1e-12
+    d = rng.standard_normal((w.nshots, w.nrec, w.nt))
+    adj = oracle.born_ext_tau_adj(g, w.vel, geo, d, 1, 3)[0]
+    ref = oracle.born_adjoint(g, w.vel, geo, d)[w.nb:w.nb + w.nx, w.nb:w.nb + w.nz]
+    assert rel_l2(adj, ref) < 1e-12
+
+
+@pytest.mark.parametrize("lag", [1, 3])
+def test_time_lag_positive_lag_is_a_delay(small, lag):
+    # p~ only at lag k = +1: the scattering source of equation n is c T2u_{n-2L},
+    # i.e. the zero-lag source delayed by 2L steps, and the recursion is
+    # shift-invariant in time, so the data are the zero-lag data delayed by 2L
+    w, g, geo = small
+    rng = np.random.default_rng(23)
+    dv = rng.standard_normal((w.nx, w.nz))
+    p1 = np.zeros((3, w.nx, w.nz))
+    p1[2] = dv
+    d1 = oracle.born_ext_tau_fwd(g, w.vel, geo, p1, lag)
+    d0 = oracle.born_ext_tau_fwd(g, w.vel, geo, dv[None], lag)
+    sh = 2 * lag
+    assert np.abs(d0).max() > 0
+    assert np.all(d1[:, :, :sh] == 0)
+    assert rel_l2(d1[:, :, sh:], d0[:, :, :-sh]) < 1e-13
