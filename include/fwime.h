@@ -107,6 +107,28 @@ int fwime_born_ext_adj(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *
                        const fwime_geom_t *geom, int32_t nh, const float *data,
                        float *ptilde_out, void *stream);
 
+/* Extended Born modeling with time lags B~_tau p~ (Section 2: B~ is extended
+ * with either time lags or horizontal subsurface offsets).  Lags
+ * tau_k = k lag dt, k = -K .. K, ntau = 2K+1 (odd, <= 1023), lag >= 1 time
+ * steps with lag (ntau - 1) <= 4 nt.  The scattering source of equation n is
+ * sum_k 2 p~(z,y,k) / (v(z,y)^3 dt^2) T2u_{n-2k lag}(z,y) on the model grid,
+ * terms whose background step falls outside 0 .. nt-2 dropped.  ptau: DEVICE
+ * [ntau][nx][nz]; data as above (overwritten).  The background's T2 history of
+ * a shot batch is held whole: about (2 nt + 10) padded fields per shot of
+ * device memory, which sets the batch size; FWIME_ENOMEM if one shot does
+ * not fit. */
+int fwime_born_ext_tau_fwd(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                           const fwime_geom_t *geom, int32_t ntau, int32_t lag,
+                           const float *ptau, float *data, void *stream);
+
+/* Adjoint of fwime_born_ext_tau_fwd:
+ * ptau_out(z,y,k) = 2/(v(z,y)^3 dt^2) sum_shots sum_n T2u_{n-2k lag}(z,y) lambda_n(z,y),
+ * with lambda the adjoint field driven by `data` at the receivers.  ptau_out:
+ * DEVICE [ntau][nx][nz] (overwritten); about 2 nt + 8 padded fields per shot. */
+int fwime_born_ext_tau_adj(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                           const fwime_geom_t *geom, int32_t ntau, int32_t lag,
+                           const float *data, float *ptau_out, void *stream);
+
 /* FWIME objective of eq. fwime.obj at the given p~ and its gradients:
  *   r = f(m) + B~(m) p~ - dobs,
  *   obj = 1/2 ||r||^2 + eps^2/2 sum_h dso[h]^2 ||p~_h||^2,

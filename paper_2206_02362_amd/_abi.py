@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_gradient", "fwime_vp_solve", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -80,6 +80,10 @@ def load() -> ctypes.CDLL:
     lib.fwime_born_ext_fwd.restype = I
     lib.fwime_born_ext_adj.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
     lib.fwime_born_ext_adj.restype = I
+    lib.fwime_born_ext_tau_fwd.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.fwime_born_ext_tau_fwd.restype = I
+    lib.fwime_born_ext_tau_adj.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.fwime_born_ext_tau_adj.restype = I
     lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
     lib.fwime_vp_solve.restype = I
     lib.fwime_vp_solve.argtypes = [P, P, P, P, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
@@ -218,6 +222,22 @@ class Context:
             _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _dptr(ptilde_out, (nh, grid.nx, grid.nz)),
             _stream(vel.device)))
 
+    def fwime_born_ext_tau_fwd(self, grid: Grid, vel, geom: Geometry, ntau: int, lag: int, ptau, data):
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_born_ext_tau_fwd(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(ntau), int(lag),
+            _dptr(ptau, (ntau, grid.nx, grid.nz)), _dptr(data, (geom.nshots, geom.nrec, grid.nt)),
+            _stream(vel.device)))
+
+    def fwime_born_ext_tau_adj(self, grid: Grid, vel, geom: Geometry, ntau: int, lag: int, data, ptau_out):
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_born_ext_tau_adj(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(ntau), int(lag),
+            _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _dptr(ptau_out, (ntau, grid.nx, grid.nz)),
+            _stream(vel.device)))
+
     def fwime_gradient(self, grid: Grid, vel, geom: Geometry, nh: int, ptilde, dobs, eps: float, dso,
                        obj, grad_vel, grad_ptilde):
         g = grid._c()
@@ -311,6 +331,16 @@ class Context:
     def born_ext_adj(self, grid: Grid, vel, geom: Geometry, data, nh: int):
         out = torch.empty((nh, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
         self.fwime_born_ext_adj(grid, vel, geom, nh, data, out)
+        return out
+
+    def born_ext_tau_fwd(self, grid: Grid, vel, geom: Geometry, ptau, lag: int):
+        data = torch.empty((geom.nshots, geom.nrec, grid.nt), device=vel.device, dtype=torch.float32)
+        self.fwime_born_ext_tau_fwd(grid, vel, geom, int(ptau.shape[0]), lag, ptau, data)
+        return data
+
+    def born_ext_tau_adj(self, grid: Grid, vel, geom: Geometry, data, ntau: int, lag: int):
+        out = torch.empty((ntau, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        self.fwime_born_ext_tau_adj(grid, vel, geom, ntau, lag, data, out)
         return out
 
     def gradient(self, grid: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):

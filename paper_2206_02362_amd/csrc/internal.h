@@ -227,6 +227,19 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
                             int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc, float *parts,
                             hipStream_t st);
 
+// Time-lag extension, lags tau_k = k L dt, k in [-K, K] (g.nh = 2K+1, g.H = K).
+// Slots hold one padded field per time step, slot n of shot s at
+// base + s*sstride + n*slot; nslots = nt - 1 steps.
+//   scatter: out_n(z, y) = sum_k c(z, y, k) in_{n-2kL}(z, y) on the model grid
+//            (terms with n - 2kL outside [0, nslots) dropped; cells outside the
+//            model grid are not written)
+//   image:   acc(z, y, k) += 2 / (v(z,y)^3 dt^2) sum_s sum_n in_{n-2kL}(z, y) lam_n(z, y)
+hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const float *in, float *out, long slot,
+                              long sstride, int nslots, int nshots, hipStream_t st);
+hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, const float *lam, long lam_slot,
+                            long lam_sstride, int nslots, int nshots, const ExtGeom &g, int L, const float *vel,
+                            float dt, float *acc, hipStream_t st);
+
 // gacc(x,z) += sum_s sum_{n<nk} (t2u_n + t2d_n) lam_n + t2u_n rho_n
 hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
                              const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,

@@ -884,6 +884,81 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
 }
 
 // ---------------------------------------------------------------------------
+// Time-lag extension (lags tau_k = k L dt, k = -K .. K; the other extension of
+// Section 2).  A model cell's scattering source at step n takes the
+// background's T2 term at steps n - 2kL, and its image at lag k correlates
+// that term with the adjoint field along time.  One thread per model cell
+// and shot (scatter) or per model cell and lag (image), cells z-fastest so
+// every access of a wavefront is one column run; the terms are summed in the
+// order k = -K .. K, and over shots then steps.
+// ---------------------------------------------------------------------------
+__global__ void k_tau_scatter(const float *coef, const float *in, float *out, long slot, long sstride, int nslots,
+                              int K, int L, int nz, int nx, int nb, int LZ, int nshots) {
+  const long ncell = (long)nx * nz;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ncell * nshots;
+       i += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(i / ncell);
+    const long cell = i - (long)s * ncell;
+    const int y = (int)(cell / nz), z = (int)(cell - (long)y * nz);
+    const long off = (long)s * sstride + (long)(y + nb) * LZ + (z + nb);
+    for (int n = 0; n < nslots; ++n) {
+      float acc = 0.f;
+      for (int k = -K; k <= K; ++k) {
+        const int m = n - 2 * k * L;
+        if (m >= 0 && m < nslots) acc = fmaf(coef[((long)(k + K) * nx + y) * nz + z], in[off + (long)m * slot], acc);
+      }
+      out[off + (long)n * slot] = acc;
+    }
+  }
+}
+
+__global__ void k_tau_image(const float *in, long in_slot, long in_sstride, const float *lam, long lam_slot,
+                            long lam_sstride, int nslots, int nshots, int K, int L, int nz, int nx, int nb, int LZ,
+                            const float *vel, float dt, float *acc) {
+  const long ncell = (long)nx * nz;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ncell * (2 * K + 1);
+       i += (long)gridDim.x * blockDim.x) {
+    const int ik = (int)(i / ncell);
+    const long cell = i - (long)ik * ncell;
+    const int y = (int)(cell / nz), z = (int)(cell - (long)y * nz);
+    const long pc = (long)(y + nb) * LZ + (z + nb);
+    const int sh = 2 * (ik - K) * L;
+    float sum = 0.f;
+    for (int s = 0; s < nshots; ++s) {
+      const float *a = in + (long)s * in_sstride + pc;
+      const float *b = lam + (long)s * lam_sstride + pc;
+      for (int n = max(0, sh); n < min(nslots, nslots + sh); ++n)   // 0 <= n - sh < nslots
+        sum = fmaf(a[(long)(n - sh) * in_slot], b[(long)n * lam_slot], sum);
+    }
+    const float v = vel[cell];
+    acc[i] += 2.f / (v * v * v * dt * dt) * sum;
+  }
+}
+
+static unsigned tau_blocks(long n) {
+  const long b = (n + 255) / 256;
+  return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
+}
+
+hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const float *in, float *out, long slot,
+                              long sstride, int nslots, int nshots, hipStream_t st) {
+  if (nslots <= 0 || nshots <= 0) return hipSuccess;
+  k_tau_scatter<<<tau_blocks((long)g.nx * g.nz * nshots), 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L,
+                                                                        g.nz, g.nx, g.nb, g.LZ, nshots);
+  return hipGetLastError();
+}
+
+hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, const float *lam, long lam_slot,
+                            long lam_sstride, int nslots, int nshots, const ExtGeom &g, int L, const float *vel,
+                            float dt, float *acc, hipStream_t st) {
+  if (nslots <= 0 || nshots <= 0) return hipSuccess;
+  k_tau_image<<<tau_blocks((long)g.nx * g.nz * g.nh), 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot,
+                                                                     lam_sstride, nslots, nshots, g.H, L, g.nz, g.nx,
+                                                                     g.nb, g.LZ, vel, dt, acc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // gacc(x, z) += sum_s sum_n (t2u_n + t2d_n) lam_n + t2u_n rho_n   (padded grid)
 // ---------------------------------------------------------------------------
 __global__ void k_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,

@@ -939,6 +939,156 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
 }
 
 // ---------------------------------------------------------------------------
+// Extended Born with time lags (lags tau_k = k L dt, k = -K .. K) and its
+// adjoint.  The scattering source at step n takes the background's T2 term at
+// steps n - 2kL, after n as well as before it, so the background's T2 history
+// of a shot batch is kept whole (nt - 1 fields per shot); the batch size
+// follows from that.  The background is carried in extended precision, as in
+// the offset operators.
+// ---------------------------------------------------------------------------
+static int check_tau(fwime_ctx_t *ctx, const fwime_grid_t *g, int ntau, int lag) {
+  if (ntau < 1 || ntau % 2 == 0 || ntau > 1023) return set_err(ctx, FWIME_EINVAL, "ntau must be odd, 1 <= ntau <= 1023");
+  if (lag < 1 || (long)lag * (ntau - 1) > 4L * g->nt)
+    return set_err(ctx, FWIME_EINVAL, "lag must be >= 1 with lag (ntau - 1) <= 4 nt");
+  return FWIME_OK;
+}
+
+// Background T2 history of a shot batch: march all nt - 1 steps, T2 of step n
+// into slot n of hist (per-shot stride hstride).
+static int tau_background(fwime_ctx_t *ctx, const Common &c, const fwime_grid_t *g, const fwime_geom_t *geo,
+                          int s0, int Sb, const DevTables &t, float *pairs, unsigned short *lows, float *hist,
+                          long hstride, hipStream_t st) {
+  const Dims &d = c.d;
+  HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
+  HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
+  Ring4 fu(pairs, d.field * Sb);
+  Ring4L lu(lows, d.field * Sb);
+  const float *wav_b = geo->wavelet + (long)s0 * g->nt;
+  return march2(ctx, c, fu, Sb, 0, g->nt - 1, kModeT2, [&](Step2Args &p, int n, int k) {
+    p.a.t2 = hist + (long)n * d.field;
+    p.t2b = k == 2 ? hist + (long)(n + 1) * d.field : nullptr;
+    p.a.t2_sstride = hstride;
+    with_src2(p, t, wav_b, g, n);
+  }, st, &lu);
+}
+
+int fwime_born_ext_tau_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                           int32_t ntau, int32_t lag, const float *ptau, float *data, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_tau(ctx, g, ntau, lag))) return rc;
+  if (!data || !ptau) return set_err(ctx, FWIME_EINVAL, "data or ptau is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {{ptau, (long)ntau * g->nx * g->nz}}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, ntau, (ntau - 1) / 2};
+  const int ns = g->nt - 1;                        // time steps (equations)
+  // per shot: T2 history and source history (ns fields each), the two
+  // wavefields' rings (8 fields) and the background's BF16 low parts (2)
+  const long per_shot = (2L * ns + 10) * d.field * 4 + (long)geo->nrec * 64;
+  const size_t fixed = (size_t)d.field * 8 + (size_t)ntau * d.nx * d.nz * 4;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches, true);
+
+  float *coef = nullptr, *pairs = nullptr, *hist = nullptr, *sc = nullptr;
+  unsigned short *lows = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX + kGxPad);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&coef, (long)ntau * d.nx * d.nz);
+  cv.add(&pairs, 8 * d.field * S);
+  cv.add(&lows, 4 * d.field * S);
+  cv.add(&hist, (long)ns * d.field * S);
+  cv.add(&sc, (long)ns * d.field * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  HIPCHK(launch_ext_coef(ptau, vel, eg, (float)g->dt, coef, st));
+
+  const long hstride = (long)ns * d.field;         // per shot in hist / sc
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    if ((rc = tau_background(ctx, c, g, geo, s0, Sb, t, pairs, lows, hist, hstride, st))) return rc;
+    HIPCHK(launch_zero(sc, hstride * Sb, st));
+    HIPCHK(launch_tau_scatter(coef, eg, lag, hist, sc, d.field, hstride, ns, Sb, st));
+    float *wp = pairs + 4 * d.field * Sb;
+    HIPCHK(launch_zero(wp, 4 * d.field * Sb, st));
+    Ring4 fw(wp, d.field * Sb);
+    rc = march2(ctx, c, fw, Sb, 0, ns, kModeDsrc, [&](Step2Args &p, int n, int k) {
+      with_dsrc2(p, sc + (long)n * d.field, d.field, k, hstride);
+      with_rec_extract(p.a, t, out_b, g->nt, n);
+    }, st);
+    if (rc) return rc;
+    HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
+  }
+  return FWIME_OK;
+}
+
+int fwime_born_ext_tau_adj(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                           int32_t ntau, int32_t lag, const float *data, float *ptau_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_tau(ctx, g, ntau, lag))) return rc;
+  if (!data || !ptau_out) return set_err(ctx, FWIME_EINVAL, "data or ptau_out is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  if ((rc = check_inputs(ctx, g, vel, geo, {{data, (long)geo->nshots * geo->nrec * g->nt}}, st))) return rc;
+
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, ntau, (ntau - 1) / 2};
+  const int ns = g->nt - 1;
+  const int R = g->nt + 1;                         // adjoint field of every time 0 .. nt
+  // per shot: T2 history (ns fields), adjoint history (R), background ring (4), low parts (2)
+  const long per_shot = ((long)ns + R + 6) * d.field * 4 + (long)geo->nrec * 64;
+  const size_t fixed = (size_t)d.field * 8;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches, true);
+
+  float *pairs = nullptr, *hist = nullptr, *lam = nullptr;
+  unsigned short *lows = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX + kGxPad);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&pairs, 4 * d.field * S);
+  cv.add(&lows, 4 * d.field * S);
+  cv.add(&hist, (long)ns * d.field * S);
+  cv.add(&lam, (long)R * d.field * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  HIPCHK(launch_zero(ptau_out, (long)ntau * d.nx * d.nz, st));
+
+  const long hstride = (long)ns * d.field, lstride = (long)R * d.field;
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    const float *data_b = data + (long)s0 * geo->nrec * g->nt;
+    if ((rc = tau_background(ctx, c, g, geo, s0, Sb, t, pairs, lows, hist, hstride, st))) return rc;
+    HIPCHK(launch_zero(lam, lstride * Sb, st));
+    if ((rc = march2_back_lambda(ctx, c, lam, lstride, R, Sb, 0, g->nt - 1, t, data_b, g->nt, st))) return rc;
+    HIPCHK(launch_tau_image(hist, d.field, hstride, lam, d.field, lstride, ns, Sb, eg, lag, vel, (float)g->dt,
+                            ptau_out, st));
+  }
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Background checkpoints of the extended-precision adjoint kept across calls
 // with the same model and shots (the variable-projection step): per shot
 // 2 nseg fields (FP32 and BF16 low parts) in shot order.  `valid` once a call
