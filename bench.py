@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only the serving replay")
     ap.add_argument("--vp-iters", type=int, default=2,
                     help="CG iterations of the variable-projection step to time (0: skip)")
+    ap.add_argument("--tau-shots", type=int, default=8,
+                    help="shots of the time-lag extended Born pair to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -359,6 +361,38 @@ def main():
               "objective": [float(x) for x in phi]}
         log(f"vp: {per_iter:.2f} s per CG iteration, objective {vp['objective']}")
 
+    tau = None
+    if args.tau_shots > 0:
+        # extended Born with time lags: 101 lags of 16 ms (the paper's Marmousi2
+        # setting) on the first shots of the workload; each shot's background
+        # history is about 2 nt padded fields, so only a few shots fit at once
+        outs.clear()
+        ns_tau = min(args.tau_shots, w.nshots)
+        ntau, lag = 101, max(1, int(round(0.016 / w.dt)))
+        gsub = fw.Geometry(w.src_iz[:ns_tau], w.src_ix[:ns_tau], w.rec_iz[:ns_tau], w.rec_ix[:ns_tau],
+                           geo.wavelet[:ns_tau].contiguous())
+        ptau = torch.tensor(1e-2 * synth.random_ptilde(ntau, w.nz, w.nx, 79), dtype=torch.float32, device=dev)
+        log(f"time-lag extension: {ns_tau} shots, ntau {ntau}, lag {lag} steps")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dtau = ctx.born_ext_tau_fwd(grid, vel, gsub, ptau, lag)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t
+        t = time.perf_counter()
+        img = ctx.born_ext_tau_adj(grid, vel, gsub, dtau, ntau, lag)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter() - t
+        cells = ns_tau * NZ * NX * (w.nt - 1)
+        tau = {"workload": f"{w.name}: {ns_tau} shots, nt {w.nt}, ntau {ntau}, lag {lag} steps "
+                           f"({lag * w.dt * 1e3:.0f} ms)",
+               "fwd_s": t_f, "adj_s": t_a,
+               "fwd_cell_updates_per_s": 2 * cells / t_f, "adj_cell_updates_per_s": 2 * cells / t_a,
+               "lag_terms_per_s_fwd": ntau * ns_tau * w.nz * w.nx * (w.nt - 1) / t_f,
+               "note": "two propagations per shot counted per operator; lag terms = ntau multiply-adds "
+                       "per model cell and step"}
+        log(f"time lag: forward {t_f:.2f} s, adjoint {t_a:.2f} s")
+        del dtau, img, ptau
+
     serving = None
     if args.serve_requests > 0:
         # give the device memory of the step back to the server's budget
@@ -394,6 +428,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
         "vp_step": vp,
+        "time_lag": tau,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)

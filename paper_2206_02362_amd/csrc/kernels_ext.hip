@@ -935,6 +935,103 @@ __global__ void k_tau_image(const float *in, long in_slot, long in_sstride, cons
   }
 }
 
+// Residue form.  With n = P q + r (P = 2L, 0 <= r < P) the lag terms only
+// connect steps of one residue: out_r[q] = sum_k c_k in_r[q - k], image_k =
+// sum_q in_r[q - k] lam_r[q], with x_r[q] = x_{Pq + r}.  A workgroup stages
+// the Q_r samples of a residue for 64 model cells (lane = cell) in LDS, so
+// each history sample is read from HBM once instead of once per lag.
+constexpr int kTauQMax = 128;                 // samples per residue held in LDS
+
+// Scatter: workgroup = (64-cell block, shot, residue); weights of the lane's
+// cell in registers (zero beyond K); the lag loop adds the same terms in the
+// same order as k_tau_scatter, so both give the same bits.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, const float *in, float *out, long slot,
+                                                         long sstride, int nslots, int K, int L, int nz, int nx,
+                                                         int nb, int LZ, int nshots, int ncb) {
+  __shared__ float win[kTauQMax * 64];
+  const int P = 2 * L;
+  const int b = blockIdx.x;
+  const int cbk = b % ncb;
+  const int s = (b / ncb) % nshots;
+  const int r = b / ncb / nshots;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long ncell = (long)nx * nz;
+  const long cell = (long)cbk * 64 + lane;
+  const bool cin = cell < ncell;
+  const int y = cin ? (int)(cell / nz) : 0, z = cin ? (int)(cell - (long)y * nz) : 0;
+  const long off = (long)s * sstride + (long)(y + nb) * LZ + (z + nb);
+  const int Q = (nslots - r + P - 1) / P;   // steps P q + r < nslots
+  for (int q = w; q < Q; q += 4) win[q * 64 + lane] = cin ? in[off + (long)(P * q + r) * slot] : 0.f;
+  float c[2 * KMAX + 1];
+#pragma unroll
+  for (int k = -KMAX; k <= KMAX; ++k)
+    c[k + KMAX] = (cin && k >= -K && k <= K) ? coef[((long)(k + K) * nx + y) * nz + z] : 0.f;
+  __syncthreads();
+  for (int q = w; q < Q; q += 4) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = -KMAX; k <= KMAX; ++k) {
+      const int j = q - k;                   // wave-uniform
+      if (j >= 0 && j < Q) acc = fmaf(c[k + KMAX], win[j * 64 + lane], acc);
+    }
+    if (cin) out[off + (long)(P * q + r) * slot] = acc;
+  }
+}
+
+// Image: workgroup = 64-cell block; it walks every shot and residue, staging
+// the history and adjoint samples, and wavefront w accumulates the lags
+// k = -K + w, -K + w + 4, ... of its cells in registers (at most KPW of them).
+template <int KPW>
+__global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_slot, long in_sstride,
+                                                       const float *lam, long lam_slot, long lam_sstride, int nslots,
+                                                       int nshots, int K, int L, int nz, int nx, int nb, int LZ,
+                                                       const float *vel, float dt, float *acc) {
+  __shared__ float ta[kTauQMax * 64], tb[kTauQMax * 64];
+  const int P = 2 * L;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long ncell = (long)nx * nz;
+  const long cell = (long)blockIdx.x * 64 + lane;
+  const bool cin = cell < ncell;
+  const int y = cin ? (int)(cell / nz) : 0, z = cin ? (int)(cell - (long)y * nz) : 0;
+  const long pc = (long)(y + nb) * LZ + (z + nb);
+  float sum[KPW];
+#pragma unroll
+  for (int i = 0; i < KPW; ++i) sum[i] = 0.f;
+  for (int s = 0; s < nshots; ++s) {
+    const float *a = in + (long)s * in_sstride + pc;
+    const float *bb = lam + (long)s * lam_sstride + pc;
+    for (int r = 0; r < P; ++r) {
+      const int Q = (nslots - r + P - 1) / P;
+      __syncthreads();                         // the previous residue's reads are done
+      for (int q = w; q < Q; q += 4) {
+        ta[q * 64 + lane] = cin ? a[(long)(P * q + r) * in_slot] : 0.f;
+        tb[q * 64 + lane] = cin ? bb[(long)(P * q + r) * lam_slot] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < KPW; ++i) {
+        const int k = -K + w + 4 * i;          // wave-uniform
+        if (k > K) break;
+        float t = 0.f;
+        for (int q = max(0, k); q < min(Q, Q + k); ++q) t = fmaf(ta[(q - k) * 64 + lane], tb[q * 64 + lane], t);
+        sum[i] += t;
+      }
+    }
+  }
+  if (!cin) return;
+  const float v = vel[cell];
+  const float sc = 2.f / (v * v * v * dt * dt);
+#pragma unroll
+  for (int i = 0; i < KPW; ++i) {
+    const int k = -K + w + 4 * i;
+    if (k > K) break;
+    acc[(long)(k + K) * ncell + cell] += sc * sum[i];
+  }
+}
+
 static unsigned tau_blocks(long n) {
   const long b = (n + 255) / 256;
   return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
@@ -943,8 +1040,24 @@ static unsigned tau_blocks(long n) {
 hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const float *in, float *out, long slot,
                               long sstride, int nslots, int nshots, hipStream_t st) {
   if (nslots <= 0 || nshots <= 0) return hipSuccess;
-  k_tau_scatter<<<tau_blocks((long)g.nx * g.nz * nshots), 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L,
-                                                                        g.nz, g.nx, g.nb, g.LZ, nshots);
+  const int P = 2 * L;
+  const long ncell = (long)g.nx * g.nz;
+  const int ncb = (int)((ncell + 63) / 64);
+  const long nblk = (long)ncb * nshots * P;
+  if ((nslots + P - 1) / P > kTauQMax || g.H > 64 || nblk >= (1L << 31)) {
+    k_tau_scatter<<<tau_blocks(ncell * nshots), 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz,
+                                                              g.nx, g.nb, g.LZ, nshots);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)nblk);
+#define FW_TAU_S(KM)                                                                                     \
+  k_tau_scatter_lds<KM><<<grid, 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz, g.nx, g.nb, \
+                                              g.LZ, nshots, ncb)
+  if (g.H <= 8) FW_TAU_S(8);
+  else if (g.H <= 16) FW_TAU_S(16);
+  else if (g.H <= 32) FW_TAU_S(32);
+  else FW_TAU_S(64);
+#undef FW_TAU_S
   return hipGetLastError();
 }
 
@@ -952,9 +1065,24 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
                             long lam_sstride, int nslots, int nshots, const ExtGeom &g, int L, const float *vel,
                             float dt, float *acc, hipStream_t st) {
   if (nslots <= 0 || nshots <= 0) return hipSuccess;
-  k_tau_image<<<tau_blocks((long)g.nx * g.nz * g.nh), 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot,
-                                                                     lam_sstride, nslots, nshots, g.H, L, g.nz, g.nx,
-                                                                     g.nb, g.LZ, vel, dt, acc);
+  const int P = 2 * L;
+  const long ncell = (long)g.nx * g.nz;
+  const int kpw = (g.nh + 3) / 4;                 // lags per wavefront
+  if ((nslots + P - 1) / P > kTauQMax || kpw > 32) {
+    k_tau_image<<<tau_blocks(ncell * g.nh), 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride,
+                                                          nslots, nshots, g.H, L, g.nz, g.nx, g.nb, g.LZ, vel, dt,
+                                                          acc);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)((ncell + 63) / 64));
+#define FW_TAU_I(KP)                                                                                              \
+  k_tau_image_lds<KP><<<grid, 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride, nslots, nshots, g.H, \
+                                            L, g.nz, g.nx, g.nb, g.LZ, vel, dt, acc)
+  if (kpw <= 4) FW_TAU_I(4);
+  else if (kpw <= 8) FW_TAU_I(8);
+  else if (kpw <= 16) FW_TAU_I(16);
+  else FW_TAU_I(32);
+#undef FW_TAU_I
   return hipGetLastError();
 }
 
