@@ -943,18 +943,24 @@ __global__ void k_tau_image(const float *in, long in_slot, long in_sstride, cons
 constexpr int kTauQMax = 128;                 // samples per residue held in LDS
 
 // Scatter: workgroup = (64-cell block, shot, residue); weights of the lane's
-// cell in registers (zero beyond K); the lag loop adds the same terms in the
-// same order as k_tau_scatter, so both give the same bits.
+// cell in registers (zero beyond K); every output adds the same terms in the
+// same order as in k_tau_scatter, so both give the same bits.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, const float *in, float *out, long slot,
                                                          long sstride, int nslots, int K, int L, int nz, int nx,
                                                          int nb, int LZ, int nshots, int ncb) {
   __shared__ float win[kTauQMax * 64];
   const int P = 2 * L;
-  const int b = blockIdx.x;
-  const int cbk = b % ncb;
-  const int s = (b / ncb) % nshots;
-  const int r = b / ncb / nshots;
+  // residue fastest, then shot, then cell block, in XCD-contiguous ranges:
+  // the workgroups of one cell block run together on one XCD and share its
+  // lag weights in that XCD's L2
+  const int total = ncb * nshots * P;
+  const int per = (total + 7) >> 3;
+  const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (b >= total) return;
+  const int r = b % P;
+  const int s = (b / P) % nshots;
+  const int cbk = b / P / nshots;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long ncell = (long)nx * nz;
@@ -969,14 +975,25 @@ __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, cons
   for (int k = -KMAX; k <= KMAX; ++k)
     c[k + KMAX] = (cin && k >= -K && k <= K) ? coef[((long)(k + K) * nx + y) * nz + z] : 0.f;
   __syncthreads();
-  for (int q = w; q < Q; q += 4) {
-    float acc = 0.f;
+  // four consecutive outputs q0 .. q0 + 3 per pass, so that each LDS read
+  // feeds up to four multiply-adds; inputs j = q0 + t are taken from the
+  // highest down, which adds every output's terms in ascending k
+  for (int q0 = 4 * w; q0 < Q; q0 += 16) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = -KMAX; k <= KMAX; ++k) {
-      const int j = q - k;                   // wave-uniform
-      if (j >= 0 && j < Q) acc = fmaf(c[k + KMAX], win[j * 64 + lane], acc);
+    for (int t = 3 + KMAX; t >= -KMAX; --t) {
+      const int j = q0 + t;                  // wave-uniform
+      if (j < 0 || j >= Q) continue;
+      const float x = win[j * 64 + lane];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int k = jj - t;                // output q0 + jj takes lag k from input j
+        if (k >= -KMAX && k <= KMAX) acc[jj] = fmaf(c[k + KMAX], x, acc[jj]);
+      }
     }
-    if (cin) out[off + (long)(P * q + r) * slot] = acc;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (cin && q0 + jj < Q) out[off + (long)(P * (q0 + jj) + r) * slot] = acc[jj];
   }
 }
 
@@ -1044,12 +1061,12 @@ hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const 
   const long ncell = (long)g.nx * g.nz;
   const int ncb = (int)((ncell + 63) / 64);
   const long nblk = (long)ncb * nshots * P;
-  if ((nslots + P - 1) / P > kTauQMax || g.H > 64 || nblk >= (1L << 31)) {
+  if ((nslots + P - 1) / P > kTauQMax || g.H > 64 || nblk + 8 >= (1L << 31)) {
     k_tau_scatter<<<tau_blocks(ncell * nshots), 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz,
                                                               g.nx, g.nb, g.LZ, nshots);
     return hipGetLastError();
   }
-  const dim3 grid((unsigned)nblk);
+  const dim3 grid((unsigned)((nblk + 7) / 8 * 8));
 #define FW_TAU_S(KM)                                                                                     \
   k_tau_scatter_lds<KM><<<grid, 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz, g.nx, g.nb, \
                                               g.LZ, nshots, ncb)
