@@ -362,7 +362,9 @@ def main():
         log(f"vp: {per_iter:.2f} s per CG iteration, objective {vp['objective']}")
 
     tau = None
-    if args.tau_shots > 0:
+    if args.tau_shots > 0 and max(1, int(round(0.016 / w.dt))) * 100 > 4 * w.nt:
+        log("time-lag extension skipped: the record is too short for 101 lags of 16 ms")
+    elif args.tau_shots > 0:
         # extended Born with time lags: 101 lags of 16 ms (the paper's Marmousi2
         # setting) on the first shots of the workload; each shot's background
         # history is about 2 nt padded fields, so only a few shots fit at once;
