@@ -998,8 +998,12 @@ __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, cons
 }
 
 // Image: workgroup = 64-cell block; it walks every shot and residue, staging
-// the history and adjoint samples, and wavefront w accumulates the lags
-// k = -K + w, -K + w + 4, ... of its cells in registers (at most KPW of them).
+// the history and adjoint samples.  Lags come in groups of four consecutive
+// ones, group G = w + 4 g to wavefront w (at most KPW lags per wavefront,
+// accumulated in registers): one adjoint sample and a window of four history
+// samples feed four multiply-adds.  Each lag sums its products in ascending
+// q, where every lag of the group is in range without a test and at the two
+// edges with one.
 template <int KPW>
 __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_slot, long in_sstride,
                                                        const float *lam, long lam_slot, long lam_sstride, int nslots,
@@ -1029,12 +1033,33 @@ __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < KPW; ++i) {
-        const int k = -K + w + 4 * i;          // wave-uniform
-        if (k > K) break;
-        float t = 0.f;
-        for (int q = max(0, k); q < min(Q, Q + k); ++q) t = fmaf(ta[(q - k) * 64 + lane], tb[q * 64 + lane], t);
-        sum[i] += t;
+      for (int g = 0; g < KPW / 4; ++g) {
+        const int k0 = -K + 4 * (w + 4 * g);   // lags k0 .. k0 + 3, wave-uniform
+        if (k0 > K) break;
+        float t[4] = {0.f, 0.f, 0.f, 0.f};
+        // lag k takes q in [max(0, k), min(Q, Q + k)); all four in [qlo, qhi)
+        const int qlo = max(0, k0 + 3), qhi = min(Q, Q + k0);
+        const int e0 = max(0, k0), e1 = min(qlo, Q);
+        for (int q = e0; q < e1; ++q) {
+          const float x = tb[q * 64 + lane];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            if (q >= k0 + jj && q < Q + k0 + jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
+        }
+        for (int q = qlo; q < qhi; ++q) {
+          const float x = tb[q * 64 + lane];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
+        }
+        const int h0 = max(qhi, qlo), h1 = min(Q, Q + k0 + 3);
+        for (int q = h0; q < h1; ++q) {
+          const float x = tb[q * 64 + lane];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            if (q >= k0 + jj && q < Q + k0 + jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) sum[4 * g + jj] += t[jj];
       }
     }
   }
@@ -1042,10 +1067,12 @@ __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_
   const float v = vel[cell];
   const float sc = 2.f / (v * v * v * dt * dt);
 #pragma unroll
-  for (int i = 0; i < KPW; ++i) {
-    const int k = -K + w + 4 * i;
-    if (k > K) break;
-    acc[(long)(k + K) * ncell + cell] += sc * sum[i];
+  for (int g = 0; g < KPW / 4; ++g) {
+    const int k0 = -K + 4 * (w + 4 * g);
+    if (k0 > K) break;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (k0 + jj <= K) acc[(long)(k0 + jj + K) * ncell + cell] += sc * sum[4 * g + jj];
   }
 }
 
@@ -1084,7 +1111,7 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
   if (nslots <= 0 || nshots <= 0) return hipSuccess;
   const int P = 2 * L;
   const long ncell = (long)g.nx * g.nz;
-  const int kpw = (g.nh + 3) / 4;                 // lags per wavefront
+  const int kpw = 4 * (((g.nh + 3) / 4 + 3) / 4); // lags per wavefront (whole groups of four)
   if ((nslots + P - 1) / P > kTauQMax || kpw > 32) {
     k_tau_image<<<tau_blocks(ncell * g.nh), 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride,
                                                           nslots, nshots, g.H, L, g.nz, g.nx, g.nb, g.LZ, vel, dt,
