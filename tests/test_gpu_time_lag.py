@@ -131,3 +131,24 @@ def test_time_lag_rejects_bad_arguments(ctx):
         with pytest.raises(fw.FwimeError):
             ctx.fwime_born_ext_tau_fwd(grid, tv, tg, ntau, lag, pt[:ntau] if ntau <= 5 else pt,
                                        dev(np.zeros((1, w.nrec, w.nt))))
+
+
+def test_time_lag_full_size_dot_product(ctx):
+    # the benchmark's setting (300 x 1700, nt 5000, 101 lags of 20 steps), 2
+    # shots: a property that holds at any size, since the oracle cannot run here
+    import torch
+    say("case: born_ext_tau dot product 300x1700 nt5000 ntau 101 lag 20, 2 shots")
+    w = synth.marmousi_set(2, 17)
+    grid, tv, tg = gpu_problem(w)
+    ntau, lag = 101, 20
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    pt = torch.randn((ntau, w.nx, w.nz), generator=g, device="cuda:0", dtype=torch.float32)
+    d = torch.randn((w.nshots, w.nrec, w.nt), generator=g, device="cuda:0", dtype=torch.float32)
+    bp = ctx.born_ext_tau_fwd(grid, tv, tg, pt, lag)
+    d2 = bp * (d.norm() / bp.norm()) + d
+    for name, dd in (("random d", d), ("d = Fp-scaled + d", d2)):
+        lhs = float((bp.double() * dd.double()).sum())
+        rhs = float((pt.double() * ctx.born_ext_tau_adj(grid, tv, tg, dd.contiguous(), ntau, lag).double()).sum())
+        say(f"  {name}: dot err {dot_err(lhs, rhs):.3e}")
+        if name != "random d":
+            assert dot_err(lhs, rhs) < DOT_TOL
