@@ -591,14 +591,27 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
 # Variable-projection step (eqs. vp.obj, pert.opt, vp.pseudo.inv)
 # ----------------------------------------------------------------------------
 
-def vp_objective(g: Grid, vel, geom: Geometry, ptilde, dres, eps: float, dso) -> float:
-    """Phi_eps,m(p~) = 1/2 || B~ p~ - dres ||^2 + eps^2/2 || D p~ ||^2, dres = d_obs - f(m) (eq. vp.obj)."""
-    r = born_ext_fwd(g, vel, geom, ptilde) - np.asarray(dres, dtype=np.float64)
+def _ext_pair(nh: int, lag):
+    """B~ and B~^T of the chosen extension: subsurface offsets (lag None) or
+    time lags with lag step `lag` (nh lags)."""
+    if lag is None:
+        return (lambda g, vel, geom, x: born_ext_fwd(g, vel, geom, x),
+                lambda g, vel, geom, d: born_ext_adj(g, vel, geom, d, nh))
+    return (lambda g, vel, geom, x: born_ext_tau_fwd(g, vel, geom, x, lag),
+            lambda g, vel, geom, d: born_ext_tau_adj(g, vel, geom, d, nh, lag))
+
+
+def vp_objective(g: Grid, vel, geom: Geometry, ptilde, dres, eps: float, dso, lag=None) -> float:
+    """Phi_eps,m(p~) = 1/2 || B~ p~ - dres ||^2 + eps^2/2 || D p~ ||^2, dres = d_obs - f(m) (eq. vp.obj).
+
+    lag None: subsurface offsets; otherwise time lags with that lag step."""
+    fwd, _ = _ext_pair(np.asarray(ptilde).shape[0], lag)
+    r = fwd(g, vel, geom, ptilde) - np.asarray(dres, dtype=np.float64)
     dso = np.asarray(dso, dtype=np.float64)
     return 0.5 * float(np.sum(r * r)) + 0.5 * eps ** 2 * float(np.sum((dso[:, None, None] * ptilde) ** 2))
 
 
-def vp_solve(g: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
+def vp_solve(g: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int, lag=None):
     """Variable-projection step by linear conjugate gradient.
 
     The minimizer of eq. vp.obj solves the normal equation
@@ -607,15 +620,17 @@ def vp_solve(g: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter
     Here: plain CG on that symmetric system from p~ = 0, niter iterations
     (stopping early only if the search direction has zero curvature).
     Returns p~ and Phi_eps,m at p~_0 = 0, p~_1, ..., each evaluated from its
-    definition (one extra application of B~ per iterate).
+    definition (one extra application of B~ per iterate).  B~ is extended
+    with subsurface offsets (lag None) or with nh time lags of step `lag`.
     """
+    fwd, adj = _ext_pair(nh, lag)
     dres = np.asarray(dobs, dtype=np.float64) - model(g, vel, geom)
     d2 = (eps * np.asarray(dso, dtype=np.float64)) ** 2
 
     def normal(x):
-        return born_ext_adj(g, vel, geom, born_ext_fwd(g, vel, geom, x), nh) + d2[:, None, None] * x
+        return adj(g, vel, geom, fwd(g, vel, geom, x)) + d2[:, None, None] * x
 
-    b = born_ext_adj(g, vel, geom, dres, nh)
+    b = adj(g, vel, geom, dres)
     p = np.zeros_like(b)
     r = b.copy()
     s = r.copy()
@@ -632,5 +647,5 @@ def vp_solve(g: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter
         rr_new = float(np.sum(r * r))
         s = r + (rr_new / rr) * s
         rr = rr_new
-        phis.append(vp_objective(g, vel, geom, p, dres, eps, dso))
+        phis.append(vp_objective(g, vel, geom, p, dres, eps, dso, lag))
     return p, phis

@@ -388,42 +388,50 @@ def test_gradient_ptilde_zero_is_fwi(grad_case):
 # direct solve
 # ---------------------------------------------------------------------------
 
-@pytest.fixture(scope="module")
-def vp_case():
+@pytest.fixture(scope="module", params=[None, 4], ids=["offsets", "time-lags"])
+def vp_case(request):
+    # the normal matrix assembled column by column, for the offset extension
+    # and for time lags (3 lags of 4 steps)
+    lag = request.param
     w = synth.tiny(nz=4, nx=6, nb=3, nt=50, nshots=2, nh=3, seed=21)
     g, geo = oracle_problem(w)
     true = w.vel * (1.0 + 0.05 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 22, 20.0))
     dobs = oracle.model(g, true, geo)
+    if lag is None:
+        fwd = lambda x: oracle.born_ext_fwd(g, w.vel, geo, x)
+        adj = lambda d: oracle.born_ext_adj(g, w.vel, geo, d, w.nh)
+    else:
+        fwd = lambda x: oracle.born_ext_tau_fwd(g, w.vel, geo, x, lag)
+        adj = lambda d: oracle.born_ext_tau_adj(g, w.vel, geo, d, w.nh, lag)
     n = w.nh * w.nx * w.nz
     cols = []
     for i in range(n):
         e = np.zeros(n)
         e[i] = 1.0
-        e = e.reshape(w.nh, w.nx, w.nz)
-        cols.append(oracle.born_ext_adj(g, w.vel, geo, oracle.born_ext_fwd(g, w.vel, geo, e), w.nh).ravel())
+        cols.append(adj(fwd(e.reshape(w.nh, w.nx, w.nz))).ravel())
     H0 = np.array(cols).T                          # B~* B~, column i = B~* B~ e_i
-    b = oracle.born_ext_adj(g, w.vel, geo, dobs - oracle.model(g, w.vel, geo), w.nh).ravel()
-    return w, g, geo, dobs, H0, b
+    b = adj(dobs - oracle.model(g, w.vel, geo)).ravel()
+    return w, g, geo, dobs, H0, b, lag
 
 
 def test_vp_normal_operator_symmetric_psd(vp_case):
-    w, g, geo, dobs, H0, b = vp_case
+    w, g, geo, dobs, H0, b, lag = vp_case
     assert np.linalg.norm(H0 - H0.T) <= 1e-10 * np.linalg.norm(H0)
     ev = np.linalg.eigvalsh(0.5 * (H0 + H0.T))
     assert ev.min() >= -1e-10 * ev.max() and ev.max() > 0
 
 
 def test_vp_cg_reaches_direct_solution(vp_case):
-    w, g, geo, dobs, H0, b = vp_case
+    w, g, geo, dobs, H0, b, lag = vp_case
     dso = synth.dso_weights(w.nh)
     lam = np.linalg.eigvalsh(0.5 * (H0 + H0.T)).max()
     eps = math.sqrt(0.1 * lam)                     # condition number about 20
     H = H0 + np.diag(np.repeat(eps ** 2 * dso ** 2, w.nx * w.nz))
     p_direct = np.linalg.solve(H, b).reshape(w.nh, w.nx, w.nz)
-    p, phis = oracle.vp_solve(g, w.vel, geo, dobs, w.nh, eps, dso, 40)
+    p, phis = oracle.vp_solve(g, w.vel, geo, dobs, w.nh, eps, dso, 40, lag)
     assert rel_l2(p, p_direct) < 1e-6
     dres = dobs - oracle.model(g, w.vel, geo)
-    phi_min = oracle.vp_objective(g, w.vel, geo, p_direct, dres, eps, dso)
+    phi_min = oracle.vp_objective(g, w.vel, geo, p_direct, dres, eps, dso, lag)
     # CG never increases the quadratic objective and stays above its minimum
     assert all(b2 <= a2 * (1 + 1e-12) for a2, b2 in zip(phis, phis[1:]))
     assert min(phis) >= phi_min * (1 - 1e-9)
@@ -431,11 +439,11 @@ def test_vp_cg_reaches_direct_solution(vp_case):
 
 
 def test_vp_objective_at_zero_and_eps_zero(vp_case):
-    w, g, geo, dobs, H0, b = vp_case
+    w, g, geo, dobs, H0, b, lag = vp_case
     # at p~ = 0 the objective is half the squared data residual; with eps = 0
     # one CG step moves along b = B~* dres by the exact line-search length
     dres = dobs - oracle.model(g, w.vel, geo)
-    p, phis = oracle.vp_solve(g, w.vel, geo, dobs, w.nh, 0.0, synth.dso_weights(w.nh), 1)
+    p, phis = oracle.vp_solve(g, w.vel, geo, dobs, w.nh, 0.0, synth.dso_weights(w.nh), 1, lag)
     assert phis[0] == pytest.approx(0.5 * float(np.sum(dres ** 2)), rel=1e-14)
     alpha = float(b @ b) / float(b @ (H0 @ b))
     assert rel_l2(p.ravel(), alpha * b) < 1e-10
