@@ -168,6 +168,17 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                    const double *dso, int32_t niter, float *ptilde_out, double *phi_out,
                    void *stream);
 
+/* The same variable-projection step with B~ extended by time lags (the
+ * paper's choice in four of its five examples): CG on
+ * (B~_tau* B~_tau + eps^2 D* D) p~ = B~_tau* (dobs - f(m)) with the operators
+ * of fwime_born_ext_tau_fwd / _adj (ntau lags of `lag` steps, same limits).
+ * dso: HOST double [ntau]; ptau_out: DEVICE [ntau][nx][nz]; phi_out as above.
+ * Device memory per shot as for fwime_born_ext_tau_fwd; no checkpoint cache. */
+int fwime_vp_solve_tau(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, int32_t ntau, int32_t lag, const float *dobs,
+                       double eps, const double *dso, int32_t niter, float *ptau_out,
+                       double *phi_out, void *stream);
+
 /* ---- Batched modeling of jobs with different grids ----------------------
  * One job = one call's worth of fwime_model (grid, velocity, shots).  All
  * jobs advance together: every time step is one launch over the tiles of all

@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -87,6 +87,8 @@ def load() -> ctypes.CDLL:
     lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
     lib.fwime_vp_solve.restype = I
     lib.fwime_vp_solve.argtypes = [P, P, P, P, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
+    lib.fwime_vp_solve_tau.restype = I
+    lib.fwime_vp_solve_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_gradient.restype = I
     lib.fwime_model_batch.argtypes = [P, ctypes.c_int32, P, P]
     lib.fwime_model_batch.restype = I
@@ -351,6 +353,29 @@ class Context:
         self.fwime_gradient(grid, vel, geom, nh, ptilde, dobs, eps, dso, obj, gv, gp)
         return obj, gv, gp
 
+
+    def fwime_vp_solve_tau(self, grid: Grid, vel, geom: Geometry, ntau: int, lag: int, dobs, eps: float, dso,
+                           niter: int, ptau_out):
+        """Variable-projection step with time lags; returns the objective history (niter + 1 floats)."""
+        g = grid._c()
+        ge = geom._c()
+        dso = np.ascontiguousarray(dso, dtype=np.float64)
+        if dso.shape != (ntau,):
+            raise ValueError("dso must have ntau entries")
+        if int(niter) < 0:
+            raise ValueError("niter must be >= 0")
+        phi = np.zeros(int(niter) + 1, dtype=np.float64)
+        self._check(self._lib.fwime_vp_solve_tau(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(ntau), int(lag),
+            _dptr(dobs, (geom.nshots, geom.nrec, grid.nt)), float(eps), dso.ctypes.data, int(niter),
+            _dptr(ptau_out, (ntau, grid.nx, grid.nz)), phi.ctypes.data, _stream(vel.device)))
+        return phi
+
+    def vp_solve_tau(self, grid: Grid, vel, geom: Geometry, dobs, ntau: int, lag: int, eps: float, dso, niter: int):
+        """p~ (time lags) after niter CG iterations of the variable-projection step, and the objective history."""
+        out = torch.empty((ntau, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        phi = self.fwime_vp_solve_tau(grid, vel, geom, ntau, lag, dobs, eps, dso, niter, out)
+        return out, phi
 
     def vp_solve(self, grid: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
         """p~ after niter CG iterations of the variable-projection step, and the objective history."""

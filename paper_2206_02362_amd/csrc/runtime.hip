@@ -1517,14 +1517,18 @@ extern "C" {
 // shot); the objective is tracked without further propagations as
 // Phi_k = 1/2 ||d_obs - f(m)||^2 - 1/2 (b + r_k) . p~_k, which holds for any
 // p~ with r = b - H p~ (b = B~* (d_obs - f(m)), H the normal matrix).
-int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
-                   int32_t nh, const float *dobs, double eps, const double *dso, int32_t niter,
-                   float *ptilde_out, double *phi_out, void *stream) {
+// The solver for either extension: subsurface offsets (tau false, nh
+// offsets) or time lags (tau true, nh lags of `lag` steps).
+static int vp_solve_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                        int32_t nh, bool tau, int32_t lag, const float *dobs, double eps, const double *dso,
+                        int32_t niter, float *ptilde_out, double *phi_out, void *stream) {
   if (!ctx) return FWIME_EINVAL;
   ctx->err.clear();
   hipStream_t st = (hipStream_t)stream;
   int rc;
-  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_nh(ctx, g, nh))) return rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) ||
+      (rc = tau ? check_tau(ctx, g, nh, lag) : check_nh(ctx, g, nh)))
+    return rc;
   if (!dobs || !dso || !ptilde_out || !phi_out) return set_err(ctx, FWIME_EINVAL, "null pointer argument");
   if (niter < 0) return set_err(ctx, FWIME_EINVAL, "niter must be >= 0");
   if (!std::isfinite(eps)) return set_err(ctx, FWIME_EINVAL, "eps must be finite");
@@ -1544,7 +1548,7 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   const int K = seg_len(g->nt);
   const long nseg = (g->nt - 1 + K - 1) / K;
   const long ck_elems = 2L * nseg * dd.field * geo->nshots;
-  bool use_cache = ctx->two_step;
+  bool use_cache = ctx->two_step && !tau;          // the time-lag adjoint keeps no checkpoints
   if (const char *e = std::getenv("FWIME_VP_NOCACHE")) use_cache = use_cache && std::atoi(e) == 0;
   if (use_cache) {
     size_t avail = 0, total = 0;
@@ -1611,7 +1615,15 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   if ((rc = dot(dres, dres, ndata, c0))) return rc;
   c0 *= 0.5;
   AdjCache *cp = use_cache ? &cache : nullptr;
-  if ((rc = born_ext_adj_run(ctx, g, vel, geo, nh, dres, b, stream, cp))) return rc;
+  auto fwd = [&](const float *x, float *d) {
+    return tau ? fwime_born_ext_tau_fwd(ctx, g, vel, geo, nh, lag, x, d, stream)
+               : fwime_born_ext_fwd(ctx, g, vel, geo, nh, x, d, stream);
+  };
+  auto adj = [&](const float *d, float *x) {
+    return tau ? fwime_born_ext_tau_adj(ctx, g, vel, geo, nh, lag, d, x, stream)
+               : born_ext_adj_run(ctx, g, vel, geo, nh, d, x, stream, cp);
+  };
+  if ((rc = adj(dres, b))) return rc;
   HIPCHK(hipMemsetAsync(ptilde_out, 0, img * sizeof(float), st));
   HIPCHK(hipMemcpyAsync(r, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(sdir, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -1620,8 +1632,8 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   int k = 0;
   for (; k < niter; ++k) {
     // q = (B~* B~ + eps^2 D* D) s
-    if ((rc = fwime_born_ext_fwd(ctx, g, vel, geo, nh, sdir, dtmp, stream))) return rc;
-    if ((rc = born_ext_adj_run(ctx, g, vel, geo, nh, dtmp, q, stream, cp))) return rc;
+    if ((rc = fwd(sdir, dtmp))) return rc;
+    if ((rc = adj(dtmp, q))) return rc;
     HIPCHK(launch_add_diag(q, sdir, e2d2, plane, nh, st));
     double curv = 0.0;
     if ((rc = dot(sdir, q, img, curv))) return rc;
@@ -1637,6 +1649,18 @@ int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   }
   for (int j = k + 1; j <= niter; ++j) phi_out[j] = phi_out[k];
   return FWIME_OK;
+}
+
+int fwime_vp_solve(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                   int32_t nh, const float *dobs, double eps, const double *dso, int32_t niter,
+                   float *ptilde_out, double *phi_out, void *stream) {
+  return vp_solve_run(ctx, g, vel, geo, nh, false, 0, dobs, eps, dso, niter, ptilde_out, phi_out, stream);
+}
+
+int fwime_vp_solve_tau(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       int32_t ntau, int32_t lag, const float *dobs, double eps, const double *dso, int32_t niter,
+                       float *ptau_out, double *phi_out, void *stream) {
+  return vp_solve_run(ctx, g, vel, geo, ntau, true, lag, dobs, eps, dso, niter, ptau_out, phi_out, stream);
 }
 
 int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo, int32_t nh,

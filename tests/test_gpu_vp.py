@@ -106,3 +106,27 @@ def test_vp_solve_full_size_decreases(ctx):
     say("  phi", list(phi))
     assert np.all(np.isfinite(phi)) and torch.isfinite(p).all().item()
     assert all(b < a for a, b in zip(phi, phi[1:]))
+
+
+@pytest.mark.parametrize("penalty", [False, True])
+def test_vp_solve_time_lag_matches_oracle(ctx, penalty):
+    # the same step with B~ extended by 5 time lags of 6 steps
+    w, g, geo, vel, dobs = _case()
+    ntau, lag = 5, 6
+    dso = synth.dso_weights(ntau)
+    eps = 0.0
+    if penalty:
+        dres = dobs.astype(np.float64) - oracle.model(g, vel, geo)
+        b = oracle.born_ext_tau_adj(g, vel, geo, dres, ntau, lag)
+        hb = oracle.born_ext_tau_adj(g, vel, geo, oracle.born_ext_tau_fwd(g, vel, geo, b, lag), ntau, lag)
+        eps = float(np.sqrt(0.3 * np.sum(b * hb) / np.sum(b * b)))
+    niter = 4
+    say(f"case: vp_solve_tau 24x32 nb8 nt160 ntau {ntau} lag {lag}, eps {eps:.3e}, {niter} iterations")
+    p_ref, phi_ref = oracle.vp_solve(g, vel, geo, dobs.astype(np.float64), ntau, eps, dso, niter, lag)
+    grid, tv, tg = gpu_problem(w)
+    p, phi = ctx.vp_solve_tau(grid, tv, tg, _dev(dobs), ntau, lag, eps, dso, niter)
+    e_p = rel_l2(p.double().cpu().numpy(), p_ref)
+    e_phi = max(abs(a - b) / abs(b) for a, b in zip(phi, phi_ref))
+    say("  rel-L2 p~", e_p, "objective", e_phi, "phi", list(phi))
+    assert e_p < TOL and e_phi < TOL
+    assert all(b <= a for a, b in zip(phi, phi[1:]))
