@@ -36,3 +36,11 @@ from .fd import (  # noqa: F401
     vp_objective,
     vp_solve,
 )
+from .inversion import (  # noqa: F401
+    hat_matrix,
+    spline_apply,
+    spline_adjoint,
+    two_loop,
+    lbfgs,
+    on_spline_grid,
+)
