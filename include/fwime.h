@@ -246,6 +246,34 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tape, const float *adjsr
 /* Release a tape (synchronizes the device); null is ignored. */
 void fwime_tape_free(fwime_tape_t *tape);
 
+/* Linear spline operator S of Section 2: the model lives on a spline grid of
+ * node coordinates zn[nzn] (depth) and xn[nxn] (lateral), in the units of dz
+ * and dx, and S maps node values onto the finite-difference grid by linear
+ * interpolation along z and along x (the tensor product of the two 1D hat
+ * interpolations; grids refined by halving end on the finite-difference grid,
+ * where S is the identity).  Fine point (ix, iz) sits at (ix dx, iz dz).
+ * zn, xn: HOST double, strictly increasing, at least two nodes each, covering
+ * [0, (nz-1) dz] and [0, (nx-1) dx] (to 1e-9 of the node span); read during
+ * the call only.  mc: DEVICE [nxn][nzn]; out: DEVICE [nx][nz], z fastest.
+ * The call synchronizes `stream` once (node upload); the interpolation tables
+ * (about 12 bytes per fine point and node) live in the context's arena.
+ * Argument errors (FWIME_EINVAL) are reported before anything is written;
+ * non-finite node values propagate. */
+int fwime_spline_apply(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx,
+                       int32_t nzn, const double *zn, int32_t nxn, const double *xn,
+                       const float *mc, float *out, void *stream);
+
+/* Adjoint S* of fwime_spline_apply (Section 2: the gradient with respect to
+ * the node values is S* applied to the model-grid gradient, eq.
+ * fwime.gradient.split): f: DEVICE [nx][nz] onto mc_out: DEVICE [nxn][nzn].
+ * Each node gathers the fine points of its two neighbouring cells with their
+ * weights in a fixed order, so results do not depend on scheduling.  Same
+ * node arguments, synchronization and errors as fwime_spline_apply; the
+ * arena also holds an [nx][nzn] FP32 intermediate. */
+int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx,
+                         int32_t nzn, const double *zn, int32_t nxn, const double *xn,
+                         const float *f, float *mc_out, void *stream);
+
 /* Static description of a return code. */
 const char *fwime_strerror(int code);
 

@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -90,6 +90,10 @@ def load() -> ctypes.CDLL:
     lib.fwime_vp_solve_tau.restype = I
     lib.fwime_vp_solve_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_gradient.restype = I
+    for name in ("fwime_spline_apply", "fwime_spline_adjoint"):
+        fn = getattr(lib, name)
+        fn.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, D, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P]
+        fn.restype = I
     lib.fwime_model_batch.argtypes = [P, ctypes.c_int32, P, P]
     lib.fwime_model_batch.restype = I
     lib.fwime_ctx_info.argtypes = [P, P]
@@ -376,6 +380,34 @@ class Context:
         out = torch.empty((ntau, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
         phi = self.fwime_vp_solve_tau(grid, vel, geom, ntau, lag, dobs, eps, dso, niter, out)
         return out, phi
+
+    def _spline_call(self, fn, nz, nx, dz, dx, zn, xn, src, src_shape, dst, dst_shape):
+        zn = np.ascontiguousarray(zn, dtype=np.float64)
+        xn = np.ascontiguousarray(xn, dtype=np.float64)
+        if zn.ndim != 1 or xn.ndim != 1:
+            raise ValueError("node coordinates must be 1D")
+        self._check(fn(self._h, int(nz), int(nx), float(dz), float(dx), zn.size, zn.ctypes.data, xn.size,
+                       xn.ctypes.data, _dptr(src, src_shape), _dptr(dst, dst_shape), _stream(src.device)))
+
+    def fwime_spline_apply(self, nz: int, nx: int, dz: float, dx: float, zn, xn, mc, out):
+        self._spline_call(self._lib.fwime_spline_apply, nz, nx, dz, dx, zn, xn,
+                          mc, (len(xn), len(zn)), out, (nx, nz))
+
+    def fwime_spline_adjoint(self, nz: int, nx: int, dz: float, dx: float, zn, xn, f, mc_out):
+        self._spline_call(self._lib.fwime_spline_adjoint, nz, nx, dz, dx, zn, xn,
+                          f, (nx, nz), mc_out, (len(xn), len(zn)))
+
+    def spline_apply(self, nz: int, nx: int, dz: float, dx: float, zn, xn, mc):
+        """S m: node values [len(xn)][len(zn)] onto the model grid [nx][nz]."""
+        out = torch.empty((nx, nz), device=mc.device, dtype=torch.float32)
+        self.fwime_spline_apply(nz, nx, dz, dx, zn, xn, mc, out)
+        return out
+
+    def spline_adjoint(self, nz: int, nx: int, dz: float, dx: float, zn, xn, f):
+        """S* f: a model-grid field [nx][nz] onto the nodes [len(xn)][len(zn)]."""
+        out = torch.empty((len(xn), len(zn)), device=f.device, dtype=torch.float32)
+        self.fwime_spline_adjoint(nz, nx, dz, dx, zn, xn, f, out)
+        return out
 
     def vp_solve(self, grid: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
         """p~ after niter CG iterations of the variable-projection step, and the objective history."""

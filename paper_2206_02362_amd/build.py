@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwime.so")
-SOURCES = ["kernels_step.hip", "kernels_step2.hip", "kernels_ext.hip", "kernels_vec.hip", "runtime.hip"]
+SOURCES = ["kernels_step.hip", "kernels_step2.hip", "kernels_ext.hip", "kernels_vec.hip", "kernels_spline.hip", "runtime.hip"]
 
 # Packed FP32 instructions are disabled on purpose: plain scalar FP32 only.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

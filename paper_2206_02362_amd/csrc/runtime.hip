@@ -2224,3 +2224,102 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Linear spline operator S and its adjoint (Section 2's spline grid)
+// ---------------------------------------------------------------------------
+namespace fw {
+hipError_t launch_spline_tables(const double *nodes, int nn, int nf, double h, int *cell, float *wt, int *start,
+                                hipStream_t st);
+hipError_t launch_spline_apply(const float *mc, int nzn, const int *cz, const float *tz, const int *cx,
+                               const float *tx, int nz, int nx, float *out, hipStream_t st);
+hipError_t launch_spline_adjoint(const float *f, int nz, int nx, const float *tz, const int *sz, int nzn,
+                                 const float *tx, const int *sx, int nxn, float *tmp, float *out, hipStream_t st);
+}  // namespace fw
+
+namespace {
+
+struct SplineAxes {
+  double *zn = nullptr, *xn = nullptr;
+  int *cz = nullptr, *cx = nullptr, *sz = nullptr, *sx = nullptr;
+  float *tz = nullptr, *tx = nullptr;
+};
+
+int check_spline_axis(fwime_ctx_t *ctx, const double *n, int32_t nn, int32_t nf, double h, const char *name) {
+  const std::string nm(name);
+  if (nn < 2) return set_err(ctx, FWIME_EINVAL, nm + ": at least two spline nodes are needed");
+  if (nf < 1) return set_err(ctx, FWIME_EINVAL, nm + ": the grid needs at least one point");
+  if (!(h > 0.0) || !std::isfinite(h)) return set_err(ctx, FWIME_EINVAL, nm + ": grid spacing must be positive");
+  if (!n) return set_err(ctx, FWIME_EINVAL, nm + " node coordinates are null");
+  for (int j = 0; j < nn; ++j)
+    if (!std::isfinite(n[j])) return set_err(ctx, FWIME_EINVAL, nm + " node coordinates must be finite");
+  for (int j = 1; j < nn; ++j)
+    if (!(n[j] > n[j - 1])) return set_err(ctx, FWIME_EINVAL, nm + " node coordinates must be strictly increasing");
+  const double tol = 1e-9 * std::max(1.0, std::fabs(n[nn - 1] - n[0]));
+  if (n[0] > tol || (nf - 1) * h > n[nn - 1] + tol)
+    return set_err(ctx, FWIME_EINVAL, nm + " nodes must cover every grid point");
+  return FWIME_OK;
+}
+
+// validates, carves the tables (plus `extra` floats) from the arena, uploads
+// the node coordinates and builds the per-axis tables on `st`
+int spline_setup(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx, int32_t nzn, const double *zn,
+                 int32_t nxn, const double *xn, const void *in, void *out, long extra, float **extra_ptr,
+                 SplineAxes &a, hipStream_t st) {
+  int rc;
+  if ((rc = check_spline_axis(ctx, zn, nzn, nz, dz, "z")) || (rc = check_spline_axis(ctx, xn, nxn, nx, dx, "x")))
+    return rc;
+  if (!in || !out) return set_err(ctx, FWIME_EINVAL, "input or output is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(st));      // earlier work on the stream may still use the arena
+  Carve cv;
+  cv.add(&a.zn, nzn);
+  cv.add(&a.xn, nxn);
+  cv.add(&a.cz, nz);
+  cv.add(&a.cx, nx);
+  cv.add(&a.tz, nz);
+  cv.add(&a.tx, nx);
+  cv.add(&a.sz, (long)nzn + 1);
+  cv.add(&a.sx, (long)nxn + 1);
+  if (extra > 0) cv.add(extra_ptr, extra);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  // pageable sources are copied synchronously: nothing of the caller's is read later
+  HIPCHK(hipMemcpyAsync(a.zn, zn, nzn * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(a.xn, xn, nxn * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(launch_spline_tables(a.zn, nzn, nz, dz, a.cz, a.tz, a.sz, st));
+  HIPCHK(launch_spline_tables(a.xn, nxn, nx, dx, a.cx, a.tx, a.sx, st));
+  return FWIME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwime_spline_apply(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx, int32_t nzn, const double *zn,
+                       int32_t nxn, const double *xn, const float *mc, float *out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  SplineAxes a;
+  int rc = spline_setup(ctx, nz, nx, dz, dx, nzn, zn, nxn, xn, mc, out, 0, nullptr, a, st);
+  if (rc) return rc;
+  HIPCHK(launch_spline_apply(mc, nzn, a.cz, a.tz, a.cx, a.tx, nz, nx, out, st));
+  return FWIME_OK;
+}
+
+int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx, int32_t nzn,
+                         const double *zn, int32_t nxn, const double *xn, const float *f, float *mc_out,
+                         void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  SplineAxes a;
+  float *tmp = nullptr;
+  int rc = spline_setup(ctx, nz, nx, dz, dx, nzn, zn, nxn, xn, f, mc_out, (long)nx * nzn, &tmp, a, st);
+  if (rc) return rc;
+  HIPCHK(launch_spline_adjoint(f, nz, nx, a.tz, a.sz, nzn, a.tx, a.sx, nxn, tmp, mc_out, st));
+  return FWIME_OK;
+}
+
+}  // extern "C"
