@@ -226,6 +226,8 @@ def main():
                     help="CG iterations of the variable-projection step to time (0: skip)")
     ap.add_argument("--tau-shots", type=int, default=8,
                     help="shots of the time-lag extended Born pair to time (0: skip)")
+    ap.add_argument("--spline-reps", type=int, default=50,
+                    help="calls of the spline operator S and its adjoint to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -406,6 +408,37 @@ def main():
         log(f"time lag: forward {t_f:.2f} s (first call {t_cold:.2f} s), adjoint {t_a:.2f} s")
         del dtau, img, ptau
 
+    spline = None
+    if args.spline_reps > 0:
+        # S and S* on the model grid, nodes every 10 cells plus a refined band
+        # of 5-cell spacing around an interface at a third of the depth
+        zn = np.unique(np.concatenate([np.arange(0, w.nz - 1, 10), [w.nz - 1],
+                                       np.arange(w.nz // 3 - 20, w.nz // 3 + 20, 5)]) * w.dz)
+        xn = np.unique(np.concatenate([np.arange(0, w.nx - 1, 10), [w.nx - 1]]) * w.dx)
+        mc = torch.tensor(synth.gaussian_perturbation(len(zn), len(xn), w.dx, 80, 30.0), dtype=torch.float32,
+                          device=dev)
+        fine = torch.empty((w.nx, w.nz), dtype=torch.float32, device=dev)
+        back = torch.empty((len(xn), len(zn)), dtype=torch.float32, device=dev)
+        times = {}
+        for name, call in (("apply", lambda: ctx.fwime_spline_apply(w.nz, w.nx, w.dz, w.dx, zn, xn, mc, fine)),
+                           ("adjoint", lambda: ctx.fwime_spline_adjoint(w.nz, w.nx, w.dz, w.dx, zn, xn, fine,
+                                                                        back))):
+            call()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.spline_reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) * 1e3 / args.spline_reps
+        spline = {"workload": f"{w.nz}x{w.nx} model grid, {len(zn)}x{len(xn)} spline nodes",
+                  "apply_us_per_call": times["apply"], "adjoint_us_per_call": times["adjoint"],
+                  "note": "whole calls (node upload with one stream synchronization, axis tables, "
+                          "interpolation); per-kernel times in the rocprofv3 summary"}
+        log(f"spline: apply {times['apply']:.1f} us, adjoint {times['adjoint']:.1f} us per call")
+        del fine, back, mc
+
     serving = None
     if args.serve_requests > 0:
         # give the device memory of the step back to the server's budget
@@ -442,6 +475,7 @@ def main():
         "batched_vs_plain": batch,
         "vp_step": vp,
         "time_lag": tau,
+        "spline": spline,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
