@@ -274,6 +274,20 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
                          int32_t nzn, const double *zn, int32_t nxn, const double *xn,
                          const float *f, float *mc_out, void *stream);
 
+/* L-BFGS search direction (Section 3 minimizes the FWIME objective over the
+ * spline nodes with L-BFGS): d_out = -H g, where H is the limited-memory
+ * inverse-Hessian approximation built from npairs pairs (s_i, y_i), oldest
+ * first, with initial matrix (s.y / y.y of the newest pair) I, or I when
+ * npairs = 0; the two-loop recursion, never forming H.  Inner products in FP64
+ * with a fixed reduction order, vector updates in FP32.
+ * s, y: DEVICE [npairs][n]; g, d_out: DEVICE [n] (d_out may be g, must not
+ * overlap s or y).  0 <= npairs <= 256, n >= 1.  Every pair must have
+ * s_i.y_i > 0 (callers drop the others); otherwise FWIME_EINVAL before
+ * anything is written.  The call synchronizes `stream` once per inner product
+ * (2 npairs + 1 of them). */
+int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const float *s, const float *y,
+                          const float *g, float *d_out, void *stream);
+
 /* Static description of a return code. */
 const char *fwime_strerror(int code);
 

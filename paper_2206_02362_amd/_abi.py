@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_lbfgs_direction", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -90,6 +90,8 @@ def load() -> ctypes.CDLL:
     lib.fwime_vp_solve_tau.restype = I
     lib.fwime_vp_solve_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_gradient.restype = I
+    lib.fwime_lbfgs_direction.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
+    lib.fwime_lbfgs_direction.restype = I
     for name in ("fwime_spline_apply", "fwime_spline_adjoint"):
         fn = getattr(lib, name)
         fn.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, D, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P]
@@ -408,6 +410,20 @@ class Context:
         out = torch.empty((len(xn), len(zn)), device=f.device, dtype=torch.float32)
         self.fwime_spline_adjoint(nz, nx, dz, dx, zn, xn, f, out)
         return out
+
+    def fwime_lbfgs_direction(self, s, y, g, d_out):
+        n = int(g.numel())
+        k = int(s.shape[0]) if s is not None else 0
+        sp = _dptr(s, (k, n)) if k else None
+        yp = _dptr(y, (k, n)) if k else None
+        self._check(self._lib.fwime_lbfgs_direction(self._h, n, k, sp, yp, _dptr(g, (n,)), _dptr(d_out, (n,)),
+                                                    _stream(g.device)))
+
+    def lbfgs_direction(self, s, y, g):
+        """-H g for the L-BFGS pairs s, y ([k][n], oldest first) and gradient g ([n])."""
+        d = torch.empty_like(g)
+        self.fwime_lbfgs_direction(s, y, g, d)
+        return d
 
     def vp_solve(self, grid: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
         """p~ after niter CG iterations of the variable-projection step, and the objective history."""

@@ -102,4 +102,15 @@ hipError_t launch_add_diag(float *q, const float *s, const float *e2d2, long pla
   return hipGetLastError();
 }
 
+// y = a x + b y (x may alias y)
+__global__ void k_axpby(const float *x, float a, float *y, float b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = fmaf(a, x[i], b * y[i]);
+}
+
+hipError_t launch_axpby(const float *x, float a, float *y, float b, long n, hipStream_t st) {
+  k_axpby<<<stream_blocks(n), 256, 0, st>>>(x, a, y, b, n);
+  return hipGetLastError();
+}
+
 }  // namespace fw

@@ -60,6 +60,7 @@ static void release_graph(fwime_ctx_t *ctx) {
 
 namespace {
 
+constexpr int kLbfgsMaxPairs = 256;    // L-BFGS pairs accepted by fwime_lbfgs_direction
 constexpr int kGxPad = 64;              // zero taper entries past NX read by the last x-tile
 constexpr int kGraphMaxTiles = 16384;   // batches above this many tiles launch directly
 constexpr double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -2319,6 +2320,76 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
   int rc = spline_setup(ctx, nz, nx, dz, dx, nzn, zn, nxn, xn, f, mc_out, (long)nx * nzn, &tmp, a, st);
   if (rc) return rc;
   HIPCHK(launch_spline_adjoint(f, nz, nx, a.tz, a.sz, nzn, a.tx, a.sx, nxn, tmp, mc_out, st));
+  return FWIME_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// L-BFGS search direction (Section 3: the outer minimization uses L-BFGS)
+// ---------------------------------------------------------------------------
+namespace fw {
+hipError_t launch_axpby(const float *x, float a, float *y, float b, long n, hipStream_t st);
+}  // namespace fw
+
+extern "C" {
+
+int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const float *s, const float *y,
+                          const float *g, float *d_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 1) return set_err(ctx, FWIME_EINVAL, "n must be >= 1");
+  if (npairs < 0 || npairs > kLbfgsMaxPairs)
+    return set_err(ctx, FWIME_EINVAL, "npairs must be in [0, " + std::to_string(kLbfgsMaxPairs) + "]");
+  if (!g || !d_out || (npairs > 0 && (!s || !y))) return set_err(ctx, FWIME_EINVAL, "null vector");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(st));      // earlier work on the stream may still use the arena
+  double *part = nullptr, *res = nullptr;
+  Carve cv;
+  cv.add(&part, dot_partials());
+  cv.add(&res, 1);
+  int rc;
+  if ((rc = arena_get(ctx, cv))) return rc;
+  auto dot = [&](const float *a, const float *b, double &out) -> int {
+    HIPCHK(launch_dot(a, b, (long)n, part, res, st));
+    HIPCHK(hipMemcpyAsync(ctx->host_red, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out = ctx->host_red[0];
+    return FWIME_OK;
+  };
+  auto S = [&](int i) { return s + (long)i * n; };
+  auto Y = [&](int i) { return y + (long)i * n; };
+  // curvature of every pair first, so that a rejected call writes nothing
+  std::vector<double> rho(npairs), alpha(npairs);
+  double sy = 0.0, yy = 1.0;
+  for (int i = 0; i < npairs; ++i) {
+    if ((rc = dot(S(i), Y(i), sy))) return rc;
+    if (!(sy > 0.0) || !std::isfinite(sy))
+      return set_err(ctx, FWIME_EINVAL, "pair " + std::to_string(i) + " has s.y <= 0 or non-finite");
+    rho[i] = 1.0 / sy;
+  }
+  double gamma = 1.0;
+  if (npairs > 0) {
+    if ((rc = dot(Y(npairs - 1), Y(npairs - 1), yy))) return rc;
+    gamma = (1.0 / rho[npairs - 1]) / yy;
+  }
+  // q = g, then q -= alpha_i y_i from the newest pair to the oldest
+  if (d_out != g) HIPCHK(hipMemcpyAsync(d_out, g, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  for (int i = npairs - 1; i >= 0; --i) {
+    double sq;
+    if ((rc = dot(S(i), d_out, sq))) return rc;
+    alpha[i] = rho[i] * sq;
+    HIPCHK(launch_axpby(Y(i), (float)-alpha[i], d_out, 1.0f, (long)n, st));
+  }
+  // r = gamma q, then r += (alpha_i - beta_i) s_i from the oldest pair to the newest
+  HIPCHK(launch_axpby(d_out, 0.0f, d_out, (float)gamma, (long)n, st));
+  for (int i = 0; i < npairs; ++i) {
+    double yr;
+    if ((rc = dot(Y(i), d_out, yr))) return rc;
+    HIPCHK(launch_axpby(S(i), (float)(alpha[i] - rho[i] * yr), d_out, 1.0f, (long)n, st));
+  }
+  HIPCHK(launch_axpby(d_out, 0.0f, d_out, -1.0f, (long)n, st));
   return FWIME_OK;
 }
 
