@@ -21,17 +21,15 @@ uses the More-Thuente method).  Readings:
   with m indexed [x node][z node]; S* f = A_x^T f A_z.
 * L-BFGS: the standard two-loop recursion over the last `memory` pairs, the
   initial inverse Hessian scaled by s.y / y.y of the newest pair, pairs with
-  s.y <= 0 not kept; the step
-  length from scipy.optimize.line_search (MINPACK's dcsrch, the More-Thuente
-  method) with c1 = 1e-4, c2 = 0.9 and a first trial step of 1.
+  s.y <= 0 not kept; the step length from scipy's scalar_search_wolfe1
+  (MINPACK's dcsrch, the More-Thuente method) on phi(a) = f(x + a d), with
+  c1 = 1e-4, c2 = 0.9, xtol = 1e-14, steps in [0, 1e10] and a first trial
+  step of 1.
 """
 from __future__ import annotations
 
-import warnings
-
 import numpy as np
-from scipy.optimize import line_search
-from scipy.optimize._linesearch import LineSearchWarning
+from scipy.optimize._linesearch import scalar_search_wolfe1
 
 
 def hat_matrix(nodes: np.ndarray, pts: np.ndarray) -> np.ndarray:
@@ -91,8 +89,9 @@ def two_loop(g: np.ndarray, S, Y) -> np.ndarray:
     return r
 
 
-def lbfgs(fun_grad, x0: np.ndarray, memory: int = 5, maxiter: int = 100, gtol: float = 1e-8):
+def lbfgs(fun_grad, x0: np.ndarray, memory: int = 5, maxiter: int = 100, gtol: float = 1e-8, trace=None):
     """Minimize fun_grad(x) -> (f, g) by L-BFGS; returns (x, [f per iterate]).
+    A list passed as `trace` receives (x, f, g) of every iterate.
 
     Stops when ||g|| <= gtol ||g_0||, after maxiter iterations, or when the line
     search finds no step (the paper then refines the spline grid)."""
@@ -110,16 +109,16 @@ def lbfgs(fun_grad, x0: np.ndarray, memory: int = 5, maxiter: int = 100, gtol: f
     f, g = fg(x)
     g0 = np.linalg.norm(g)
     hist = [f]
+    if trace is not None:
+        trace.append((x.copy(), f, g.copy()))
     S, Y = [], []
     for _ in range(maxiter):
         if np.linalg.norm(g) <= gtol * g0:
             break
         d = -two_loop(g, S, Y)
-        with warnings.catch_warnings():
-            # no step satisfying both conditions is reported as None below
-            warnings.simplefilter("ignore", LineSearchWarning)
-            step = line_search(lambda z: fg(z)[0], lambda z: fg(z)[1], x, d, g, f,
-                               c1=1e-4, c2=0.9, amax=1e10)[0]
+        step = scalar_search_wolfe1(lambda a: fg(x + a * d)[0], lambda a: float(fg(x + a * d)[1] @ d),
+                                    phi0=f, derphi0=float(g @ d), c1=1e-4, c2=0.9,
+                                    amax=1e10, amin=0.0, xtol=1e-14)[0]
         if step is None:
             break
         x_new = x + step * d
@@ -133,6 +132,8 @@ def lbfgs(fun_grad, x0: np.ndarray, memory: int = 5, maxiter: int = 100, gtol: f
                 Y.pop(0)
         x, f, g = x_new, f_new, g_new
         hist.append(f)
+        if trace is not None:
+            trace.append((x.copy(), f, g.copy()))
     return x, hist
 
 

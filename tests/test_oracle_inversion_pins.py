@@ -13,7 +13,8 @@ Each pin checks the oracle against something other than itself:
   applied pair by pair (the textbook dense formula), and satisfies the
   newest secant equation H y = s;
 * L-BFGS reaches the known minimizers of a convex quadratic and of the
-  Rosenbrock function, with a non-increasing objective;
+  Rosenbrock function, with a non-increasing objective, and every accepted
+  step meets the strong Wolfe conditions;
 * the spline-grid objective's gradient S* grad f(S m) matches central
   differences, on a quadratic and on the FWIME objective.
 """
@@ -142,6 +143,23 @@ def test_lbfgs_rosenbrock():
     x, hist = oracle.lbfgs(fg, np.array([-1.2, 1.0]), maxiter=200)
     assert np.linalg.norm(x - 1.0) < 1e-6
     assert all(b2 <= a2 for a2, b2 in zip(hist, hist[1:]))
+
+
+def test_lbfgs_steps_satisfy_strong_wolfe():
+    # every accepted step s = x_{k+1} - x_k meets both conditions of the
+    # strong Wolfe rule the More-Thuente search is asked for (c1 = 1e-4,
+    # c2 = 0.9): sufficient decrease and a small enough directional derivative
+    def fg(x):                                       # a smooth non-quadratic convex function
+        e = np.exp(0.3 * x)
+        return float(np.sum(e - 0.3 * x) + 0.5 * np.sum((x[1:] - x[:-1]) ** 2)), \
+            0.3 * e - 0.3 + np.concatenate([[0.0], x[1:] - x[:-1]]) - np.concatenate([x[1:] - x[:-1], [0.0]])
+    tr = []
+    oracle.lbfgs(fg, np.linspace(-4.0, 6.0, 30), maxiter=40, trace=tr)
+    assert len(tr) > 5
+    for (x0, f0, g0), (x1, f1, g1) in zip(tr, tr[1:]):
+        s = x1 - x0
+        assert f1 <= f0 + 1e-4 * float(g0 @ s) + 1e-15 * abs(f0)
+        assert abs(float(g1 @ s)) <= 0.9 * abs(float(g0 @ s)) * (1 + 1e-12)
 
 
 def test_spline_objective_gradient_quadratic(grid):
