@@ -288,6 +288,32 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
 int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const float *s, const float *y,
                           const float *g, float *d_out, void *stream);
 
+/* Objective callback of fwime_lbfgs_minimize: evaluate f at the DEVICE
+ * vector x[n], write the gradient to the DEVICE vector g[n] and f to *f;
+ * return 0, or nonzero to stop the minimization.  Device work must be queued
+ * on the minimization's stream or be complete when the callback returns. */
+typedef int (*fwime_objective_fn)(void *user, const float *x, float *g, double *f);
+
+/* L-BFGS minimization (Section 3: the FWIME objective is minimized over the
+ * spline nodes with L-BFGS and a More-Thuente line search).  From x, each
+ * iteration takes d = -H g from the last `memory` pairs (as
+ * fwime_lbfgs_direction), searches a step along d for the strong Wolfe
+ * conditions (ftol 1e-4, gtol 0.9, first trial step 1, at most 100 trials),
+ * and keeps the new pair if s.y > 1e-12 |s| |y|.  It stops after maxiter
+ * iterations, when |g| <= gtol |g_0|, when d is not a descent direction, or
+ * when the line search ends without an acceptable step.
+ * x: DEVICE [n], the start on entry and the last accepted iterate on return.
+ * work: DEVICE float [4096 + (2 memory + 6) n], 8-byte aligned, caller-owned
+ * (nothing is allocated, so the callback may use the same context freely).
+ * f_hist: HOST double [maxiter + 1], f at x_0 and after each iteration, the
+ * last value repeated past the stop; iters: HOST, iterations taken.
+ * 1 <= memory <= 256.  A callback error stops with FWIME_EINVAL and a
+ * non-finite objective with FWIME_ENONFINITE; x then holds the last accepted
+ * iterate.  The call synchronizes `stream` once per inner product. */
+int fwime_lbfgs_minimize(fwime_ctx_t *ctx, int64_t n, int32_t memory, int32_t maxiter, double gtol,
+                         fwime_objective_fn fg, void *user, float *x, float *work, double *f_hist,
+                         int32_t *iters, void *stream);
+
 /* Static description of a return code. */
 const char *fwime_strerror(int code);
 

@@ -26,8 +26,14 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_lbfgs_direction", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
+
+
+# int (*)(void *user, const float *x, float *g, double *f)
+OBJECTIVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_double))
+LBFGS_WORK_HEAD = 4096
 
 
 class FwimeError(RuntimeError):
@@ -90,6 +96,9 @@ def load() -> ctypes.CDLL:
     lib.fwime_vp_solve_tau.restype = I
     lib.fwime_vp_solve_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_gradient.restype = I
+    lib.fwime_lbfgs_minimize.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, D, OBJECTIVE_FN, P,
+                                         P, P, P, P, P]
+    lib.fwime_lbfgs_minimize.restype = I
     lib.fwime_lbfgs_direction.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
     lib.fwime_lbfgs_direction.restype = I
     for name in ("fwime_spline_apply", "fwime_spline_adjoint"):
@@ -424,6 +433,44 @@ class Context:
         d = torch.empty_like(g)
         self.fwime_lbfgs_direction(s, y, g, d)
         return d
+
+    def lbfgs_minimize(self, fun_grad, x0, memory: int = 5, maxiter: int = 20, gtol: float = 1e-8):
+        """L-BFGS from x0 (a float32 device tensor) on fun_grad(x) -> (f, g), with x and g
+        device tensors of x0's size; returns (x, f history, iterations)."""
+        n = int(x0.numel())
+        x = x0.detach().reshape(-1).clone()
+        work = torch.empty(LBFGS_WORK_HEAD + (2 * int(memory) + 6) * n, device=x.device, dtype=torch.float32)
+        base = work.data_ptr()
+        errors = []
+
+        def view(ptr):
+            if ptr == x.data_ptr():
+                return x
+            off = (ptr - base) // 4
+            if ptr < base or off + n > work.numel():
+                raise RuntimeError("callback pointer outside the workspace")
+            return work[off:off + n]
+
+        def callback(user, xp, gp, fp):
+            try:
+                f, g = fun_grad(view(xp).view_as(x0))
+                view(gp).copy_(g.reshape(-1))
+                fp[0] = float(f)
+                return 0
+            except BaseException as e:          # reported after the call returns
+                errors.append(e)
+                return 1
+
+        cfn = OBJECTIVE_FN(callback)
+        hist = np.zeros(int(maxiter) + 1, dtype=np.float64)
+        iters = ctypes.c_int32(0)
+        rc = self._lib.fwime_lbfgs_minimize(self._h, n, int(memory), int(maxiter), float(gtol), cfn, None,
+                                            _dptr(x, (n,)), _dptr(work, None), hist.ctypes.data,
+                                            ctypes.byref(iters), _stream(x.device))
+        if errors:
+            raise errors[0]
+        self._check(rc)
+        return x.view_as(x0), hist[:iters.value + 1], iters.value
 
     def vp_solve(self, grid: Grid, vel, geom: Geometry, dobs, nh: int, eps: float, dso, niter: int):
         """p~ after niter CG iterations of the variable-projection step, and the objective history."""

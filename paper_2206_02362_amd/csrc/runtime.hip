@@ -18,6 +18,7 @@
 //     segment, while the adjoint fields live in rings of K + 2 time slots.
 #include "../../include/fwime.h"
 #include "internal.h"
+#include "line_search.h"
 
 #include <algorithm>
 #include <cmath>
@@ -2332,6 +2333,56 @@ namespace fw {
 hipError_t launch_axpby(const float *x, float a, float *y, float b, long n, hipStream_t st);
 }  // namespace fw
 
+namespace {
+
+constexpr int kLbfgsMaxEvals = 100;      // trial steps per line search
+constexpr long kLbfgsWorkHead = 4096;    // floats of the workspace before the vectors (dot partials)
+
+// d = H g by the two-loop recursion over the pairs S[i], Y[i] (oldest first),
+// H_0 = (s.y / y.y of the newest pair) I; FP64 inner products, FP32 updates.
+// Every pair's curvature is checked before d is written.
+int two_loop(fwime_ctx_t *ctx, long n, const std::vector<const float *> &S, const std::vector<const float *> &Y,
+             const float *g, float *d, double *part, double *res, hipStream_t st) {
+  const int k = (int)S.size();
+  int rc;
+  auto dot = [&](const float *a, const float *b, double &out) -> int {
+    HIPCHK(launch_dot(a, b, n, part, res, st));
+    HIPCHK(hipMemcpyAsync(ctx->host_red, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out = ctx->host_red[0];
+    return FWIME_OK;
+  };
+  std::vector<double> rho(k), alpha(k);
+  double sy = 0.0, yy = 1.0;
+  for (int i = 0; i < k; ++i) {
+    if ((rc = dot(S[i], Y[i], sy))) return rc;
+    if (!(sy > 0.0) || !std::isfinite(sy))
+      return set_err(ctx, FWIME_EINVAL, "pair " + std::to_string(i) + " has s.y <= 0 or non-finite");
+    rho[i] = 1.0 / sy;
+  }
+  double gamma = 1.0;
+  if (k > 0) {
+    if ((rc = dot(Y[k - 1], Y[k - 1], yy))) return rc;
+    gamma = (1.0 / rho[k - 1]) / yy;
+  }
+  if (d != g) HIPCHK(hipMemcpyAsync(d, g, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  for (int i = k - 1; i >= 0; --i) {
+    double sq;
+    if ((rc = dot(S[i], d, sq))) return rc;
+    alpha[i] = rho[i] * sq;
+    HIPCHK(launch_axpby(Y[i], (float)-alpha[i], d, 1.0f, n, st));
+  }
+  HIPCHK(launch_axpby(d, 0.0f, d, (float)gamma, n, st));
+  for (int i = 0; i < k; ++i) {
+    double yr;
+    if ((rc = dot(Y[i], d, yr))) return rc;
+    HIPCHK(launch_axpby(S[i], (float)(alpha[i] - rho[i] * yr), d, 1.0f, n, st));
+  }
+  return FWIME_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const float *s, const float *y,
@@ -2351,6 +2402,40 @@ int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const flo
   cv.add(&res, 1);
   int rc;
   if ((rc = arena_get(ctx, cv))) return rc;
+  std::vector<const float *> S(npairs), Y(npairs);
+  for (int i = 0; i < npairs; ++i) {
+    S[i] = s + (long)i * n;
+    Y[i] = y + (long)i * n;
+  }
+  if ((rc = two_loop(ctx, (long)n, S, Y, g, d_out, part, res, st))) return rc;
+  HIPCHK(launch_axpby(d_out, 0.0f, d_out, -1.0f, (long)n, st));
+  return FWIME_OK;
+}
+
+int fwime_lbfgs_minimize(fwime_ctx_t *ctx, int64_t n, int32_t memory, int32_t maxiter, double gtol,
+                         fwime_objective_fn fg, void *user, float *x, float *work, double *f_hist,
+                         int32_t *iters, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 1) return set_err(ctx, FWIME_EINVAL, "n must be >= 1");
+  if (memory < 1 || memory > kLbfgsMaxPairs)
+    return set_err(ctx, FWIME_EINVAL, "memory must be in [1, " + std::to_string(kLbfgsMaxPairs) + "]");
+  if (maxiter < 0) return set_err(ctx, FWIME_EINVAL, "maxiter must be >= 0");
+  if (!(gtol >= 0.0) || !std::isfinite(gtol)) return set_err(ctx, FWIME_EINVAL, "gtol must be finite and >= 0");
+  if (!fg || !x || !work || !f_hist || !iters) return set_err(ctx, FWIME_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  // work: dot partials, then g, d, trial x, trial g and memory + 1 slots each of s and y
+  double *part = (double *)work, *res = part + dot_partials();
+  float *vec = work + kLbfgsWorkHead;
+  auto V = [&](long j) { return vec + j * (long)n; };
+  float *g = V(0), *d = V(1), *xt = V(2), *gt = V(3);
+  std::vector<float *> sslot(memory + 1), yslot(memory + 1);
+  for (int j = 0; j <= memory; ++j) {
+    sslot[j] = V(4 + j);
+    yslot[j] = V(5 + memory + j);
+  }
+  int rc;
   auto dot = [&](const float *a, const float *b, double &out) -> int {
     HIPCHK(launch_dot(a, b, (long)n, part, res, st));
     HIPCHK(hipMemcpyAsync(ctx->host_red, res, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2358,38 +2443,71 @@ int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const flo
     out = ctx->host_red[0];
     return FWIME_OK;
   };
-  auto S = [&](int i) { return s + (long)i * n; };
-  auto Y = [&](int i) { return y + (long)i * n; };
-  // curvature of every pair first, so that a rejected call writes nothing
-  std::vector<double> rho(npairs), alpha(npairs);
-  double sy = 0.0, yy = 1.0;
-  for (int i = 0; i < npairs; ++i) {
-    if ((rc = dot(S(i), Y(i), sy))) return rc;
-    if (!(sy > 0.0) || !std::isfinite(sy))
-      return set_err(ctx, FWIME_EINVAL, "pair " + std::to_string(i) + " has s.y <= 0 or non-finite");
-    rho[i] = 1.0 / sy;
+  auto eval = [&](const float *at, float *grad, double &f) -> int {
+    const int cb = fg(user, at, grad, &f);
+    if (cb != 0) return set_err(ctx, FWIME_EINVAL, "objective callback returned " + std::to_string(cb));
+    if (!std::isfinite(f)) return set_err(ctx, FWIME_ENONFINITE, "objective is not finite");
+    return FWIME_OK;
+  };
+  double f = 0.0, gg = 0.0;
+  if ((rc = eval(x, g, f)) || (rc = dot(g, g, gg))) return rc;
+  const double g0 = std::sqrt(gg);
+  f_hist[0] = f;
+  // pairs kept oldest first, as slot indices; one slot is always free
+  std::vector<int> pairs, free_slots;
+  for (int j = memory; j >= 0; --j) free_slots.push_back(j);
+  int it = 0;
+  for (; it < maxiter; ++it) {
+    if (std::sqrt(gg) <= gtol * g0) break;
+    std::vector<const float *> S, Y;
+    for (int j : pairs) {
+      S.push_back(sslot[j]);
+      Y.push_back(yslot[j]);
+    }
+    if ((rc = two_loop(ctx, (long)n, S, Y, g, d, part, res, st))) return rc;
+    HIPCHK(launch_axpby(d, 0.0f, d, -1.0f, (long)n, st));   // descent direction -H g
+    double dphi0;
+    if ((rc = dot(g, d, dphi0))) return rc;
+    if (!(dphi0 < 0.0)) break;
+    MoreThuente ls;
+    ls.stpmin = 0.0;
+    ls.stpmax = 1e10;
+    auto status = ls.start(1.0, f, dphi0);
+    double ft = 0.0;
+    for (int nfev = 0; status == MoreThuente::kEvaluate && nfev < kLbfgsMaxEvals; ++nfev) {
+      HIPCHK(hipMemcpyAsync(xt, x, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+      HIPCHK(launch_axpby(d, (float)ls.stp, xt, 1.0f, (long)n, st));
+      double dphi;
+      if ((rc = eval(xt, gt, ft)) || (rc = dot(gt, d, dphi))) return rc;
+      status = ls.next(ft, dphi);
+    }
+    if (status != MoreThuente::kConverged) break;
+    // new pair: s = x_t - x, y = g_t - g, kept if its curvature is positive
+    const int slot = free_slots.back();
+    float *sn = sslot[slot], *yn = yslot[slot];
+    HIPCHK(hipMemcpyAsync(sn, xt, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_axpby(x, -1.0f, sn, 1.0f, (long)n, st));
+    HIPCHK(hipMemcpyAsync(yn, gt, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_axpby(g, -1.0f, yn, 1.0f, (long)n, st));
+    double sy, ss, yy;
+    if ((rc = dot(sn, yn, sy)) || (rc = dot(sn, sn, ss)) || (rc = dot(yn, yn, yy))) return rc;
+    if (sy > 1e-12 * std::sqrt(ss) * std::sqrt(yy)) {
+      free_slots.pop_back();
+      pairs.push_back(slot);
+      if ((int)pairs.size() > memory) {
+        free_slots.push_back(pairs.front());
+        pairs.erase(pairs.begin());
+      }
+    }
+    HIPCHK(hipMemcpyAsync(x, xt, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(g, gt, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    f = ft;
+    if ((rc = dot(g, g, gg))) return rc;
+    f_hist[it + 1] = f;
   }
-  double gamma = 1.0;
-  if (npairs > 0) {
-    if ((rc = dot(Y(npairs - 1), Y(npairs - 1), yy))) return rc;
-    gamma = (1.0 / rho[npairs - 1]) / yy;
-  }
-  // q = g, then q -= alpha_i y_i from the newest pair to the oldest
-  if (d_out != g) HIPCHK(hipMemcpyAsync(d_out, g, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
-  for (int i = npairs - 1; i >= 0; --i) {
-    double sq;
-    if ((rc = dot(S(i), d_out, sq))) return rc;
-    alpha[i] = rho[i] * sq;
-    HIPCHK(launch_axpby(Y(i), (float)-alpha[i], d_out, 1.0f, (long)n, st));
-  }
-  // r = gamma q, then r += (alpha_i - beta_i) s_i from the oldest pair to the newest
-  HIPCHK(launch_axpby(d_out, 0.0f, d_out, (float)gamma, (long)n, st));
-  for (int i = 0; i < npairs; ++i) {
-    double yr;
-    if ((rc = dot(Y(i), d_out, yr))) return rc;
-    HIPCHK(launch_axpby(S(i), (float)(alpha[i] - rho[i] * yr), d_out, 1.0f, (long)n, st));
-  }
-  HIPCHK(launch_axpby(d_out, 0.0f, d_out, -1.0f, (long)n, st));
+  for (int j = it + 1; j <= maxiter; ++j) f_hist[j] = f;
+  *iters = it;
+  HIPCHK(hipStreamSynchronize(st));
   return FWIME_OK;
 }
 
