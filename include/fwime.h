@@ -252,7 +252,7 @@ void fwime_tape_free(fwime_tape_t *tape);
  * interpolation along z and along x (the tensor product of the two 1D hat
  * interpolations; grids refined by halving end on the finite-difference grid,
  * where S is the identity).  Fine point (ix, iz) sits at (ix dx, iz dz).
- * zn, xn: HOST double, strictly increasing, at least two nodes each, covering
+ * zn, xn: HOST double, strictly increasing, 2 to 2^24 nodes each, covering
  * [0, (nz-1) dz] and [0, (nx-1) dx] (to 1e-9 of the node span); read during
  * the call only.  mc: DEVICE [nxn][nzn]; out: DEVICE [nx][nz], z fastest.
  * The call synchronizes `stream` once (node upload); the interpolation tables
@@ -303,16 +303,17 @@ typedef int (*fwime_objective_fn)(void *user, const float *x, float *g, double *
  * iterations, when |g| <= gtol |g_0|, when d is not a descent direction, or
  * when the line search ends without an acceptable step.
  * x: DEVICE [n], the start on entry and the last accepted iterate on return.
- * work: DEVICE float [4096 + (2 memory + 6) n], 8-byte aligned, caller-owned
- * (nothing is allocated, so the callback may use the same context freely).
+ * work: DEVICE float [work_floats], at least 4096 + (2 memory + 6) n floats,
+ * 8-byte aligned, caller-owned (nothing is allocated, so the callback may use
+ * the same context freely); a smaller or misaligned buffer is FWIME_EINVAL.
  * f_hist: HOST double [maxiter + 1], f at x_0 and after each iteration, the
  * last value repeated past the stop; iters: HOST, iterations taken.
  * 1 <= memory <= 256.  A callback error stops with FWIME_EINVAL and a
  * non-finite objective with FWIME_ENONFINITE; x then holds the last accepted
  * iterate.  The call synchronizes `stream` once per inner product. */
 int fwime_lbfgs_minimize(fwime_ctx_t *ctx, int64_t n, int32_t memory, int32_t maxiter, double gtol,
-                         fwime_objective_fn fg, void *user, float *x, float *work, double *f_hist,
-                         int32_t *iters, void *stream);
+                         fwime_objective_fn fg, void *user, float *x, float *work, int64_t work_floats,
+                         double *f_hist, int32_t *iters, void *stream);
 
 /* Static description of a return code. */
 const char *fwime_strerror(int code);

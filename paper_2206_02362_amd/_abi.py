@@ -97,7 +97,7 @@ def load() -> ctypes.CDLL:
     lib.fwime_vp_solve_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_gradient.restype = I
     lib.fwime_lbfgs_minimize.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, D, OBJECTIVE_FN, P,
-                                         P, P, P, P, P]
+                                         P, P, ctypes.c_int64, P, P, P]
     lib.fwime_lbfgs_minimize.restype = I
     lib.fwime_lbfgs_direction.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
     lib.fwime_lbfgs_direction.restype = I
@@ -465,7 +465,7 @@ class Context:
         hist = np.zeros(int(maxiter) + 1, dtype=np.float64)
         iters = ctypes.c_int32(0)
         rc = self._lib.fwime_lbfgs_minimize(self._h, n, int(memory), int(maxiter), float(gtol), cfn, None,
-                                            _dptr(x, (n,)), _dptr(work, None), hist.ctypes.data,
+                                            _dptr(x, (n,)), _dptr(work, None), work.numel(), hist.ctypes.data,
                                             ctypes.byref(iters), _stream(x.device))
         if errors:
             raise errors[0]

@@ -21,6 +21,7 @@
 #include "line_search.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -61,6 +62,7 @@ static void release_graph(fwime_ctx_t *ctx) {
 
 namespace {
 
+constexpr int kSplineMaxNodes = 1 << 24;  // spline nodes per axis
 constexpr int kLbfgsMaxPairs = 256;    // L-BFGS pairs accepted by fwime_lbfgs_direction
 constexpr int kGxPad = 64;              // zero taper entries past NX read by the last x-tile
 constexpr int kGraphMaxTiles = 16384;   // batches above this many tiles launch directly
@@ -2250,6 +2252,7 @@ struct SplineAxes {
 int check_spline_axis(fwime_ctx_t *ctx, const double *n, int32_t nn, int32_t nf, double h, const char *name) {
   const std::string nm(name);
   if (nn < 2) return set_err(ctx, FWIME_EINVAL, nm + ": at least two spline nodes are needed");
+  if (nn > kSplineMaxNodes) return set_err(ctx, FWIME_EINVAL, nm + ": more than 2^24 spline nodes");
   if (nf < 1) return set_err(ctx, FWIME_EINVAL, nm + ": the grid needs at least one point");
   if (!(h > 0.0) || !std::isfinite(h)) return set_err(ctx, FWIME_EINVAL, nm + ": grid spacing must be positive");
   if (!n) return set_err(ctx, FWIME_EINVAL, nm + " node coordinates are null");
@@ -2413,8 +2416,8 @@ int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const flo
 }
 
 int fwime_lbfgs_minimize(fwime_ctx_t *ctx, int64_t n, int32_t memory, int32_t maxiter, double gtol,
-                         fwime_objective_fn fg, void *user, float *x, float *work, double *f_hist,
-                         int32_t *iters, void *stream) {
+                         fwime_objective_fn fg, void *user, float *x, float *work, int64_t work_floats,
+                         double *f_hist, int32_t *iters, void *stream) {
   if (!ctx) return FWIME_EINVAL;
   ctx->err.clear();
   hipStream_t st = (hipStream_t)stream;
@@ -2424,6 +2427,9 @@ int fwime_lbfgs_minimize(fwime_ctx_t *ctx, int64_t n, int32_t memory, int32_t ma
   if (maxiter < 0) return set_err(ctx, FWIME_EINVAL, "maxiter must be >= 0");
   if (!(gtol >= 0.0) || !std::isfinite(gtol)) return set_err(ctx, FWIME_EINVAL, "gtol must be finite and >= 0");
   if (!fg || !x || !work || !f_hist || !iters) return set_err(ctx, FWIME_EINVAL, "null argument");
+  if ((reinterpret_cast<uintptr_t>(work) & 7) != 0) return set_err(ctx, FWIME_EINVAL, "work must be 8-byte aligned");
+  if (n > (int64_t(1) << 40) || work_floats < kLbfgsWorkHead + (2 * (int64_t)memory + 6) * n)
+    return set_err(ctx, FWIME_EINVAL, "work needs 4096 + (2 memory + 6) n floats");
   HIPCHK(hipSetDevice(ctx->device));
   // work: dot partials, then g, d, trial x, trial g and memory + 1 slots each of s and y
   double *part = (double *)work, *res = part + dot_partials();

@@ -155,3 +155,21 @@ def test_lbfgs_minimize_fwime_on_spline_grid(ctx):
     assert iters >= 1 and hist[-1] < hist[0]
     assert len(hist) == len(ref) and np.allclose(hist, ref, rtol=1e-4)
     assert all(q <= p for p, q in zip(hist, hist[1:]))
+
+
+def test_lbfgs_minimize_rejects_small_workspace(ctx):
+    import ctypes
+    import torch
+    import paper_2206_02362_amd as fw
+    from paper_2206_02362_amd import _abi
+    n, memory = 1000, 4
+    x = dev(np.ones(n))
+    work = torch.empty(_abi.LBFGS_WORK_HEAD + (2 * memory + 6) * n - 1, device="cuda:0")
+    hist = np.zeros(3)
+    iters = ctypes.c_int32(-1)
+    cb = _abi.OBJECTIVE_FN(lambda user, xp, gp, fp: 1)       # never reached
+    rc = ctx._lib.fwime_lbfgs_minimize(ctx._h, n, memory, 2, 0.0, cb, None, x.data_ptr(), work.data_ptr(),
+                                       work.numel(), hist.ctypes.data, ctypes.byref(iters),
+                                       torch.cuda.current_stream().cuda_stream)
+    assert rc == fw.FWIME_EINVAL and iters.value == -1
+    assert "work needs" in ctx._lib.fwime_last_error(ctx._h).decode()
