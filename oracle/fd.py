@@ -28,6 +28,15 @@ readings are made and used everywhere below:
 * Taper: g = g_z(iz) g_x(ix), g_1D(k) = exp(-(alpha k / nb)^2) for the cell k
   = 1..nb cells into the strip (Cerjan et al.'s Gaussian profile;
   alpha = 0.3 reproduces their edge value exp(-0.09)).
+* Free surface (``Grid.free_surface``; the free-surface-multiples variant of
+  the Marmousi2 test in Section 3 models with a free surface at the water
+  surface and absorbing boundaries elsewhere, after Robertsson's image-based
+  condition): the pressure vanishes on the model's first row (padded row nb),
+  and the Laplacian of the rows below reads
+  the field mirrored with opposite sign above it (the image method: u(nb - k)
+  = -u(nb + k)).  The field at and above the surface row stays zero, so the
+  top strip is unused.  The mirrored operator is symmetric on the remaining
+  rows, so the adjoint recursion and reciprocity hold as without it.
 * Point source: f^n = w(n dt) / (dx dz) at the source cell, so the scheme
   approximates (1/v^2) u_tt - Laplacian u = delta(x) w(t).  Receivers sample
   u^k at their cell, k = 0 .. nt-1 (d^0 = 0).
@@ -175,6 +184,7 @@ class Grid:
     dx: float
     dt: float
     sponge_alpha: float = 0.3
+    free_surface: bool = False
 
 
 @dataclass
@@ -205,9 +215,29 @@ class _Medium:
         gz = sponge_profile(g.nz, g.nb, g.sponge_alpha)
         self.gam = np.outer(gx, gz)
         self.shape = self.vpad.shape
+        self.fs = bool(g.free_surface)
+        if self.fs and g.nb < 4:
+            raise ValueError("a free surface needs nb >= 4 (the mirrored stencil rows)")
 
     def lap(self, u):
-        return laplacian(u, self.g.dz, self.g.dx)
+        if not self.fs:
+            return laplacian(u, self.g.dz, self.g.dx)
+        # free surface on the model's first row: zero there, mirrored with
+        # opposite sign above it, nothing computed at or above it
+        nb = self.g.nb
+        m = np.zeros_like(u)
+        m[:, nb + 1:] = u[:, nb + 1:]
+        for k in range(1, 5):
+            m[:, nb - k] = -u[:, nb + k]
+        out = laplacian(m, self.g.dz, self.g.dx)
+        out[:, :nb + 1] = 0.0
+        return out
+
+    def restrict(self, u):
+        """With a free surface, the field at and above the surface row is zero."""
+        if self.fs:
+            u[:, :self.g.nb + 1] = 0.0
+        return u
 
     def forward_record(self, source, rec_x, rec_z, keep=False):
         """Forward solve and sample receivers: returns (data[nrec][nt], history|None)."""
@@ -220,7 +250,7 @@ class _Medium:
         for n in range(nt - 1):
             f = source(n)
             rhs = self.lap(u) if f is None else self.lap(u) + f
-            u_next = gam * (2.0 * u - gam * u_prev + V * rhs)
+            u_next = self.restrict(gam * (2.0 * u - gam * u_prev + V * rhs))
             u_prev, u = u, u_next
             data[:, n + 1] = u[rec_x, rec_z]
             if keep:
@@ -243,7 +273,7 @@ class _Medium:
         for k in range(nt - 1, 0, -1):
             s = adj_source(k)
             rhs = self.lap(cur) if s is None else self.lap(cur) + s
-            prev = gam * (2.0 * cur - gam * lam_next + V * rhs)
+            prev = self.restrict(gam * (2.0 * cur - gam * lam_next + V * rhs))
             lam[k - 1] = prev
             lam_next, cur = cur, prev
         return lam
