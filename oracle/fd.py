@@ -539,14 +539,16 @@ def born_ext_tau_adj(g: Grid, vel: np.ndarray, geom: Geometry, data: np.ndarray,
 # FWIME objective (eq. fwime.obj at a given p~) and its gradient
 # ----------------------------------------------------------------------------
 
-def objective(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso) -> float:
-    """Phi = 1/2 || f(m) + B~(m) p~ - d_obs ||^2 + eps^2/2 || D p~ ||^2 (forward operators only)."""
-    r = model(g, vel, geom) + born_ext_fwd(g, vel, geom, ptilde) - np.asarray(dobs, dtype=np.float64)
+def objective(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso, lag=None) -> float:
+    """Phi = 1/2 || f(m) + B~(m) p~ - d_obs ||^2 + eps^2/2 || D p~ ||^2 (forward operators only);
+    B~ extends with subsurface offsets, or with time lags of `lag` steps when lag is given."""
+    ext = born_ext_fwd(g, vel, geom, ptilde) if lag is None else born_ext_tau_fwd(g, vel, geom, ptilde, lag)
+    r = model(g, vel, geom) + ext - np.asarray(dobs, dtype=np.float64)
     dso = np.asarray(dso, dtype=np.float64)
     return 0.5 * float(np.sum(r * r)) + 0.5 * eps ** 2 * float(np.sum((dso[:, None, None] * ptilde) ** 2))
 
 
-def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
+def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso, lag=None):
     """Objective and gradients of eq. fwime.obj at a fixed p~.
 
     With p~ held fixed (at the variable-projection optimum the partial
@@ -566,17 +568,34 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
                                                               (coefficient depends on v)
       grad_vel = P^T (g_B + g_1 + g_2) + g_3,
       grad_p~  = B~^T r + eps^2 d_h^2 p~.
+
+    With time lags (lag = L steps) the scattering source of equation n is
+    sum_k c_k T2u_{n-2kL}, so e_m = sum_k c_k lambda_{m+2kL} and g_3 takes
+    sum_k sum_n T2u_{n-2kL} lambda_n in place of the offset image; the rest
+    is unchanged.
     """
     _check(g, vel, geom)
     med = _Medium(g, vel)
     ptilde = np.asarray(ptilde, dtype=np.float64)
     dso = np.asarray(dso, dtype=np.float64)
     nh = ptilde.shape[0]
-    hs = _offsets(nh)
+    hs = _offsets(nh) if lag is None else _lags(nh)
+    if lag is not None and int(lag) < 1:
+        raise ValueError("lag must be a positive number of time steps")
     coef = _ext_coef(med, ptilde)
     nb, nt = g.nb, g.nt
     NX = med.shape[0]
-    zs = slice(nb, nb + g.nz)
+    zs, ys = slice(nb, nb + g.nz), slice(nb, nb + g.nx)
+
+    def scatter(n, hu):
+        if lag is None:
+            return _ext_scatter(med, coef, hs, med.t2(hu, n))
+        src = np.zeros(med.shape)
+        for i, k in enumerate(hs):
+            m = n - 2 * int(k) * int(lag)
+            if 0 <= m <= nt - 2:
+                src[ys, zs] += coef[i] * med.t2(hu, m)[ys, zs]
+        return src
 
     gpad = np.zeros(med.shape)               # g_B + g_1 + g_2 before the 2/(v^3 dt^2) factor
     img = np.zeros((nh, g.nx, g.nz))         # sum_n T2u(y-h) lambda(y+h)
@@ -584,7 +603,7 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
     for s in range(geom.nshots):
         rx, rz = _receivers(med, geom, s)
         d_u, hu = med.forward_record(_point_source(med, geom, s), rx, rz, keep=True)
-        d_du, hdu = med.forward_record(lambda n: _ext_scatter(med, coef, hs, med.t2(hu, n)), rx, rz, keep=True)
+        d_du, hdu = med.forward_record(lambda n: scatter(n, hu), rx, rz, keep=True)
         r = d_u + d_du - np.asarray(dobs[s], dtype=np.float64)
         misfit += 0.5 * float(np.sum(r * r))
         lam = med.adjoint(_receiver_injection(med, rx, rz, r))
@@ -593,6 +612,11 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
         e = np.zeros((nt + 1,) + med.shape)   # e[n] for n = 0..nt-2, zero beyond
         for n in range(nt - 1):
             for i, ih in enumerate(hs):
+                if lag is not None:
+                    m = n + 2 * int(ih) * int(lag)
+                    if 0 <= m <= nt - 2:
+                        e[n][ys, zs] += coef[i] * lam[m][ys, zs]
+                    continue
                 y = _y_range(NX, nb, g.nx, ih)
                 if y.size == 0:
                     continue
@@ -606,7 +630,14 @@ def gradient(g: Grid, vel, geom: Geometry, ptilde, dobs, eps: float, dso):
         for n in range(nt - 1):
             t2u = med.t2(hu, n)
             gpad += (t2u + med.t2(hdu, n)) * lam[n] + t2u * rho[n]
-        img += _ext_image(med, hs, lambda n: med.t2(hu, n), lam)
+        if lag is None:
+            img += _ext_image(med, hs, lambda n: med.t2(hu, n), lam)
+        else:
+            for n in range(nt - 1):
+                for i, k in enumerate(hs):
+                    m = n - 2 * int(k) * int(lag)
+                    if 0 <= m <= nt - 2:
+                        img[i] += med.t2(hu, m)[ys, zs] * lam[n][ys, zs]
 
     gpad *= 2.0 / (med.vpad ** 3 * g.dt ** 2)
     img_scaled = img * 2.0 / (med.vel[None] ** 3 * g.dt ** 2)          # B~^T r

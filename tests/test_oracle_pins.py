@@ -382,6 +382,55 @@ def test_gradient_ptilde_zero_is_fwi(grad_case):
     assert rel_l2(gp, oracle.born_ext_adj(g, w.vel, geo, r, w.nh)) < 1e-12
 
 
+# the gradient with time lags: central differences in m (error ~ t^2) and in
+# p~, and a single lag against the single offset (the same scattering source)
+@pytest.fixture(scope="module")
+def grad_case_tau():
+    w = synth.tiny(nz=16, nx=22, nb=5, nt=110, nshots=2, nh=5, seed=21)
+    g, geo = oracle_problem(w)
+    true = w.vel + 80.0 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 22, 30.0)
+    dobs = oracle.model(g, true, geo)
+    rng = np.random.default_rng(24)
+    pt = 0.05 * rng.standard_normal((5, w.nx, w.nz))
+    dso = synth.dso_weights(5)
+    eps, lag = 1e-3, 6
+    out = oracle.gradient(g, w.vel, geo, pt, dobs, eps, dso, lag=lag)
+    return w, g, geo, dobs, pt, dso, eps, lag, out
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_time_lag_velocity_central_difference(grad_case_tau, seed):
+    w, g, geo, dobs, pt, dso, eps, lag, (obj, gv, gp) = grad_case_tau
+    assert obj == pytest.approx(oracle.objective(g, w.vel, geo, pt, dobs, eps, dso, lag=lag), rel=1e-13)
+    dm = synth.gaussian_perturbation(w.nz, w.nx, w.dx, 200 + seed, 30.0)
+    t = 0.1
+    fp = oracle.objective(g, w.vel + t * dm, geo, pt, dobs, eps, dso, lag=lag)
+    fm = oracle.objective(g, w.vel - t * dm, geo, pt, dobs, eps, dso, lag=lag)
+    fd = (fp - fm) / (2 * t)
+    an = float(np.sum(gv * dm))
+    assert abs(fd - an) / abs(an) < 1e-6, (fd, an)
+
+
+def test_gradient_time_lag_ptilde_central_difference(grad_case_tau):
+    w, g, geo, dobs, pt, dso, eps, lag, (obj, gv, gp) = grad_case_tau
+    dp = np.random.default_rng(32).standard_normal(pt.shape)
+    t = 0.1
+    fp = oracle.objective(g, w.vel, geo, pt + t * dp, dobs, eps, dso, lag=lag)
+    fm = oracle.objective(g, w.vel, geo, pt - t * dp, dobs, eps, dso, lag=lag)
+    fd = (fp - fm) / (2 * t)
+    an = float(np.sum(gp * dp))
+    assert abs(fd - an) / abs(an) < 1e-9, (fd, an)
+
+
+def test_gradient_single_lag_equals_single_offset(grad_case_tau):
+    w, g, geo, dobs, pt, dso, eps, lag, _ = grad_case_tau
+    one = pt[2:3]
+    a = oracle.gradient(g, w.vel, geo, one, dobs, eps, dso[2:3], lag=lag)
+    b = oracle.gradient(g, w.vel, geo, one, dobs, eps, dso[2:3])
+    assert a[0] == pytest.approx(b[0], rel=1e-13)
+    assert rel_l2(a[1], b[1]) < 1e-12 and rel_l2(a[2], b[2]) < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # Variable-projection step (eqs. vp.obj, pert.opt): linear CG on the normal
 # equation, pinned against the normal matrix assembled column by column and a
