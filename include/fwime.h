@@ -255,7 +255,8 @@ void fwime_tape_free(fwime_tape_t *tape);
  * zn, xn: HOST double, strictly increasing, 2 to 2^24 nodes each, covering
  * [0, (nz-1) dz] and [0, (nx-1) dx] (to 1e-9 of the node span); read during
  * the call only.  mc: DEVICE [nxn][nzn]; out: DEVICE [nx][nz], z fastest.
- * The call synchronizes `stream` once (node upload); the interpolation tables
+ * The call synchronizes `stream` twice (before taking the context's arena and
+ * after the node upload); the interpolation tables
  * (about 12 bytes per fine point and node) live in the context's arena.
  * Argument errors (FWIME_EINVAL) are reported before anything is written;
  * non-finite node values propagate. */
@@ -283,8 +284,8 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
  * s, y: DEVICE [npairs][n]; g, d_out: DEVICE [n] (d_out may be g, must not
  * overlap s or y).  0 <= npairs <= 256, n >= 1.  Every pair must have
  * s_i.y_i > 0 (callers drop the others); otherwise FWIME_EINVAL before
- * anything is written.  The call synchronizes `stream` once per inner product
- * (2 npairs + 1 of them). */
+ * anything is written.  The call synchronizes `stream` once before it starts
+ * and once per inner product (3 npairs + 1 of them). */
 int fwime_lbfgs_direction(fwime_ctx_t *ctx, int64_t n, int32_t npairs, const float *s, const float *y,
                           const float *g, float *d_out, void *stream);
 
