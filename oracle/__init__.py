@@ -11,8 +11,11 @@ by model extension: practical applications" (arXiv 2206.02362), Section 2
 ("FWIME theory"): the objective (eq. fwime.obj), the variable-projection
 objective (eq. vp.obj) and the gradient split into a Born and a tomographic
 part (eqs. fwime.gradient.split, fwime.gradient.born, fwime.gradient.tomo).
+The outer loop of Sections 2 and 3 (the linear spline operator S and its
+adjoint, L-BFGS with a More-Thuente line search) is in :mod:`oracle.inversion`.
 The paper states the operators but not their discretization; every reading
-made here is listed in the module docstring of :mod:`oracle.fd`.
+made here is listed in the module docstrings of :mod:`oracle.fd` and
+:mod:`oracle.inversion`.
 """
 from .fd import (  # noqa: F401
     fd_second_derivative_weights,
