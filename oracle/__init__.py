@@ -43,6 +43,7 @@ from .inversion import (  # noqa: F401
     hat_matrix,
     spline_apply,
     spline_adjoint,
+    spline_refine,
     two_loop,
     lbfgs,
     on_spline_grid,

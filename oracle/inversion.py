@@ -70,6 +70,15 @@ def spline_adjoint(zn, xn, nz: int, nx: int, dz: float, dx: float, f: np.ndarray
     return Ax.T @ np.asarray(f, dtype=np.float64) @ Az
 
 
+def spline_refine(zn, xn, mc: np.ndarray, zn_fine, xn_fine) -> np.ndarray:
+    """Node values mc [len(xn)][len(zn)] onto a finer node set [len(xn_fine)][len(zn_fine)]:
+    the same linear interpolation evaluated at the new nodes (the next grid of
+    the coarse-to-fine sequence)."""
+    Az = hat_matrix(zn, zn_fine)
+    Ax = hat_matrix(xn, xn_fine)
+    return Ax @ np.asarray(mc, dtype=np.float64) @ Az.T
+
+
 def two_loop(g: np.ndarray, S, Y) -> np.ndarray:
     """H g for the L-BFGS inverse-Hessian approximation H built from the pairs
     (s_i, y_i), oldest first, with H_0 = (s.y / y.y of the newest pair) I, or I

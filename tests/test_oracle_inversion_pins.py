@@ -8,7 +8,8 @@ Each pin checks the oracle against something other than itself:
 * S is the identity when the nodes are the finite-difference grid, and one
   halving of the spacing puts the average of the two neighbours at each
   midpoint (the refinement sequence of Section 2);
-* S* is the adjoint of S (dot-product test);
+* S* is the adjoint of S (dot-product test); refining onto a node set that
+  contains the old one leaves the model on the grid unchanged;
 * the two-loop recursion equals the explicit BFGS inverse-Hessian update
   applied pair by pair (the textbook dense formula), and satisfies the
   newest secant equation H y = s;
@@ -79,6 +80,21 @@ def test_spline_identity_on_fd_grid_and_one_halving():
     assert np.allclose(fine[::2, 1::2], 0.5 * (mc[:, :-1] + mc[:, 1:]), atol=1e-14)
     assert np.allclose(fine[1::2, 1::2],
                        0.25 * (mc[:-1, :-1] + mc[1:, :-1] + mc[:-1, 1:] + mc[1:, 1:]), atol=1e-14)
+
+
+def test_spline_refine_keeps_the_model(grid):
+    # a node set containing the coarse one describes the same piecewise-linear
+    # model: refining and then mapping to the grid changes nothing
+    nz, nx, dz, dx, zn, xn = grid
+    rng = np.random.default_rng(11)
+    zf = np.unique(np.concatenate([zn, 0.5 * (zn[:-1] + zn[1:])]))
+    xf = np.unique(np.concatenate([xn, 0.5 * (xn[:-1] + xn[1:])]))
+    mc = rng.standard_normal((len(xn), len(zn)))
+    mf = oracle.spline_refine(zn, xn, mc, zf, xf)
+    assert np.allclose(mf[::2, ::2], mc, atol=1e-14)
+    a = oracle.spline_apply(zn, xn, nz, nx, dz, dx, mc)
+    b = oracle.spline_apply(zf, xf, nz, nx, dz, dx, mf)
+    assert np.max(np.abs(a - b)) < 1e-12
 
 
 def test_spline_adjoint_dot_product(grid):
