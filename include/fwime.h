@@ -275,6 +275,18 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
                          int32_t nzn, const double *zn, int32_t nxn, const double *xn,
                          const float *f, float *mc_out, void *stream);
 
+/* Model on the next, finer spline grid (Section 2: the inversion moves along
+ * a sequence of spline grids of decreasing spacing): the node values mc on
+ * (zn, xn) evaluated by the same linear interpolation at the new nodes
+ * (zf, xf).  zn, xn: HOST double as for fwime_spline_apply (starting at the
+ * grid's origin); zf[nzf], xf[nxf]: HOST double, strictly increasing, within
+ * the old nodes' span (to 1e-9 of it), 1 to 2^24 each; read during the call
+ * only.  mc: DEVICE [nxn][nzn]; mf_out: DEVICE [nxf][nzf].  Synchronizes
+ * `stream` twice; argument errors (FWIME_EINVAL) before anything is written. */
+int fwime_spline_refine(fwime_ctx_t *ctx, int32_t nzn, const double *zn, int32_t nxn, const double *xn,
+                        const float *mc, int32_t nzf, const double *zf, int32_t nxf, const double *xf,
+                        float *mf_out, void *stream);
+
 /* L-BFGS search direction (Section 3 minimizes the FWIME objective over the
  * spline nodes with L-BFGS): d_out = -H g, where H is the limited-memory
  * inverse-Hessian approximation built from npairs pairs (s_i, y_i), oldest

@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_spline_refine", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -101,6 +101,9 @@ def load() -> ctypes.CDLL:
     lib.fwime_lbfgs_minimize.restype = I
     lib.fwime_lbfgs_direction.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
     lib.fwime_lbfgs_direction.restype = I
+    lib.fwime_spline_refine.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.c_int32, P,
+                                        ctypes.c_int32, P, P, P]
+    lib.fwime_spline_refine.restype = I
     for name in ("fwime_spline_apply", "fwime_spline_adjoint"):
         fn = getattr(lib, name)
         fn.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, D, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P]
@@ -407,6 +410,15 @@ class Context:
     def fwime_spline_adjoint(self, nz: int, nx: int, dz: float, dx: float, zn, xn, f, mc_out):
         self._spline_call(self._lib.fwime_spline_adjoint, nz, nx, dz, dx, zn, xn,
                           f, (nx, nz), mc_out, (len(xn), len(zn)))
+
+    def spline_refine(self, zn, xn, mc, zf, xf):
+        """Node values mc [len(xn)][len(zn)] moved to the finer nodes [len(xf)][len(zf)]."""
+        zn, xn, zf, xf = (np.ascontiguousarray(v, dtype=np.float64) for v in (zn, xn, zf, xf))
+        out = torch.empty((xf.size, zf.size), device=mc.device, dtype=torch.float32)
+        self._check(self._lib.fwime_spline_refine(
+            self._h, zn.size, zn.ctypes.data, xn.size, xn.ctypes.data, _dptr(mc, (xn.size, zn.size)),
+            zf.size, zf.ctypes.data, xf.size, xf.ctypes.data, _dptr(out, None), _stream(mc.device)))
+        return out
 
     def spline_apply(self, nz: int, nx: int, dz: float, dx: float, zn, xn, mc):
         """S m: node values [len(xn)][len(zn)] onto the model grid [nx][nz]."""

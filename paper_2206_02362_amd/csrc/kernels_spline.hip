@@ -7,7 +7,8 @@
 // the last cell closed) with weight tz for node kz+1 and 1 - tz for node kz;
 // likewise along x.  Per axis a table kernel finds every fine point's cell by
 // binary search over the node coordinates (in FP64) and, for every node j,
-// the first fine point whose cell is at least j.  Because the cell index never
+// the first fine point whose cell is at least j.  The same tables, evaluated
+// at the nodes of a finer spline grid, move a model to that grid.  Because the cell index never
 // decreases along the axis, the fine points of cell j form the range
 // [start[j], start[j+1]), so the adjoint is a deterministic gather: node j
 // collects the points of cell j - 1 with weight t and those of cell j with
@@ -25,11 +26,13 @@ static unsigned spline_blocks(long n) {
   return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
-// cell[i], wt[i] for fine points i = 0..nf-1 at coordinate i*h; nn >= 2 nodes
-__global__ void k_spline_axis(const double *nodes, int nn, int nf, double h, int *cell, float *wt) {
+// cell[i], wt[i] for target points i = 0..nf-1 at coordinate pts[i], or at
+// i*h without pts (the finite-difference grid); nn >= 2 nodes
+__global__ void k_spline_axis(const double *nodes, int nn, const double *pts, int nf, double h, int *cell,
+                              float *wt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
-  const double p = i * h;
+  const double p = pts ? pts[i] : i * h;
   int lo = 0, hi = nn - 2;                     // the cell is in [lo, hi]
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -98,9 +101,9 @@ __global__ void k_spline_adj_x(const float *__restrict__ tmp, int nzn, const flo
   }
 }
 
-hipError_t launch_spline_tables(const double *nodes, int nn, int nf, double h, int *cell, float *wt, int *start,
-                                hipStream_t st) {
-  k_spline_axis<<<(nf + 255) / 256, 256, 0, st>>>(nodes, nn, nf, h, cell, wt);
+hipError_t launch_spline_tables(const double *nodes, int nn, const double *pts, int nf, double h, int *cell,
+                                float *wt, int *start, hipStream_t st) {
+  k_spline_axis<<<(nf + 255) / 256, 256, 0, st>>>(nodes, nn, pts, nf, h, cell, wt);
   k_spline_starts<<<(nn + 1 + 255) / 256, 256, 0, st>>>(cell, nf, nn, start);
   return hipGetLastError();
 }

@@ -2233,8 +2233,8 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
 // Linear spline operator S and its adjoint (Section 2's spline grid)
 // ---------------------------------------------------------------------------
 namespace fw {
-hipError_t launch_spline_tables(const double *nodes, int nn, int nf, double h, int *cell, float *wt, int *start,
-                                hipStream_t st);
+hipError_t launch_spline_tables(const double *nodes, int nn, const double *pts, int nf, double h, int *cell,
+                                float *wt, int *start, hipStream_t st);
 hipError_t launch_spline_apply(const float *mc, int nzn, const int *cz, const float *tz, const int *cx,
                                const float *tx, int nz, int nx, float *out, hipStream_t st);
 hipError_t launch_spline_adjoint(const float *f, int nz, int nx, const float *tz, const int *sz, int nzn,
@@ -2292,8 +2292,8 @@ int spline_setup(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, double dx,
   HIPCHK(hipMemcpyAsync(a.zn, zn, nzn * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(a.xn, xn, nxn * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(launch_spline_tables(a.zn, nzn, nz, dz, a.cz, a.tz, a.sz, st));
-  HIPCHK(launch_spline_tables(a.xn, nxn, nx, dx, a.cx, a.tx, a.sx, st));
+  HIPCHK(launch_spline_tables(a.zn, nzn, nullptr, nz, dz, a.cz, a.tz, a.sz, st));
+  HIPCHK(launch_spline_tables(a.xn, nxn, nullptr, nx, dx, a.cx, a.tx, a.sx, st));
   return FWIME_OK;
 }
 
@@ -2324,6 +2324,59 @@ int fwime_spline_adjoint(fwime_ctx_t *ctx, int32_t nz, int32_t nx, double dz, do
   int rc = spline_setup(ctx, nz, nx, dz, dx, nzn, zn, nxn, xn, f, mc_out, (long)nx * nzn, &tmp, a, st);
   if (rc) return rc;
   HIPCHK(launch_spline_adjoint(f, nz, nx, a.tz, a.sz, nzn, a.tx, a.sx, nxn, tmp, mc_out, st));
+  return FWIME_OK;
+}
+
+int fwime_spline_refine(fwime_ctx_t *ctx, int32_t nzn, const double *zn, int32_t nxn, const double *xn,
+                        const float *mc, int32_t nzf, const double *zf, int32_t nxf, const double *xf,
+                        float *mf_out, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  // the new nodes: strictly increasing, inside the old nodes' span
+  auto targets = [&](const double *t, int32_t nt_, const double *n, int32_t nn, const char *name) -> int {
+    const std::string nm(name);
+    if (nt_ < 1 || nt_ > kSplineMaxNodes) return set_err(ctx, FWIME_EINVAL, nm + ": 1 to 2^24 new nodes");
+    if (!t) return set_err(ctx, FWIME_EINVAL, nm + " new node coordinates are null");
+    for (int j = 0; j < nt_; ++j)
+      if (!std::isfinite(t[j]) || (j > 0 && !(t[j] > t[j - 1])))
+        return set_err(ctx, FWIME_EINVAL, nm + " new node coordinates must be finite and strictly increasing");
+    if (nn >= 2 && n) {
+      const double tol = 1e-9 * std::max(1.0, std::fabs(n[nn - 1] - n[0]));
+      if (t[0] < n[0] - tol || t[nt_ - 1] > n[nn - 1] + tol)
+        return set_err(ctx, FWIME_EINVAL, nm + " new nodes must lie within the old nodes");
+    }
+    return FWIME_OK;
+  };
+  int rc;
+  if ((rc = check_spline_axis(ctx, zn, nzn, 1, 1.0, "z")) || (rc = check_spline_axis(ctx, xn, nxn, 1, 1.0, "x")) ||
+      (rc = targets(zf, nzf, zn, nzn, "z")) || (rc = targets(xf, nxf, xn, nxn, "x")))
+    return rc;
+  if (!mc || !mf_out) return set_err(ctx, FWIME_EINVAL, "input or output is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(st));      // earlier work on the stream may still use the arena
+  SplineAxes a;
+  double *zt = nullptr, *xt = nullptr;
+  Carve cv;
+  cv.add(&a.zn, nzn);
+  cv.add(&a.xn, nxn);
+  cv.add(&zt, nzf);
+  cv.add(&xt, nxf);
+  cv.add(&a.cz, nzf);
+  cv.add(&a.cx, nxf);
+  cv.add(&a.tz, nzf);
+  cv.add(&a.tx, nxf);
+  cv.add(&a.sz, (long)nzn + 1);
+  cv.add(&a.sx, (long)nxn + 1);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  HIPCHK(hipMemcpyAsync(a.zn, zn, nzn * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(a.xn, xn, nxn * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(zt, zf, nzf * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(xt, xf, nxf * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(launch_spline_tables(a.zn, nzn, zt, nzf, 0.0, a.cz, a.tz, a.sz, st));
+  HIPCHK(launch_spline_tables(a.xn, nxn, xt, nxf, 0.0, a.cx, a.tx, a.sx, st));
+  HIPCHK(launch_spline_apply(mc, nzn, a.cz, a.tz, a.cx, a.tx, nzf, nxf, mf_out, st));
   return FWIME_OK;
 }
 

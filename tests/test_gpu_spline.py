@@ -117,3 +117,31 @@ def test_spline_rejects_bad_nodes(ctx):
         with pytest.raises(fw.FwimeError):
             ctx.fwime_spline_apply(nz, nx, dz, dx, zn, xn, mc, out)
     assert float(out.min()) == 7.0 and float(out.max()) == 7.0
+
+
+def test_spline_refine_matches_oracle(ctx):
+    # the next grid of the sequence: every node, every midpoint and a few extra
+    # nodes near an interface, on the benchmark's model size
+    nz, nx, dz, dx = 300, 1700, 10.0, 10.0
+    zn, xn = _nodes(nz, dz, 20, None), _nodes(nx, dx, 20)
+    zf = np.unique(np.concatenate([zn, 0.5 * (zn[:-1] + zn[1:]), [1203.7, 1207.1]]))
+    xf = np.unique(np.concatenate([xn, 0.5 * (xn[:-1] + xn[1:])]))
+    say(f"case: spline refine {len(zn)}x{len(xn)} -> {len(zf)}x{len(xf)} nodes")
+    mc = (2000.0 + 300.0 * np.random.default_rng(3).standard_normal((len(xn), len(zn)))).astype(np.float32)
+    ref = oracle.spline_refine(zn, xn, mc.astype(np.float64), zf, xf)
+    mf = ctx.spline_refine(zn, xn, dev(mc), zf, xf)
+    err = rel_l2(t2n(mf), ref)
+    # the refined model on the grid is the coarse one
+    a = t2n(ctx.spline_apply(nz, nx, dz, dx, zn, xn, dev(mc)))
+    b = t2n(ctx.spline_apply(nz, nx, dz, dx, zf, xf, mf))
+    say(f"  rel-L2 {err:.3e}, grid models differ by {rel_l2(b, a):.3e}")
+    assert err < TOL and rel_l2(b, a) < TOL
+
+
+def test_spline_refine_rejects_nodes_outside(ctx):
+    import paper_2206_02362_amd as fw
+    zn, xn = np.array([0.0, 100.0, 200.0]), np.array([0.0, 300.0])
+    mc = dev(np.ones((2, 3)))
+    for zf in (np.array([0.0, 250.0]), np.array([50.0, 40.0])):
+        with pytest.raises(fw.FwimeError):
+            ctx.spline_refine(zn, xn, mc, zf, xn)
