@@ -2253,7 +2253,7 @@ int check_spline_axis(fwime_ctx_t *ctx, const double *n, int32_t nn, int32_t nf,
   const std::string nm(name);
   if (nn < 2) return set_err(ctx, FWIME_EINVAL, nm + ": at least two spline nodes are needed");
   if (nn > kSplineMaxNodes) return set_err(ctx, FWIME_EINVAL, nm + ": more than 2^24 spline nodes");
-  if (nf < 1) return set_err(ctx, FWIME_EINVAL, nm + ": the grid needs at least one point");
+  if (nf < 1 || nf > (1 << 30)) return set_err(ctx, FWIME_EINVAL, nm + ": the grid needs 1 to 2^30 points");
   if (!(h > 0.0) || !std::isfinite(h)) return set_err(ctx, FWIME_EINVAL, nm + ": grid spacing must be positive");
   if (!n) return set_err(ctx, FWIME_EINVAL, nm + " node coordinates are null");
   for (int j = 0; j < nn; ++j)
