@@ -43,3 +43,46 @@ def test_strerror_without_gpu():
 def test_python_binding_exports_match_header():
     import paper_2206_02362_amd as fw
     assert sorted(fw.EXPORTED) == declared_functions()
+
+
+def _prototypes():
+    """name -> [parameter declarations] of every function include/fwime.h declares."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(fwime_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        params = [p.strip() for p in m.group(2).replace("\n", " ").split(",")]
+        out[m.group(1)] = [] if params == ["void"] or params == [""] else params
+    return out
+
+
+def _c_kind(param: str):
+    if "*" in param or param.startswith("fwime_objective_fn"):
+        return ("ptr", ctypes.sizeof(ctypes.c_void_p))
+    base = param.rsplit(" ", 1)[0].replace("const ", "").strip()
+    sizes = {"double": ("float", 8), "int32_t": ("int", 4), "int": ("int", 4), "int64_t": ("int", 8),
+             "size_t": ("int", ctypes.sizeof(ctypes.c_size_t))}
+    return sizes[base]
+
+
+def _py_kind(t):
+    if t in (ctypes.c_double, ctypes.c_float):
+        return ("float", ctypes.sizeof(t))
+    if t in (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint32):
+        return ("int", ctypes.sizeof(t))
+    return ("ptr", ctypes.sizeof(ctypes.c_void_p))      # c_void_p, POINTER(...), c_char_p, CFUNCTYPE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfwime.so not built")
+def test_binding_argtypes_match_header_prototypes():
+    # a parameter count or kind that differs between the header and the ctypes
+    # binding would hand the library misplaced arguments
+    from paper_2206_02362_amd import _abi
+    lib = _abi.load()
+    protos = _prototypes()
+    assert sorted(protos) == declared_functions()
+    for name, params in protos.items():
+        fn = getattr(lib, name)
+        assert fn.argtypes is not None, name
+        assert len(fn.argtypes) == len(params), (name, len(fn.argtypes), params)
+        for p, t in zip(params, fn.argtypes):
+            assert _c_kind(p) == _py_kind(t), (name, p, t)
