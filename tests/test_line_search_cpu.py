@@ -114,3 +114,37 @@ def test_line_search_matches_minpack(tmp_path):
             assert status == 2, (k, a0, gt, status, task)
     print(f"{converged} of {len(cases)} searches converged")
     assert converged >= len(cases) - 4
+
+
+def test_line_search_error_and_bound_paths(tmp_path):
+    # invalid starts are errors; on phi(a) = -a (no minimizer) the search
+    # climbs to stpmax and ends in a warning there, as MINPACK's does
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    prog = '#include <cstdio>\n#include "' + HEADER + r'''"
+int main() {
+  fw::MoreThuente a;
+  std::printf("%d ", (int)a.start(1.0, 0.0, 1.0));          // ascent direction
+  std::printf("%d ", (int)a.start(-1.0, 0.0, -1.0));        // step below stpmin
+  fw::MoreThuente b;
+  b.stpmin = 0.0; b.stpmax = 10.0;
+  auto st = b.start(1.0, 0.0, -1.0);
+  int nfev = 0;
+  while (st == fw::MoreThuente::kEvaluate && nfev < 100) { st = b.next(-b.stp, -1.0); ++nfev; }
+  std::printf("%d %d %.17g\n", (int)st, nfev, b.stp);
+  return 0;
+}
+'''
+    cpp, exe = tmp_path / "e.cpp", tmp_path / "e"
+    cpp.write_text(prog)
+    subprocess.run([gxx, "-O1", "-std=c++17", "-o", str(exe), str(cpp)], check=True)
+    e_up, e_low, status, nfev, stp = subprocess.run([str(exe)], check=True, capture_output=True,
+                                                    text=True).stdout.split()
+    assert int(e_up) == 3 and int(e_low) == 3
+    calls = []
+    srch = DCSRCH(lambda a: calls.append(a) or -a, lambda a: -1.0, 1e-4, 0.9, 1e-14, 0.0, 10.0)
+    stp_ref, _, _, task = srch(1.0, phi0=0.0, derphi0=-1.0, maxiter=100)
+    task = task.decode() if isinstance(task, bytes) else str(task)
+    assert task.startswith("WARN") and "STPMAX" in task.upper()
+    assert int(status) == 2 and float(stp) == 10.0 and int(nfev) == len(calls)
