@@ -13,6 +13,11 @@
   slot q was issued, two stores each).  A model of the kernel's program order
   (three slots issued ahead, then per slot: wait, barrier, issue q + 3,
   consume q) must give exactly that count for every slot of every length.
+* The spline table kernels (k_spline_axis, k_spline_starts in
+  csrc/kernels_spline.hip), compiled with g++ and run thread by thread,
+  threads past the end included: cells stay in [0, nn - 2] and equal numpy's
+  searchsorted, weights lie in [0, 1], each node's range holds exactly the
+  points of its cell.
 """
 import os
 import random
@@ -163,3 +168,61 @@ def test_scatter_wait_counts_are_exact(per):
                 assert younger == per * y + 2 * c, (q0, q1, q)
                 issue(q + 3)
                 consume(q)
+
+
+def test_spline_tables_match_searchsorted(tmp_path):
+    # k_spline_axis / k_spline_starts (csrc/kernels_spline.hip), compiled with
+    # g++ and run thread by thread over random node sets and target points:
+    # every cell index stays in [0, nn - 2], agrees with numpy's searchsorted,
+    # and every node's range of points is the set of points in its cell
+    import numpy as np
+    src = open(os.path.join(CSRC, "kernels_spline.hip")).read()
+    axis = _function(src, "__global__ void k_spline_axis(")
+    starts = _function(src, "__global__ void k_spline_starts(")
+    rng = np.random.default_rng(5)
+    cases = []
+    for _ in range(60):
+        nn = int(rng.integers(2, 40))
+        nodes = np.sort(rng.choice(np.arange(0, 4000), nn, replace=False)) * 0.25
+        nf = int(rng.integers(1, 300))
+        pts = np.sort(rng.uniform(nodes[0], nodes[-1], nf))
+        pts[0], pts[-1] = nodes[0], nodes[-1]
+        cases.append((nodes, pts))
+    body = []
+    for c, (nodes, pts) in enumerate(cases):
+        body.append(f"static const double N{c}[] = {{{', '.join(repr(float(v)) for v in nodes)}}};")
+        body.append(f"static const double P{c}[] = {{{', '.join(repr(float(v)) for v in pts)}}};")
+    runs = "\n".join(f"  run(N{c}, {len(n)}, P{c}, {len(p)});" for c, (n, p) in enumerate(cases))
+    prog = ("#include <cmath>\n#include <cstdio>\n#include <vector>\nusing std::fmin; using std::fmax;\n"
+            "#define __global__\nstruct Dim { int x; };\nstatic Dim blockIdx, threadIdx, blockDim{1};\n"
+            + axis + "\n" + starts + "\n" + "\n".join(body) + r"""
+static void run(const double *nodes, int nn, const double *pts, int nf) {
+  std::vector<int> cell(nf, -1), start(nn + 1, -1);
+  std::vector<float> wt(nf, -1.0f);
+  blockIdx.x = 0;
+  for (int i = 0; i < nf + 3; ++i) { threadIdx.x = i; k_spline_axis(nodes, nn, pts, nf, 0.0, cell.data(), wt.data()); }
+  for (int j = 0; j < nn + 4; ++j) { threadIdx.x = j; k_spline_starts(cell.data(), nf, nn, start.data()); }
+  for (int i = 0; i < nf; ++i) std::printf("%d %.9g ", cell[i], wt[i]);
+  std::printf("| ");
+  for (int j = 0; j <= nn; ++j) std::printf("%d ", start[j]);
+  std::printf("\n");
+}
+int main() {
+""" + runs + "\n  return 0;\n}\n")
+    lines = _run_cpp(tmp_path, prog).strip().split("\n")
+    assert len(lines) == len(cases)
+    for (nodes, pts), line in zip(cases, lines):
+        left, right = line.split("|")
+        vals = left.split()
+        cell = np.array([int(v) for v in vals[0::2]])
+        wt = np.array([float(v) for v in vals[1::2]])
+        start = np.array([int(v) for v in right.split()])
+        nn = len(nodes)
+        ref = np.clip(np.searchsorted(nodes, pts, side="right") - 1, 0, nn - 2)
+        assert np.array_equal(cell, ref)
+        assert np.all((wt >= 0) & (wt <= 1))
+        t = (pts - nodes[ref]) / (nodes[ref + 1] - nodes[ref])
+        assert np.allclose(wt, np.clip(t, 0, 1), atol=1e-7)
+        for j in range(nn):
+            assert np.array_equal(np.arange(start[j], start[j + 1]), np.nonzero(cell == j)[0])
+        assert start[0] == 0 and start[nn] == len(pts)
