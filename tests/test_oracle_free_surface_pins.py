@@ -7,8 +7,9 @@ mirrored with opposite sign.
   source and its image of opposite sign (velocity and taper mirrored too).
 * Analytic: in a homogeneous medium the response is G(r) - G(r'), with r' the
   distance to the image source (the 2D Green's function, within 1e-2).
-* Reciprocity, the Born and extended Born dot-product tests, and the velocity
-  gradient against central differences, all with the free surface on.
+* Reciprocity, the Born, extended-Born and time-lag dot-product tests, and
+  the velocity gradient against central differences, all with the free
+  surface on.
 """
 import math
 
@@ -117,6 +118,16 @@ def test_free_surface_dot_born_extended(fs_small):
     d = rng.standard_normal((geo.nshots, w.nrec, w.nt))
     lhs = float(np.sum(oracle.born_ext_fwd(g, w.vel, geo, p) * d))
     rhs = float(np.sum(p * oracle.born_ext_adj(g, w.vel, geo, d, w.nh)))
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs))
+
+
+def test_free_surface_dot_born_time_lag(fs_small):
+    w, g, geo = fs_small
+    rng = np.random.default_rng(6)
+    p = rng.standard_normal((5, w.nx, w.nz))
+    d = rng.standard_normal((geo.nshots, w.nrec, w.nt))
+    lhs = float(np.sum(oracle.born_ext_tau_fwd(g, w.vel, geo, p, 4) * d))
+    rhs = float(np.sum(p * oracle.born_ext_tau_adj(g, w.vel, geo, d, 5, 4)))
     assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs))
 
 
