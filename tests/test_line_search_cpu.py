@@ -7,7 +7,7 @@ phi(a) = (a + 0.004)^5 - 2 (a + 0.004)^4), a quadratic, an exponential and a
 wavy function, from first trial steps between 1e-3 and 1e3 and with
 gtol 0.1 and 0.9.  Its accepted step must equal that of scipy's
 DCSRCH (MINPACK's dcsrch, the routine behind scalar_search_wolfe1, the same
-published method), after the same number of evaluations, and must satisfy
+published method), after the same trial steps, and must satisfy
 the strong Wolfe conditions; where scipy reports no step, the header
 must end in a warning.
 """
@@ -16,6 +16,7 @@ import os
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 from scipy.optimize._dcsrch import DCSRCH
 
@@ -57,7 +58,7 @@ def _run_header(tmp_path):
     if gxx is None:
         pytest.skip("g++ not available")
     lines = "\n".join(f"  {{{k}, {a0!r}, {gt!r}}}," for k, a0, gt in _cases())
-    prog = ('#include <cmath>\n#include <cstdio>\n#include "' + HEADER + '"\n' + CPP_FUNCS + r"""
+    prog = ('#include <cmath>\n#include <cstdio>\n#include <vector>\n#include "' + HEADER + '"\n' + CPP_FUNCS + r"""
 struct Case { int k; double a0, gtol; };
 static const Case kCases[] = {
 """ + lines + r"""
@@ -70,13 +71,17 @@ int main() {
     phi(c.k, 0.0, f0, g0);
     auto st = ls.start(c.a0, f0, g0);
     int nfev = 0;
+    std::vector<double> trials;
     while (st == fw::MoreThuente::kEvaluate && nfev < 100) {
       double f, g;
       phi(c.k, ls.stp, f, g);
+      trials.push_back(ls.stp);
       ++nfev;
       st = ls.next(f, g);
     }
-    std::printf("%d %d %.17g\n", (int)st, nfev, ls.stp);
+    std::printf("%d %d %.17g", (int)st, nfev, ls.stp);
+    for (double t : trials) std::printf(" %.17g", t);
+    std::printf("\n");
   }
   return 0;
 }
@@ -86,7 +91,8 @@ int main() {
     cpp.write_text(prog)
     subprocess.run([gxx, "-O1", "-std=c++17", "-o", str(exe), str(cpp)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
-    return [(int(a), int(b), float(c)) for a, b, c in (l.split() for l in out if l.strip())]
+    rows = [l.split() for l in out if l.strip()]
+    return [(int(r[0]), int(r[1]), float(r[2]), [float(v) for v in r[3:]]) for r in rows]
 
 
 def test_line_search_matches_minpack(tmp_path):
@@ -94,7 +100,7 @@ def test_line_search_matches_minpack(tmp_path):
     cases = _cases()
     assert len(res) == len(cases)
     converged = 0
-    for (k, a0, gt), (status, nfev, stp) in zip(cases, res):
+    for (k, a0, gt), (status, nfev, stp, trials) in zip(cases, res):
         f, g = FUNCS[k]
         # the first trial step is an input of the method; scipy's wrapper
         # (scalar_search_wolfe1) picks it itself, so its DCSRCH class, the
@@ -107,6 +113,7 @@ def test_line_search_matches_minpack(tmp_path):
             assert status == 1, (k, a0, gt, status, task)
             assert stp == pytest.approx(stp_ref, rel=1e-10), (k, a0, gt, stp, stp_ref)
             assert nfev == len(calls), (k, a0, gt, nfev, len(calls))
+            assert np.allclose(trials, calls, rtol=1e-10, atol=0), (k, a0, gt)
             assert f(stp) <= f(0.0) + 1e-4 * stp * g(0.0)
             assert abs(g(stp)) <= gt * abs(g(0.0))
             converged += 1
