@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the FWIME hot path on one MI355X.
 
-One step = one pass of every operator of the hot path over the whole shot set:
-nonlinear modeling f(m), extended Born B~(m) p~, its adjoint B~^T d and the
-FWIME objective with both gradients, each through the C ABI.  The workload is
-the Marmousi-like 300 x 1700 grid (10 m, 60-cell absorbing strip, padded
-420 x 1820), 100 shots every 170 m, 1700 receivers, 8 Hz Ricker, dt = 0.8 ms,
-nt = 5000, 61 subsurface offsets; inputs are synthetic and seeded.
+Headline (one "step"): nonlinear modeling of 256 shots on uneven grids --
+200 x 600, 300 x 1700 and 500 x 2500 cells at 10 m with a 40-cell absorbing
+strip, smooth random 1500-4500 m/s models, Ricker 6-12 Hz, nt 3000-6000,
+dt = 0.8 ms, one receiver per column -- as ONE fwime_model_batch call: every
+time step of every shot runs in shared two-step stencil launches with an
+autotuned tile width.  cell-updates/s counts NZ * NX * (nt - 1) padded
+cell-updates per shot.  Inputs are synthetic and seeded and already in HBM.
 
-cell-updates/s counts propagations as the paper's cost analysis does
-(Section "Computational aspects": modeling 1, extended Born 2, its adjoint 2,
-gradient 6 per shot), each NZ * NX * (nt - 1) padded cell-updates; recomputed
-propagations of the checkpointing scheme are not counted.
+After the timed steps, each further section runs only while the run stays
+inside its wall-clock deadline (a skipped section is recorded as such):
+  roofline   the stencil launches of the timed calls (HIP events on the stream
+             they run on) against 16 algorithmic bytes per cell-update;
+  plain      the same 256 shots one fwime_model call at a time;
+  serving    a seeded Poisson request stream (20 requests/s) through the
+             request loop and through one-at-a-time FIFO, p50/p99 latency;
+  marmousi   one pass of all four operators (modeling, extended Born, its
+             adjoint, the gradient) on the 300 x 1700 Marmousi-like set,
+             100 shots, nt 5000, 61 offsets;
+  time_lag, spline, vp_step   the rows built beyond the hot path;
+  cpu_baseline  the FP64 oracle on the host cores (run in worker processes
+             beside the GPU sections, never during the timed steps).
 """
 from __future__ import annotations
 
@@ -22,46 +32,173 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, ROOT)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
 STENCIL_BYTES = 16         # read u^n, u^{n-1}, V; write u^{n+1}
 PROPAGATIONS = {"model": 1, "born_ext_fwd": 2, "born_ext_adj": 2, "gradient": 6}
+CSRC = os.path.join(ROOT, "paper_2206_02362_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_multi_batch256_traffic.json")
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - T_START:7.1f} s]", *a, file=sys.stderr, flush=True)
 
 
-CSRC = os.path.join(ROOT, "paper_2206_02362_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+def elapsed() -> float:
+    return time.perf_counter() - T_START
 
 
-def two_step() -> bool:
-    """The library runs two time steps per stencil launch unless FWIME_STEP1 is set."""
-    v = os.environ.get("FWIME_STEP1")
-    return not (v and int(v) != 0)
+# ----------------------------------------------------------------------------
+# CPU baseline: the oracle in worker processes (numpy only, one thread each)
+# ----------------------------------------------------------------------------
 
+def _cpu_model_task(kind: str, index: int, steps: int):
+    """oracle.model on one shot for the first `steps` time steps."""
+    import oracle
+    import synth
+    if kind == "batch":
+        w = synth.batch_set(256)[index]
+    else:
+        w = synth.marmousi_set(100).subset([index])
+    steps = min(steps, w.nt)
+    g = oracle.Grid(w.nz, w.nx, w.nb, steps, w.dz, w.dx, w.dt, w.sponge_alpha)
+    geo = oracle.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix, w.wavelet[:, :steps].copy())
+    t = time.perf_counter()
+    oracle.model(g, w.vel, geo)
+    dt = time.perf_counter() - t
+    cells = (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (steps - 1)
+    return {"kind": kind, "index": index, "steps": steps, "cells": cells, "s": dt,
+            "full_cells": (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)}
+
+
+def _cpu_plain_small_task():
+    """All four operators of the oracle on the 100 x 200 problem (nt 1500, 11 offsets)."""
+    import oracle
+    import synth
+    w = synth.plain_small()
+    g = oracle.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+    geo = oracle.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix, w.wavelet)
+    pt = 1e-2 * synth.random_ptilde(w.nh, w.nz, w.nx, 1)
+    out = {}
+    t = time.perf_counter()
+    d = oracle.model(g, w.vel, geo)
+    out["model_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.born_ext_fwd(g, w.vel, geo, pt)
+    out["born_ext_fwd_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.born_ext_adj(g, w.vel, geo, d, w.nh)
+    out["born_ext_adj_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.gradient(g, w.vel, geo, pt, 0.9 * d, 1e-3, synth.dso_weights(w.nh))
+    out["gradient_s"] = time.perf_counter() - t
+    cells = (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
+    total = sum(out.values())
+    out["cell_updates_per_s"] = sum(PROPAGATIONS.values()) * cells / total
+    return out
+
+
+def _cpu_task(spec):
+    if spec[0] == "plain_small":
+        return _cpu_plain_small_task()
+    return _cpu_model_task(*spec)
+
+
+def cpu_host():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "model": model}
+
+
+class CpuBaseline:
+    """Starts the oracle runs in a pool of spawned worker processes."""
+
+    def __init__(self, step_cells):
+        import multiprocessing as mp
+        self.workers = max(2, min(os.cpu_count() or 2, 16) - 2)
+        nb = self.workers - 1                      # one worker runs the 100 x 200 four-operator set
+        # headline sample: the first nb shots of the 256-shot set, each for
+        # about 1.5e8 padded cell-updates (a few hundred time steps)
+        self.batch_specs = [("batch", i, max(20, int(1.5e8 / step_cells[i]))) for i in range(nb)]
+        # Marmousi-like modeling, shot-parallel: nb shots, 60 steps each
+        self.marm_specs = [("marmousi", i, 60) for i in range(nb)]
+        specs = [("plain_small",)] + self.batch_specs + self.marm_specs
+        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+        for k in saved:
+            os.environ[k] = "1"
+        try:
+            self.pool = mp.get_context("spawn").Pool(self.workers)
+            self.t0 = time.perf_counter()
+            self.res = self.pool.map_async(_cpu_task, specs, chunksize=1)
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+
+    def result(self, timeout: float):
+        try:
+            out = self.res.get(timeout=max(1.0, timeout))
+        except Exception as e:       # timeout or a worker error: report, do not fail the bench
+            self.pool.terminate()
+            return {"skipped": f"cpu baseline did not finish: {type(e).__name__}"}
+        self.pool.close()
+        small, rest = out[0], out[1:]
+        batch = [r for r in rest if r["kind"] == "batch"]
+        marm = [r for r in rest if r["kind"] == "marmousi"]
+        # headline sample: shots run concurrently, one per process
+        b_cells = sum(r["cells"] for r in batch)
+        b_wall = max(r["s"] for r in batch)
+        m_rate = sum(r["cells"] / r["s"] for r in marm)
+        m_full = 100 * marm[0]["full_cells"]
+        return {
+            "value": b_cells / b_wall, "unit": "cell-updates/s", "cores": len(batch), "kind": "oracle",
+            "sample": f"oracle.model (NumPy FP64, one thread per process) on the first {len(batch)} shots of "
+                      f"the 256-shot uneven-grid set, {len(batch)} processes at once, each shot for its first "
+                      f"{min(r['steps'] for r in batch)}-{max(r['steps'] for r in batch)} time steps "
+                      f"({b_cells:.3g} padded cell-updates in {b_wall:.1f} s); run beside the GPU sections, "
+                      f"after the timed steps",
+            "host": cpu_host(),
+            "plain_100x200_four_ops_one_core": small,
+            "marmousi_model_shot_parallel": {
+                "processes": len(marm), "steps_per_shot": marm[0]["steps"],
+                "cell_updates_per_s": m_rate,
+                "extrapolated_100_shots_s": m_full / m_rate,
+                "note": "extrapolated from the first 60 steps of one shot per process to 100 shots x 5000 "
+                        "steps at the same rate"},
+        }
+
+
+# ----------------------------------------------------------------------------
+# GPU sections
+# ----------------------------------------------------------------------------
 
 def stencil_source_hash() -> str:
-    """Hash of the sources that define the dominant stencil kernel."""
-    names = ["kernels_step2.hip", "internal.h"] if two_step() else ["kernels_step.hip", "internal.h"]
     h = hashlib.sha256()
-    for n in names:
+    for n in ("kernels_step2.hip", "internal.h"):
         h.update(open(os.path.join(CSRC, n), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(nshots: int, nt: int):
-    """HBM bytes per stencil launch from the committed counter runs, or None
-    when those counters were taken on another version of the kernel or
-    another launch shape."""
+def measured_traffic(launches: int):
+    """HBM bytes per stencil launch of the headline from the committed counter
+    runs, or None when those were taken on another kernel version or shape."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha") != stencil_source_hash() or rec.get("shots_per_launch") != nshots:
+    if rec.get("kernel_source_sha") != stencil_source_hash() or rec.get("launches_per_call") != launches:
         return None
     return rec.get("bytes_per_launch")
 
@@ -82,45 +219,12 @@ def copy_calibration(nbytes: int, reps: int):
                       "GB_per_s": 2 * n * 4 / dt / 1e9}), flush=True)
 
 
-def make_workload(name: str, nshots: int | None):
-    import synth
-    if name == "marmousi":
-        w = synth.marmousi_set(100 if nshots is None else nshots)
-    elif name == "plain-small":
-        w = synth.plain_small()
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return w
-
-
-def cpu_baseline(w, steps: int):
-    """The FP64 oracle on a bounded sample: one shot, the first `steps` time steps."""
-    import numpy as np
-    import oracle
-    import synth
-    sub = w.subset([0])
-    g = oracle.Grid(sub.nz, sub.nx, sub.nb, steps, sub.dz, sub.dx, sub.dt, sub.sponge_alpha)
-    geo = oracle.Geometry(sub.src_iz, sub.src_ix, sub.rec_iz, sub.rec_ix, sub.wavelet[:, :steps].copy())
-    t = time.perf_counter()
-    oracle.model(g, sub.vel, geo)
-    dt = time.perf_counter() - t
-    cells = (sub.nz + 2 * sub.nb) * (sub.nx + 2 * sub.nb) * (steps - 1)
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle.model, 1 shot of the {sub.nz}x{sub.nx} workload, first {steps} time steps "
-                      f"({cells:.3g} padded cell-updates in {dt:.1f} s, NumPy FP64, one thread)"}
-
-
-def batch_compare(ctx, nshots: int = 256):
-    """256 shots on three grid sizes (200x600, 300x1700, 500x2500), nt 3000-6000:
-    one fwime_model_batch call (all shots per launch, graph-replayed, autotuned
-    tile width) against the plain path, one fwime_model call per shot."""
+def batch_jobs(nshots: int = 256):
     import torch
     import paper_2206_02362_amd as fw
     import synth
     ws = synth.batch_set(nshots)
-    vels = {}
-    jobs = []
-    cells = 0
+    vels, jobs, cells = {}, [], []
     for w in ws:
         k = w.extra["size"]
         if k not in vels:
@@ -130,35 +234,32 @@ def batch_compare(ctx, nshots: int = 256):
                           torch.tensor(w.wavelet, dtype=torch.float32, device="cuda:0"))
         data = torch.empty((1, w.nrec, w.nt), device="cuda:0")
         jobs.append((grid, vels[k], geo, data))
-        cells += (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
-    log(f"batch compare: {len(jobs)} jobs, {cells:.3g} cell-updates")
-    ctx.fwime_model_batch(jobs)          # first call tunes the tile width
+        cells.append((w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1))
+    return ws, jobs, cells
+
+
+def plain_compare(ctx, jobs, cells, batched_s):
+    import torch
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    ctx.fwime_model_batch(jobs)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t
-    log(f"batched: {tb:.2f} s")
     t = time.perf_counter()
     for grid, vel, geo, data in jobs:
         ctx.fwime_model(grid, vel, geo, data)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t
-    log(f"plain: {tp:.2f} s")
-    return {"workload": f"{len(jobs)} shots on 200x600 / 300x1700 / 500x2500 grids (40-cell strip), "
-                        f"nt 3000-6000, Ricker 6-12 Hz, modeling",
-            "cell_updates": cells, "batched_s": tb, "plain_s": tp,
-            "batched_cell_updates_per_s": cells / tb, "plain_cell_updates_per_s": cells / tp,
-            "speedup": tp / tb, "tile_x": ctx.info()["last_batch_tile_x"]}
+    c = float(sum(cells))
+    return {"plain_s": tp, "batched_s": batched_s, "plain_cell_updates_per_s": c / tp,
+            "batched_cell_updates_per_s": c / batched_s, "speedup": tp / batched_s,
+            "note": "plain = one fwime_model call per shot (one shot per launch, two time steps per launch); "
+                    "batched = the headline step (all 256 shots in shared launches)"}
 
 
 def serve_compare(nreq: int, seed: int = 42, slots: int = 3):
-    """A seeded Poisson stream (mean 20 requests/s) of modeling 40 %, extended
-    Born 30 % (half forward, half adjoint) and gradient 30 % requests on grids
-    from 200x600 to 600x3000 (10 m, 40-cell strip), 1-32 shots, nt 2000-6000,
-    11 offsets, over six resident models: the request loop (`slots` streams,
-    footprint admission, merged modeling) against plain first-come-first-served
-    (one request at a time, one context, no merging)."""
+    """The first nreq requests of the seeded Poisson stream (mean 20 requests/s;
+    modeling 40 %, extended Born 30 % half forward half adjoint, gradient 30 %;
+    grids 200x600 .. 600x3000 at 10 m; 1-32 shots; nt 2000-6000; 11 offsets;
+    six resident models), through the request loop (`slots` streams,
+    footprint admission, continuous batching of modeling requests) and through
+    one-at-a-time FIFO on one context."""
     import torch
     import synth
     import paper_2206_02362_amd as fw
@@ -179,7 +280,8 @@ def serve_compare(nreq: int, seed: int = 42, slots: int = 3):
 
     arrivals = [s.arrival for s in mix.requests]
     res = {}
-    for name, kw in (("plain_fifo", dict(slots=1, merge_models=1)), ("served", dict(slots=slots, merge_models=8))):
+    for name, kw in (("plain_fifo", dict(slots=1, merge_models=1, engine=False)),
+                     ("served", dict(slots=slots, engine=True))):
         srv = Server(0, **kw)
         reqs = requests(srv)
         torch.cuda.synchronize()
@@ -194,40 +296,155 @@ def serve_compare(nreq: int, seed: int = 42, slots: int = 3):
         st["budget_bytes"] = srv.budget
         res[name] = st
         log(f"  {name}: p50 {st['p50_s']:.2f} s, p99 {st['p99_s']:.2f} s, makespan {st['makespan_s']:.2f} s")
-        for s_ in srv.slots:
-            s_.ctx.close()
+        srv.close()
         del srv, reqs, done
         torch.cuda.empty_cache()
     kinds = {}
     for s_ in mix.requests:
         kinds[s_.kind] = kinds.get(s_.kind, 0) + 1
-    return {"workload": f"{nreq} requests, Poisson 20/s (seed {seed}), kinds {kinds}, grids 200x600..600x3000, "
-                        f"1-32 shots, nt 2000-6000, nh {mix.nh}, {len(mix.pool)} resident models",
-            "slots": slots, **res,
+    return {"workload": f"first {nreq} requests of a Poisson stream at 20/s (seed {seed}), kinds {kinds}, grids "
+                        f"200x600..600x3000, 1-32 shots, nt 2000-6000, nh {mix.nh}, {len(mix.pool)} resident models",
+            "arrival_span_s": arrivals[-1], "samples": nreq, "slots": slots, **res,
             "throughput_speedup": res["served"]["cell_updates_per_s"] / res["plain_fifo"]["cell_updates_per_s"],
-            "p99_ratio_served_over_plain": res["served"]["p99_s"] / res["plain_fifo"]["p99_s"]}
+            "p50_ratio_served_over_plain": res["served"]["p50_s"] / res["plain_fifo"]["p50_s"],
+            "p99_ratio_served_over_plain": res["served"]["p99_s"] / res["plain_fifo"]["p99_s"],
+            "note": "with fewer than 100 samples p99 is close to the maximum latency"}
+
+
+def serve_estimate_s(nreq: int, rate: float = 1.5e11) -> float:
+    """Rough GPU seconds of the served + FIFO replays of the first nreq requests."""
+    import synth
+    from paper_2206_02362_amd.serve import PROPAGATIONS as SP
+    mix = synth.serve_mix(nreq=nreq, seed=42, velocities=False)
+    cells = 0.0
+    for s in mix.requests:
+        nz, nx, _ = mix.pool[s.model]
+        extra = {"model": 1.0, "born_fwd": 1.0, "born_adj": 1.5, "gradient": 1.4}[s.kind]
+        cells += extra * SP[s.kind] * len(s.src_ix) * (nz + 2 * mix.nb) * (nx + 2 * mix.nb) * (s.nt - 1)
+    return 2.0 * cells / rate + 5.0
+
+
+def marmousi_pass(ctx):
+    import torch
+    import paper_2206_02362_amd as fw
+    import synth
+    w = synth.marmousi_set(100)
+    dev = "cuda:0"
+    grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
+    vel = torch.tensor(w.vel, dtype=torch.float32, device=dev)
+    geo = fw.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix, torch.tensor(w.wavelet, dtype=torch.float32, device=dev))
+    vtrue = torch.tensor(w.vel * (1.0 + 0.03 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 77, 300.0)),
+                         dtype=torch.float32, device=dev)
+    ptilde = torch.tensor(1e-2 * synth.random_ptilde(w.nh, w.nz, w.nx, 78), dtype=torch.float32, device=dev)
+    dso = synth.dso_weights(w.nh)
+    dobs = ctx.model(grid, vtrue, geo)
+    torch.cuda.synchronize()
+    times = {}
+    for name, call in (("model", lambda: ctx.model(grid, vel, geo)),
+                       ("born_ext_fwd", lambda: ctx.born_ext_fwd(grid, vel, geo, ptilde)),
+                       ("born_ext_adj", lambda: ctx.born_ext_adj(grid, vel, geo, dobs, w.nh)),
+                       ("gradient", lambda: ctx.gradient(grid, vel, geo, ptilde, dobs, 1e-4, dso))):
+        t = time.perf_counter()
+        out = call()
+        torch.cuda.synchronize()
+        times[name] = time.perf_counter() - t
+        del out
+    per_prop = w.nshots * (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
+    total = sum(times.values())
+    return {"workload": f"{w.name}: {w.nshots} shots, nt {w.nt}, nh {w.nh}, padded "
+                        f"{w.nz + 2 * w.nb}x{w.nx + 2 * w.nb}, one pass of each operator (first calls)",
+            "seconds": times, "total_s": total,
+            "cell_updates_per_s": sum(PROPAGATIONS.values()) * per_prop / total,
+            "note": "propagations counted as in the paper's cost analysis: modeling 1, extended Born 2, "
+                    "adjoint 2, gradient 6 per shot; checkpoint recomputations not counted"}, (grid, vel, geo, dobs, w)
+
+
+def time_lag_section(ctx, grid, vel, geo, w, nshots=8):
+    import torch
+    import paper_2206_02362_amd as fw
+    import synth
+    ctx.trim()
+    torch.cuda.empty_cache()
+    ns = min(nshots, w.nshots)
+    ntau, lag = 101, max(1, int(round(0.016 / w.dt)))
+    gsub = fw.Geometry(w.src_iz[:ns], w.src_ix[:ns], w.rec_iz[:ns], w.rec_ix[:ns], geo.wavelet[:ns].contiguous())
+    ptau = torch.tensor(1e-2 * synth.random_ptilde(ntau, w.nz, w.nx, 79), dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dtau = ctx.born_ext_tau_fwd(grid, vel, gsub, ptau, lag)
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t
+    t = time.perf_counter()
+    dtau = ctx.born_ext_tau_fwd(grid, vel, gsub, ptau, lag)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t
+    t = time.perf_counter()
+    ctx.born_ext_tau_adj(grid, vel, gsub, dtau, ntau, lag)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter() - t
+    cells = ns * (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
+    return {"workload": f"{w.name}: {ns} shots, nt {w.nt}, ntau {ntau}, lag {lag} steps ({lag * w.dt * 1e3:.0f} ms)",
+            "fwd_s": t_f, "adj_s": t_a, "fwd_first_call_s": t_cold,
+            "fwd_cell_updates_per_s": 2 * cells / t_f, "adj_cell_updates_per_s": 2 * cells / t_a,
+            "lag_terms_per_s_fwd": ntau * ns * w.nz * w.nx * (w.nt - 1) / t_f}
+
+
+def spline_section(ctx, w, reps=50):
+    import numpy as np
+    import torch
+    import synth
+    zn = np.unique(np.concatenate([np.arange(0, w.nz - 1, 10), [w.nz - 1],
+                                   np.arange(w.nz // 3 - 20, w.nz // 3 + 20, 5)]) * w.dz)
+    xn = np.unique(np.concatenate([np.arange(0, w.nx - 1, 10), [w.nx - 1]]) * w.dx)
+    mc = torch.tensor(synth.gaussian_perturbation(len(zn), len(xn), w.dx, 80, 30.0), dtype=torch.float32,
+                      device="cuda:0")
+    fine = torch.empty((w.nx, w.nz), dtype=torch.float32, device="cuda:0")
+    back = torch.empty((len(xn), len(zn)), dtype=torch.float32, device="cuda:0")
+    times = {}
+    for name, call in (("apply", lambda: ctx.fwime_spline_apply(w.nz, w.nx, w.dz, w.dx, zn, xn, mc, fine)),
+                       ("adjoint", lambda: ctx.fwime_spline_adjoint(w.nz, w.nx, w.dz, w.dx, zn, xn, fine, back))):
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) * 1e3 / reps
+    return {"workload": f"{w.nz}x{w.nx} model grid, {len(zn)}x{len(xn)} spline nodes",
+            "apply_us_per_call": times["apply"], "adjoint_us_per_call": times["adjoint"]}
+
+
+def vp_section(ctx, grid, vel, geo, dobs, w, iters=2):
+    import torch
+    import synth
+    dso = synth.dso_weights(w.nh)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, 0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
+    _, phi = ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, iters)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t
+    per_iter = (t_all - t_setup) / iters
+    per_prop = w.nshots * (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (w.nt - 1)
+    return {"iterations": iters, "s_setup": t_setup, "s_per_iteration": per_iter,
+            "cell_updates_per_s": 4 * per_prop / per_iter, "objective": [float(x) for x in phi]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="marmousi")
-    ap.add_argument("--shots", type=int, default=None)
-    ap.add_argument("--ops", default="model,born_ext_fwd,born_ext_adj,gradient")
-    ap.add_argument("--cpu-steps", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--nt", type=int, default=None, help="shorten the time axis (counter runs)")
-    ap.add_argument("--no-batch-compare", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16, help="requests in the serving replay (0: skip)")
-    ap.add_argument("--serve-only", action="store_true", help="only the serving replay")
-    ap.add_argument("--vp-iters", type=int, default=2,
-                    help="CG iterations of the variable-projection step to time (0: skip)")
-    ap.add_argument("--tau-shots", type=int, default=8,
-                    help="shots of the time-lag extended Born pair to time (0: skip)")
-    ap.add_argument("--spline-reps", type=int, default=50,
-                    help="calls of the spline operator S and its adjoint to time (0: skip)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--deadline-s", type=float, default=480.0,
+                    help="wall-clock budget from process start; optional sections past it are skipped")
+    ap.add_argument("--sections", default="roofline,plain,cpu,serving,marmousi,time_lag,spline,vp",
+                    help="comma list of the sections to run after the timed steps")
+    ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving replay (0: fit)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -237,221 +454,119 @@ def main():
               "(shots would shard across GPUs with one all-reduce of the gradients).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_2206_02362_amd as fw
-    import synth
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     if args.copy_calibration:
         copy_calibration(1 << 30, 5)
         return
-    if args.serve_only:
-        print(json.dumps({"serving": serve_compare(args.serve_requests)}), flush=True)
-        return
-    ops = [o for o in args.ops.split(",") if o]
-    w = make_workload(args.workload, args.shots)
-    if args.nt is not None:
-        w.nt = args.nt
-        w.wavelet = w.wavelet[:, :args.nt].copy()
-    log(f"workload {w.name}: {w.nshots} shots, nt {w.nt}, nh {w.nh}, padded {w.nz + 2 * w.nb}x{w.nx + 2 * w.nb}")
-    dev = "cuda:0"
+    sections = set(s for s in args.sections.split(",") if s)
+    deadline = args.deadline_s
+
+    def fits(name, est):
+        if name not in sections:
+            return False
+        left = deadline - elapsed()
+        if est > left:
+            log(f"section {name} skipped: needs about {est:.0f} s, {left:.0f} s left")
+            skipped[name] = {"skipped": "deadline", "estimate_s": est, "left_s": left}
+            return False
+        return True
+
+    skipped = {}
+    ws, jobs, cells = batch_jobs(256)
+    total_cells = float(sum(cells))
+    log(f"headline: {len(jobs)} shots on 200x600 / 300x1700 / 500x2500, {total_cells:.4g} cell-updates per step")
     ctx = fw.Context(0)
-    grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
-    vel = torch.tensor(w.vel, dtype=torch.float32, device=dev)
-    geo = fw.Geometry(w.src_iz, w.src_ix, w.rec_iz, w.rec_ix,
-                      torch.tensor(w.wavelet, dtype=torch.float32, device=dev))
-    vtrue = torch.tensor(w.vel * (1.0 + 0.03 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 77, 300.0)),
-                         dtype=torch.float32, device=dev)
-    ptilde = torch.tensor(1e-2 * synth.random_ptilde(w.nh, w.nz, w.nx, 78), dtype=torch.float32, device=dev)
-    dso = synth.dso_weights(w.nh)
-    log("setup: observed data")
-    dobs = ctx.model(grid, vtrue, geo)
-    torch.cuda.synchronize()
-
-    outs = {}
-
-    def step():
-        if "model" in ops:
-            outs["model"] = ctx.model(grid, vel, geo)
-        if "born_ext_fwd" in ops:
-            outs["born"] = ctx.born_ext_fwd(grid, vel, geo, ptilde)
-        if "born_ext_adj" in ops:
-            outs["adj"] = ctx.born_ext_adj(grid, vel, geo, dobs, w.nh)
-        if "gradient" in ops:
-            outs["grad"] = ctx.gradient(grid, vel, geo, ptilde, dobs, 1e-4, dso)
-
+    ctx.set_timing(True)
     for i in range(args.warmup):
         t = time.perf_counter()
-        step()
+        ctx.fwime_model_batch(jobs)
         torch.cuda.synchronize()
-        log(f"warmup {i}: {time.perf_counter() - t:.2f} s")
+        log(f"warmup {i}: {time.perf_counter() - t:.2f} s (tile width {ctx.info()['last_batch_tile_x']})")
+    launches, kern_ms = 0, 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step()
-        torch.cuda.synchronize()
-        log(f"step {i} done at {time.perf_counter() - t0:.2f} s")
+        ctx.fwime_model_batch(jobs)
+        inf = ctx.info()                 # waits for the call's last stencil launch
+        launches += inf["last_stencil_launches"]
+        kern_ms += inf["last_stencil_ms"]
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
+    t_steps = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_steps / args.steps
+    value = total_cells / (t_steps / args.steps)
+    log(f"timed: {args.steps} steps, {ms_per_step:.1f} ms per step, {value:.4g} cell-updates/s")
 
-    NZ, NX = w.nz + 2 * w.nb, w.nx + 2 * w.nb
-    per_prop = w.nshots * NZ * NX * (w.nt - 1)
-    nprop = sum(PROPAGATIONS[o] for o in ops)
-    value = nprop * per_prop / (elapsed / args.steps)
-
-    # Dominant kernel: the stencil.  fwime_model is ceil((nt - 1) / 2) launches
-    # of the two-step kernel (nt - 1 of the one-step kernel with FWIME_STEP1=1),
-    # all shots in one launch, plus one receiver gather; time it with events on
-    # the stream the library launches on.
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    data = torch.empty((w.nshots, w.nrec, w.nt), device=dev)
-    ctx.fwime_model(grid, vel, geo, data)      # tables and arena warm
-    torch.cuda.synchronize()
-    reps = 2
-    tev = 0.0
-    for _ in range(reps):
-        # the bracket also holds the call's validation reduction and table upload
-        e0.record(st)
-        ctx.fwime_model(grid, vel, geo, data)
-        e1.record(st)
-        e1.synchronize()
-        tev += e0.elapsed_time(e1) / 1e3
-    steps_per_launch = 2 if two_step() else 1
-    launches = (w.nt - 1 + steps_per_launch - 1) // steps_per_launch
-    per_launch = tev / reps / launches
-    step_bytes = STENCIL_BYTES * w.nshots * NZ * NX          # algorithmic bytes of one time step
-    achieved = step_bytes * (w.nt - 1) / (tev / reps)
-    kname = ("k_step2 (two stencil time steps per launch, all shots)" if steps_per_launch == 2
-             else "k_step (one stencil time step per launch, all shots)")
+    # roofline of the dominant kernel (k_step2_multi): algorithmic bytes of the
+    # timed calls over the event time of their stencil launches
+    algo_bytes = STENCIL_BYTES * total_cells * args.steps
+    per_launch_us = 1e3 * kern_ms / launches
+    achieved = algo_bytes / (kern_ms / 1e3)
+    lpc = launches // args.steps
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": measured_traffic(w.nshots, w.nt),
+                "frac": achieved / PEAK_HBM, "traffic": measured_traffic(lpc),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": kname, "steps_per_launch": steps_per_launch,
-                "bytes_per_launch": step_bytes * steps_per_launch, "avg_launch_us": per_launch * 1e6}
-    log(f"stencil: {per_launch * 1e6:.1f} us per launch ({steps_per_launch} steps), "
-        f"{achieved / 1e9:.0f} GB/s algorithmic")
+                "kernel": f"k_step2_multi<{ctx.info()['last_batch_tile_x']}> (two stencil time steps per launch, "
+                          f"all active shots of all grids)",
+                "launches_per_call": lpc, "avg_launch_us": per_launch_us,
+                "bytes_per_launch": algo_bytes / launches,
+                "stencil_share_of_step": kern_ms / (1e3 * t_steps)}
+    log(f"stencil: {per_launch_us:.1f} us per launch, {achieved / 1e9:.0f} GB/s algorithmic "
+        f"({roofline['frac']:.3f} of 8 TB/s)")
 
-    batch = None
-    if not args.no_batch_compare:
-        batch = batch_compare(ctx)
-
-    vp = None
-    if args.vp_iters > 0:
-        # variable-projection step (eq. vp.obj): model + B~* once, then B~ and
-        # B~* per CG iteration; timed as a whole and per iteration
-        outs.clear()
-        log(f"variable-projection step: {args.vp_iters} CG iterations")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, phi = ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, 0)
-        torch.cuda.synchronize()
-        t_setup = time.perf_counter() - t
-        t = time.perf_counter()
-        _, phi = ctx.vp_solve(grid, vel, geo, dobs, w.nh, 0.0, dso, args.vp_iters)
-        torch.cuda.synchronize()
-        t_all = time.perf_counter() - t
-        per_iter = (t_all - t_setup) / args.vp_iters
-        vp = {"iterations": args.vp_iters, "eps": 0.0, "s_total": t_all, "s_setup": t_setup,
-              "s_per_iteration": per_iter,
-              "cell_updates_per_s": 4 * per_prop / per_iter,
-              "note": "setup = f(m) and B~* once (3 propagations/shot); each CG iteration = B~ + B~* "
-                      "(4 propagations/shot counted)",
-              "objective": [float(x) for x in phi]}
-        log(f"vp: {per_iter:.2f} s per CG iteration, objective {vp['objective']}")
-
-    tau = None
-    if args.tau_shots > 0 and max(1, int(round(0.016 / w.dt))) * 100 > 4 * w.nt:
-        log("time-lag extension skipped: the record is too short for 101 lags of 16 ms")
-    elif args.tau_shots > 0:
-        # extended Born with time lags: 101 lags of 16 ms (the paper's Marmousi2
-        # setting) on the first shots of the workload; each shot's background
-        # history is about 2 nt padded fields, so only a few shots fit at once;
-        # the context's arena and solver buffers are released first, or the
-        # batches shrink to a shot or two
-        outs.clear()
-        ctx.trim()
-        torch.cuda.empty_cache()
-        ns_tau = min(args.tau_shots, w.nshots)
-        ntau, lag = 101, max(1, int(round(0.016 / w.dt)))
-        gsub = fw.Geometry(w.src_iz[:ns_tau], w.src_ix[:ns_tau], w.rec_iz[:ns_tau], w.rec_ix[:ns_tau],
-                           geo.wavelet[:ns_tau].contiguous())
-        ptau = torch.tensor(1e-2 * synth.random_ptilde(ntau, w.nz, w.nx, 79), dtype=torch.float32, device=dev)
-        log(f"time-lag extension: {ns_tau} shots, ntau {ntau}, lag {lag} steps")
-        # one untimed call grows the context's arena to the histories' size
-        # (after the larger earlier sections that first allocation alone takes
-        # seconds), as the other sections time warm calls
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        dtau = ctx.born_ext_tau_fwd(grid, vel, gsub, ptau, lag)
-        torch.cuda.synchronize()
-        t_cold = time.perf_counter() - t
-        t = time.perf_counter()
-        dtau = ctx.born_ext_tau_fwd(grid, vel, gsub, ptau, lag)
-        torch.cuda.synchronize()
-        t_f = time.perf_counter() - t
-        t = time.perf_counter()
-        img = ctx.born_ext_tau_adj(grid, vel, gsub, dtau, ntau, lag)
-        torch.cuda.synchronize()
-        t_a = time.perf_counter() - t
-        cells = ns_tau * NZ * NX * (w.nt - 1)
-        tau = {"workload": f"{w.name}: {ns_tau} shots, nt {w.nt}, ntau {ntau}, lag {lag} steps "
-                           f"({lag * w.dt * 1e3:.0f} ms)",
-               "fwd_s": t_f, "adj_s": t_a, "fwd_first_call_s": t_cold,
-               "fwd_cell_updates_per_s": 2 * cells / t_f, "adj_cell_updates_per_s": 2 * cells / t_a,
-               "lag_terms_per_s_fwd": ntau * ns_tau * w.nz * w.nx * (w.nt - 1) / t_f,
-               "note": "two propagations per shot counted per operator; lag terms = ntau multiply-adds "
-                       "per model cell and step"}
-        log(f"time lag: forward {t_f:.2f} s (first call {t_cold:.2f} s), adjoint {t_a:.2f} s")
-        del dtau, img, ptau
-
-    spline = None
-    if args.spline_reps > 0:
-        # S and S* on the model grid, nodes every 10 cells plus a refined band
-        # of 5-cell spacing around an interface at a third of the depth
-        zn = np.unique(np.concatenate([np.arange(0, w.nz - 1, 10), [w.nz - 1],
-                                       np.arange(w.nz // 3 - 20, w.nz // 3 + 20, 5)]) * w.dz)
-        xn = np.unique(np.concatenate([np.arange(0, w.nx - 1, 10), [w.nx - 1]]) * w.dx)
-        mc = torch.tensor(synth.gaussian_perturbation(len(zn), len(xn), w.dx, 80, 30.0), dtype=torch.float32,
-                          device=dev)
-        fine = torch.empty((w.nx, w.nz), dtype=torch.float32, device=dev)
-        back = torch.empty((len(xn), len(zn)), dtype=torch.float32, device=dev)
-        times = {}
-        for name, call in (("apply", lambda: ctx.fwime_spline_apply(w.nz, w.nx, w.dz, w.dx, zn, xn, mc, fine)),
-                           ("adjoint", lambda: ctx.fwime_spline_adjoint(w.nz, w.nx, w.dz, w.dx, zn, xn, fine,
-                                                                        back))):
-            call()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.spline_reps):
-                call()
-            e1.record()
-            torch.cuda.synchronize()
-            times[name] = e0.elapsed_time(e1) * 1e3 / args.spline_reps
-        spline = {"workload": f"{w.nz}x{w.nx} model grid, {len(zn)}x{len(xn)} spline nodes",
-                  "apply_us_per_call": times["apply"], "adjoint_us_per_call": times["adjoint"],
-                  "note": "whole calls (node upload with one stream synchronization, axis tables, "
-                          "interpolation); per-kernel times in the rocprofv3 summary"}
-        log(f"spline: apply {times['apply']:.1f} us, adjoint {times['adjoint']:.1f} us per call")
-        del fine, back, mc
-
-    serving = None
-    if args.serve_requests > 0:
-        # give the device memory of the step back to the server's budget
-        outs.clear()
-        del data
-        ctx.trim()
-        torch.cuda.empty_cache()
-        serving = serve_compare(args.serve_requests)
-
+    plain = serving = marm = tau = spline = vp = None
     cpu = None
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle, {args.cpu_steps} steps")
-        cpu = cpu_baseline(w, args.cpu_steps)
+    if fits("plain", 2.6 * t_steps / args.steps + 5):
+        plain = plain_compare(ctx, jobs, cells, t_steps / args.steps)
+        log(f"plain: {plain['plain_s']:.2f} s, batched {plain['speedup']:.2f}x faster")
+    del jobs
+    ctx.trim()
+    torch.cuda.empty_cache()
+
+    cpu_job = None
+    if "cpu" in sections and deadline - elapsed() > 60:
+        cpu_job = CpuBaseline([(w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) for w in ws])
+        log(f"cpu baseline started in {cpu_job.workers} worker processes")
+
+    if "serving" in sections:
+        n = args.serve_requests
+        if n <= 0:
+            n = 0
+            for cand in (96, 80, 64, 48, 40, 32, 24, 16):
+                if serve_estimate_s(cand) < 0.5 * (deadline - elapsed() - 30):
+                    n = cand
+                    break
+        if n and fits("serving", serve_estimate_s(n)):
+            serving = serve_compare(n)
+        elif not n:
+            skipped["serving"] = {"skipped": "deadline"}
+
+    marm_ctx = None
+    if fits("marmousi", 45):
+        marm, marm_ctx = marmousi_pass(ctx)
+        log(f"marmousi four-operator pass: {marm['total_s']:.1f} s")
+    if marm_ctx is not None:
+        grid, vel, geo, dobs, w = marm_ctx
+        if fits("time_lag", 15):
+            tau = time_lag_section(ctx, grid, vel, geo, w)
+            log(f"time lag: forward {tau['fwd_s']:.2f} s, adjoint {tau['adj_s']:.2f} s")
+        if fits("spline", 3):
+            spline = spline_section(ctx, w)
+        if fits("vp", 45):
+            ctx.trim()
+            torch.cuda.empty_cache()
+            vp = vp_section(ctx, grid, vel, geo, dobs, w)
+            log(f"vp: {vp['s_per_iteration']:.2f} s per CG iteration")
+        del marm_ctx, grid, vel, geo, dobs
+
+    if cpu_job is not None:
+        cpu = cpu_job.result(deadline + 60 - elapsed())
+        log(f"cpu baseline: {cpu.get('value', 0):.4g} cell-updates/s")
+    elif "cpu" in sections:
+        cpu = {"skipped": "deadline"}
 
     rec = {
         "metric": "cell-updates/s",
@@ -466,17 +581,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.nshots} shots, nt {w.nt}, nh {w.nh}, padded {NZ}x{NX}, "
-                               f"ops {'+'.join(ops)} ({nprop} propagations/shot counted)",
-                   "nshots": w.nshots, "nt": w.nt, "nh": w.nh, "padded_cells": NZ * NX,
-                   "model_cells": w.nz * w.nx},
+        "config": {"workload": "batch-256: 256 modeling shots on uneven grids (200x600, 300x1700, 500x2500 at "
+                               "10 m, 40-cell strip), nt 3000-6000, Ricker 6-12 Hz, one fwime_model_batch call "
+                               "per step",
+                   "nshots": 256, "cell_updates_per_step": total_cells},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "batched_vs_plain": batch,
-        "vp_step": vp,
+        "batched_vs_plain": plain,
+        "serving": serving,
+        "marmousi_four_ops": marm,
         "time_lag": tau,
         "spline": spline,
-        "serving": serving,
+        "vp_step": vp,
+        "skipped": skipped or None,
+        "wall_s": elapsed(),
     }
     print(json.dumps(rec), flush=True)
 

@@ -67,7 +67,17 @@ typedef struct {
   int32_t nt;          /* time samples (>= 2)                            */
   double dz, dx, dt;   /* m, m, s                                        */
   double sponge_alpha; /* taper strength (0 disables the taper)          */
+  int32_t free_surface; /* nonzero: free surface on the model's first row */
 } fwime_grid_t;
+/* Free surface (the free-surface-multiples variant of the Marmousi2 test in
+ * Section 3 models with a free surface at the water surface and absorbing
+ * boundaries elsewhere, after Robertsson's image method): the pressure is
+ * zero on the model's first row (padded row nb) and above it, and the
+ * Laplacian of the rows below reads the field mirrored with opposite sign,
+ * u(nb - k) = -u(nb + k).  The top strip is then unused; it needs nb >= 4
+ * (FWIME_EINVAL otherwise).  Every operator honours it: all of them step the
+ * same stencil, and the mirrored operator stays symmetric, so adjoints and
+ * gradients carry over unchanged. */
 
 /* Acquisition: nshots shots sharing the grid and velocity model. */
 typedef struct {
@@ -141,6 +151,19 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                    const float *dobs, double eps, const double *dso,
                    double *obj, float *grad_vel, float *grad_ptilde, void *stream);
 
+/* The same objective and gradients with B~ extended by time lags (Section 2
+ * names both extensions; the paper's Marmousi2 test uses 101 lags of 16 ms):
+ * ntau lags of `lag` steps as in fwime_born_ext_tau_fwd.  The tomographic
+ * part spreads the adjoint field over the lags, e_m = sum_k c_k lambda_{m+2k lag}
+ * with c_k = 2 ptau_k / (v^3 dt^2), and g_3 takes the lag image in place of
+ * the offset image.  dso: HOST double [ntau]; ptau, grad_ptau: DEVICE
+ * [ntau][nx][nz]; others as for fwime_gradient.  Every history of a shot
+ * batch is kept whole: about 4 (nt + 1) + 80 padded fields per shot. */
+int fwime_gradient_tau(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, int32_t ntau, int32_t lag, const float *ptau,
+                       const float *dobs, double eps, const double *dso,
+                       double *obj, float *grad_vel, float *grad_ptau, void *stream);
+
 /* Variable-projection step of FWIME (Section 2, eqs. vp.obj, pert.opt and
  * vp.pseudo.inv): niter iterations of linear conjugate gradient on the normal
  * equation (B~* B~ + eps^2 D* D) p~ = B~* (dobs - f(m)), starting from p~ = 0,
@@ -195,6 +218,45 @@ typedef struct {
 
 int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, void *stream);
 
+/* ---- Continuous batching of modeling jobs (request loops) ---------------
+ * An engine runs modeling jobs in shared launches while jobs come and go:
+ * a submitted job joins at the next round, every round advances all joined
+ * jobs by steps_per_round time steps with one two-step launch per two steps
+ * over the tiles of all of them (each job at its own time index), and a job
+ * leaves once its last sample is recorded.  Each job computes exactly what
+ * fwime_model computes for it, bit for bit.  Per-job device memory (about
+ * four padded fields per shot plus tables) is allocated stream-ordered on the
+ * engine's stream at submission and released the same way after the job's
+ * last round.  The job's vel, wavelet and data stay owned by the caller and
+ * must stay valid until fwime_engine_poll reports the job done.
+ * All engine calls come from one host thread. */
+typedef struct fwime_engine fwime_engine_t;
+typedef struct {
+  int32_t pending;     /* submitted, not yet joined              */
+  int32_t active;      /* in the time loop                       */
+  int32_t finishing;   /* last round enqueued, not yet completed */
+  int64_t step;        /* global step counter                    */
+  int64_t rounds, launches;
+} fwime_engine_info_t;
+
+/* steps_per_round: even, >= 2; max_jobs: jobs held at once (pending +
+ * active); stream: the engine's stream, used by every later engine call. */
+int fwime_engine_create(fwime_ctx_t *ctx, int32_t steps_per_round, int32_t max_jobs, void *stream,
+                        fwime_engine_t **out);
+/* Validates the job (one device reduction and a synchronization of
+ * check_stream, the stream on which its inputs were written: not the engine's
+ * stream, whose rounds keep running), prepares it on the engine's stream and
+ * queues it for the next round.  *ticket identifies it in fwime_engine_poll. */
+int fwime_engine_submit(fwime_engine_t *e, const fwime_job_t *job, void *check_stream, int64_t *ticket);
+/* Enqueues one round on the engine's stream (nothing when no job is joined). */
+int fwime_engine_run(fwime_engine_t *e);
+/* Reports up to cap jobs whose data is complete (*ndone of them, in tickets)
+ * and releases them; does not block. */
+int fwime_engine_poll(fwime_engine_t *e, int64_t *tickets, int32_t cap, int32_t *ndone);
+int fwime_engine_info(const fwime_engine_t *e, fwime_engine_info_t *out);
+/* Waits for the engine's stream and releases everything it holds. */
+void fwime_engine_destroy(fwime_engine_t *e);
+
 /* Context state, for schedulers and tests. */
 typedef struct {
   size_t arena_bytes;        /* scratch arena currently held            */
@@ -202,9 +264,20 @@ typedef struct {
   int32_t tile_x;            /* default stencil tile width               */
   int32_t last_batch_tile_x; /* width used by the last fwime_model_batch */
   int32_t tuned_signatures;  /* batch shapes with a tuned width          */
+  int64_t last_stencil_launches; /* stencil launches of the last timed call, -1 if none */
+  double last_stencil_ms;    /* event time of those launches, ms         */
 } fwime_info_t;
 
+/* With timing on, the last fwime_model / fwime_model_batch call's stencil
+ * launch loop is bracketed by two HIP events recorded on the call's stream;
+ * this call then waits for the second event and reports the elapsed time
+ * and the number of stencil launches (a launch advances every active shot
+ * by one or two time steps).  Without timing, last_stencil_launches is -1. */
 int fwime_ctx_info(const fwime_ctx_t *ctx, fwime_info_t *out);
+
+/* Turn the event timing above on (on != 0) or off.  It adds two event
+ * records per modeling call and nothing to the kernels. */
+int fwime_ctx_set_timing(fwime_ctx_t *ctx, int32_t on);
 
 /* Release the context's scratch arena after `stream` (its stream) is idle.
  * The next call allocates again.  For schedulers that share one HBM budget

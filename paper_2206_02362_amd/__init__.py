@@ -17,6 +17,7 @@ from ._abi import (  # noqa: F401
     FWIME_OP_MODEL,
     LIB_PATH,
     Context,
+    Engine,
     FwimeError,
     Geometry,
     Grid,

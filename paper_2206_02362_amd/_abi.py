@@ -24,9 +24,11 @@ FWIME_ENONFINITE = 4
 
 FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 2, 3
 
-EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_trim", "fwime_footprint",
+EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_set_timing", "fwime_ctx_trim",
+            "fwime_footprint",
             "fwime_model", "fwime_born_ext_fwd",
-            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_spline_refine", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_forward_tape",
+            "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_gradient_tau", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_spline_refine", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_engine_create", "fwime_engine_submit", "fwime_engine_run", "fwime_engine_poll",
+            "fwime_engine_info", "fwime_engine_destroy", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
 
 
@@ -45,7 +47,7 @@ class FwimeError(RuntimeError):
 class _Grid(ctypes.Structure):
     _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32), ("nb", ctypes.c_int32), ("nt", ctypes.c_int32),
                 ("dz", ctypes.c_double), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
-                ("sponge_alpha", ctypes.c_double)]
+                ("sponge_alpha", ctypes.c_double), ("free_surface", ctypes.c_int32)]
 
 
 class _Geom(ctypes.Structure):
@@ -59,9 +61,15 @@ class _Job(ctypes.Structure):
     _fields_ = [("grid", _Grid), ("vel", ctypes.c_void_p), ("geom", _Geom), ("data", ctypes.c_void_p)]
 
 
+class _EngineInfo(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("finishing", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("tape_bytes", ctypes.c_size_t), ("tile_x", ctypes.c_int32),
-                ("last_batch_tile_x", ctypes.c_int32), ("tuned_signatures", ctypes.c_int32)]
+                ("last_batch_tile_x", ctypes.c_int32), ("tuned_signatures", ctypes.c_int32),
+                ("last_stencil_launches", ctypes.c_int64), ("last_stencil_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -91,6 +99,8 @@ def load() -> ctypes.CDLL:
     lib.fwime_born_ext_tau_adj.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.fwime_born_ext_tau_adj.restype = I
     lib.fwime_gradient.argtypes = [P, P, P, P, ctypes.c_int32, P, P, D, P, P, P, P, P]
+    lib.fwime_gradient_tau.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, D, P, P, P, P, P]
+    lib.fwime_gradient_tau.restype = I
     lib.fwime_vp_solve.restype = I
     lib.fwime_vp_solve.argtypes = [P, P, P, P, ctypes.c_int32, P, D, P, ctypes.c_int32, P, P, P]
     lib.fwime_vp_solve_tau.restype = I
@@ -110,8 +120,22 @@ def load() -> ctypes.CDLL:
         fn.restype = I
     lib.fwime_model_batch.argtypes = [P, ctypes.c_int32, P, P]
     lib.fwime_model_batch.restype = I
+    lib.fwime_engine_create.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)]
+    lib.fwime_engine_create.restype = I
+    lib.fwime_engine_submit.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int64)]
+    lib.fwime_engine_submit.restype = I
+    lib.fwime_engine_run.argtypes = [P]
+    lib.fwime_engine_run.restype = I
+    lib.fwime_engine_poll.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.fwime_engine_poll.restype = I
+    lib.fwime_engine_info.argtypes = [P, P]
+    lib.fwime_engine_info.restype = I
+    lib.fwime_engine_destroy.argtypes = [P]
+    lib.fwime_engine_destroy.restype = None
     lib.fwime_ctx_info.argtypes = [P, P]
     lib.fwime_ctx_info.restype = I
+    lib.fwime_ctx_set_timing.argtypes = [P, ctypes.c_int32]
+    lib.fwime_ctx_set_timing.restype = I
     lib.fwime_ctx_trim.argtypes = [P, P]
     lib.fwime_ctx_trim.restype = I
     lib.fwime_footprint.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -142,9 +166,11 @@ class Grid:
     dx: float
     dt: float
     sponge_alpha: float = 0.3
+    free_surface: bool = False
 
     def _c(self) -> _Grid:
-        return _Grid(self.nz, self.nx, self.nb, self.nt, self.dz, self.dx, self.dt, self.sponge_alpha)
+        return _Grid(self.nz, self.nx, self.nb, self.nt, self.dz, self.dx, self.dt, self.sponge_alpha,
+                     1 if self.free_surface else 0)
 
 
 class Geometry:
@@ -273,6 +299,21 @@ class Context:
             float(eps), dso.ctypes.data, obj.data_ptr(), _dptr(grad_vel, (grid.nx, grid.nz)),
             _dptr(grad_ptilde, (nh, grid.nx, grid.nz)), _stream(vel.device)))
 
+    def fwime_gradient_tau(self, grid: Grid, vel, geom: Geometry, ntau: int, lag: int, ptau, dobs, eps: float,
+                           dso, obj, grad_vel, grad_ptau):
+        g = grid._c()
+        ge = geom._c()
+        dso = np.ascontiguousarray(dso, dtype=np.float64)
+        if dso.shape != (ntau,):
+            raise ValueError("dso must have ntau entries")
+        if not (isinstance(obj, torch.Tensor) and obj.is_cuda and obj.dtype == torch.float64 and obj.numel() == 1):
+            raise TypeError("obj must be a 1-element float64 CUDA tensor")
+        self._check(self._lib.fwime_gradient_tau(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge), int(ntau), int(lag),
+            _dptr(ptau, (ntau, grid.nx, grid.nz)), _dptr(dobs, (geom.nshots, geom.nrec, grid.nt)),
+            float(eps), dso.ctypes.data, obj.data_ptr(), _dptr(grad_vel, (grid.nx, grid.nz)),
+            _dptr(grad_ptau, (ntau, grid.nx, grid.nz)), _stream(vel.device)))
+
     def fwime_vp_solve(self, grid: Grid, vel, geom: Geometry, nh: int, dobs, eps: float, dso, niter: int,
                        ptilde_out):
         """Variable-projection step; returns the objective history (niter + 1 floats)."""
@@ -308,6 +349,11 @@ class Context:
         """Release the scratch arena once this context's stream is idle."""
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         self._check(self._lib.fwime_ctx_trim(self._h, st))
+
+    def set_timing(self, on: bool = True):
+        """Bracket the stencil launch loop of each modeling call with HIP events
+        on the call's stream (read back through info())."""
+        self._check(self._lib.fwime_ctx_set_timing(self._h, 1 if on else 0))
 
     def info(self) -> dict:
         out = _Info()
@@ -371,6 +417,15 @@ class Context:
         self.fwime_gradient(grid, vel, geom, nh, ptilde, dobs, eps, dso, obj, gv, gp)
         return obj, gv, gp
 
+
+    def gradient_tau(self, grid: Grid, vel, geom: Geometry, ptau, lag: int, dobs, eps: float, dso):
+        """(objective, grad_vel, grad_ptau) of eq. fwime.obj with the time-lag extension."""
+        ntau = int(ptau.shape[0])
+        obj = torch.empty(1, device=vel.device, dtype=torch.float64)
+        gv = torch.empty((grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        gp = torch.empty((ntau, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
+        self.fwime_gradient_tau(grid, vel, geom, ntau, lag, ptau, dobs, eps, dso, obj, gv, gp)
+        return obj, gv, gp
 
     def fwime_vp_solve_tau(self, grid: Grid, vel, geom: Geometry, ntau: int, lag: int, dobs, eps: float, dso,
                            niter: int, ptau_out):
@@ -489,6 +544,68 @@ class Context:
         out = torch.empty((nh, grid.nx, grid.nz), device=vel.device, dtype=torch.float32)
         phi = self.fwime_vp_solve(grid, vel, geom, nh, dobs, eps, dso, niter, out)
         return out, phi
+
+
+class Engine:
+    """Continuous batching of modeling jobs (fwime_engine_*): jobs join a running
+    time loop at round boundaries and leave when done.  `stream` is the
+    engine's torch stream; every call comes from one host thread."""
+
+    def __init__(self, ctx: Context, stream, steps_per_round: int = 64, max_jobs: int = 256):
+        self.ctx = ctx                 # the engine's errors are reported through its context
+        self.stream = stream
+        h = ctypes.c_void_p()
+        ctx._check(ctx._lib.fwime_engine_create(ctx._h, int(steps_per_round), int(max_jobs), stream.cuda_stream,
+                                                ctypes.byref(h)))
+        self._h = h
+        self._jobs = {}                # ticket -> (job struct, geometry, data) kept alive until done
+
+    def submit(self, grid: Grid, vel, geom: Geometry, data, check_stream) -> int:
+        """Queue one modeling job writing into `data`; inputs are checked on
+        check_stream (where they were written).  Returns its ticket."""
+        job = _Job()
+        job.grid = grid._c()
+        job.vel = _dptr(vel, (grid.nx, grid.nz))
+        job.geom = geom._c()
+        job.data = _dptr(data, (geom.nshots, geom.nrec, grid.nt))
+        t = ctypes.c_int64()
+        self.ctx._check(self.ctx._lib.fwime_engine_submit(self._h, ctypes.byref(job), check_stream.cuda_stream,
+                                                          ctypes.byref(t)))
+        self._jobs[t.value] = (job, geom, vel, data)
+        return t.value
+
+    def run(self):
+        """Enqueue one round on the engine's stream."""
+        self.ctx._check(self.ctx._lib.fwime_engine_run(self._h))
+
+    def poll(self) -> list:
+        """Tickets of the jobs whose data is complete."""
+        cap = max(1, len(self._jobs))
+        buf = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        self.ctx._check(self.ctx._lib.fwime_engine_poll(self._h, ctypes.cast(buf, ctypes.c_void_p), cap,
+                                                        ctypes.byref(n)))
+        done = [int(buf[i]) for i in range(n.value)]
+        for t in done:
+            self._jobs.pop(t, None)
+        return done
+
+    def info(self) -> dict:
+        out = _EngineInfo()
+        self.ctx._check(self.ctx._lib.fwime_engine_info(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _EngineInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.ctx._lib.fwime_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Tape:

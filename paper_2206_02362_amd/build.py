@@ -32,11 +32,14 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        _run([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+    # one hipcc per translation unit, compiled concurrently
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = min(len(SOURCES), max(1, min(os.cpu_count() or 1, 16)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, [hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+                  for src, obj in zip(SOURCES, objs)]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

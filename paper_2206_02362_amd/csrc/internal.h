@@ -112,6 +112,7 @@ struct StepArgs {
   long sstride = 0;             // elements between shots in cur/prev/out
   float cz[kR] = {};            // w_k / dz^2
   float cx[kR] = {};            // w_k / dx^2
+  int fs = -1;                  // padded row of a free surface (mode kModeFS), -1: none
 };
 
 enum StepMode : int {
@@ -120,7 +121,25 @@ enum StepMode : int {
   kModeDsrc = 2,     // add a dense source field
   kModeNu = 4,       // add the e-ring second time difference as a dense source
   kModeDF = 8,       // two-step kernel only: fields carried as FP32 hi + BF16 lo
+  // Free surface on row fs (image method): the field is zero at and above
+  // row fs, and the Laplacian of the rows below reads the field mirrored with
+  // opposite sign above it, u(fs - k) = -u(fs + k).  The launch functions add
+  // this bit themselves when StepArgs::fs >= 0; with fs = -1 the FS kernels
+  // compute exactly what the plain ones do.
+  kModeFS = 16,
 };
+
+// Rows fs-kR .. fs-1 above a free surface on row fs (none when fs < 0: a job
+// without a free surface served by a free-surface multi-job launch).
+__device__ __forceinline__ bool fs_mirrored(int z, int fs) { return fs >= 0 && z >= fs - kR && z < fs; }
+
+// Row read for the stencil operand of padded row z under a free surface on
+// row fs: rows fs-kR .. fs-1 read the mirrored row 2 fs - z with opposite sign.
+__device__ __forceinline__ int fs_mirror_row(int z, int fs, float &sign) {
+  const bool m = fs_mirrored(z, fs);
+  sign = m ? -1.f : 1.f;
+  return m ? 2 * fs - z : z;
+}
 
 // One job of a multi-job launch: its step arguments (cur/prev/out are chosen
 // per step from bufA/bufB by the parity of the job's time index), the job's
@@ -156,7 +175,9 @@ struct Step2Args {
   int two = 1;
 };
 
-// mode: kModePlain, kModeT2, kModeDsrc, kModeNu, kModeDF or kModeT2 | kModeDF
+// mode: kModePlain, kModeT2, kModeDsrc, kModeT2 | kModeDsrc (a.t2 and a.dsrc in
+// distinct buffers), kModeNu, kModeDF, kModeT2 | kModeDF or kModeDsrc | kModeDF
+// (plus kModeFS, added when p.a.fs >= 0)
 hipError_t launch_step2(const Step2Args &p, int tile_x, int mode, hipStream_t st);
 
 // One job of a two-step multi-job launch: its step arguments (fields, times
@@ -170,11 +191,14 @@ struct BatchJob2 {
   int nt = 0;
 };
 
-hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int tile_x,
-                              hipStream_t st);
+// The global step is *step when `step` is non-null (a device counter that
+// graph replays advance with launch_bump), else step_val.  fs: some job has
+// a free surface (the FS kernel then serves every job of the launch).
+hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int step_val,
+                              int tile_x, bool fs, hipStream_t st);
 
-hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int tile_x,
-                             hipStream_t st);
+hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int step_val,
+                             int tile_x, bool fs, hipStream_t st);
 hipError_t launch_bump(int *step, int by, hipStream_t st);
 
 // Tile width in x of the stencil kernel (columns per workgroup).
@@ -218,14 +242,15 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
                               float *out, long out_slot, long sstride, int nshots, int nk, hipStream_t st,
                               int in_ring = 0, int in_first = 0, int out_ring = 0, int out_first = 0);
 
-// acc(z,y,h) += sum_s sum_{n<nk} a_n(z, y-h) b_n(z, y+h).  Slot n of a is a + n*a_slot;
-// slot of b is ring index (b_first + n) % b_ring.  parts: scratch for up to
-// kImageGroups partial images ([kImageGroups][nh][nx][nz]) that let the slots
-// be split over more workgroups; null keeps one group.
+// acc(z,y,h) += sum_s sum_{n<nk} a_n(z, y-h) b_n(z, y+h) (FP64 accumulator;
+// products summed in FP32 over at most 64 slots at a time).  Slot n of a is
+// a + n*a_slot; slot of b is ring index (b_first + n) % b_ring.  parts:
+// scratch for up to kImageGroups FP64 partial images ([kImageGroups][nh][nx][nz])
+// that let the slots be split over more workgroups; null keeps one group.
 constexpr int kImageGroups = 4;
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
-                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc, float *parts,
-                            hipStream_t st);
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, double *acc,
+                            double *parts, hipStream_t st);
 
 // Time-lag extension, lags tau_k = k L dt, k in [-K, K] (g.nh = 2K+1, g.H = K).
 // Slots hold one padded field per time step, slot n of shot s at
@@ -241,28 +266,39 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
                             float dt, float *acc, hipStream_t st);
 
 // gacc(x,z) += sum_s sum_{n<nk} (t2u_n + t2d_n) lam_n + t2u_n rho_n
+// (lam and rho in rings of the same shape)
 hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
                              const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
                              int nk, int NZ, int NX, int LZ, float *gacc, hipStream_t st);
+// the same with lam and rho in rings of their own shapes
+hipError_t launch_grad_accum2(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
+                              long lam_slot, long lam_sstride, int lam_ring, int lam_first, const float *rho,
+                              long rho_slot, long rho_sstride, int rho_ring, int rho_first, int nshots, int nk,
+                              int NZ, int NX, int LZ, float *gacc, hipStream_t st);
 
-// r = du + ddu - dobs (in place into du), sum r^2 ADDED to *sumsq (double)
-hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq,
+// r = du + ddu - dobs (in place into du), sum r^2 ADDED to *sumsq (double);
+// part: red_partials() doubles of scratch.  The sum is taken in a fixed order.
+hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *part, double *sumsq,
                            hipStream_t st);
+int red_partials();
+// a[0 .. n) = 0 (a kernel, usable under graph capture)
+hipError_t launch_zero_d(double *a, long n, hipStream_t st);
 
 // out = a + b (receiver data of u and du~)
 hipError_t launch_residual_sum(float *out, const float *a, const float *b, long n, hipStream_t st);
 
 // ptilde_out = 2/(v^3 dt^2) acc  (+ eps^2 d_h^2 p~ when ptilde != null)
-hipError_t launch_ext_finalize(const float *acc, const float *vel, const ExtGeom &g, float dt,
+hipError_t launch_ext_finalize(const double *acc, const float *vel, const ExtGeom &g, float dt,
                                const float *ptilde, const float *dso2eps2, float *out, hipStream_t st);
 
 // grad_vel = P^T (2/(v^3 dt^2) gacc) - 3/v sum_h p~ img   (img already scaled)
 hipError_t launch_grad_finalize(const float *gacc, const float *V, const float *vel, const ExtGeom &g,
                                 float dt, const float *ptilde, const float *img, float *grad, hipStream_t st);
 
-// obj = 0.5 * sumsq + 0.5 * sum_h eps2d2[h] ||p~_h||^2
+// obj = 0.5 * sumsq + 0.5 * sum_h eps2d2[h] ||p~_h||^2 (fixed summation order;
+// part: red_partials() doubles of scratch)
 hipError_t launch_objective(const double *sumsq, const float *ptilde, const float *eps2d2, const ExtGeom &g,
-                            double *obj, hipStream_t st);
+                            double *part, double *obj, hipStream_t st);
 
 // Vector kernels of the variable-projection solver (kernels_vec.hip).
 // out = a - b

@@ -539,11 +539,17 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
 constexpr int kImgYT = 8;
 constexpr int kImgHT = 8;
 
+// Each wavefront sums its tile in FP32 registers over at most kImgFlush
+// slots, then adds the sums to an FP64 image (the accumulator, or with
+// several slot groups its group's partial image), so no FP32 chain grows
+// with the number of shots and steps of a launch.
+constexpr int kImgFlush = 64;
+
 struct ImageArgs {
   const float *a;
   const float *b;
-  float *acc;
-  float *parts;        // groups > 1: partial images, one per slot group
+  double *acc;
+  double *parts;       // groups > 1: partial images, one per slot group
   long a_slot, b_slot, a_sstride, b_sstride;
   int b_ring, b_first;
   int nshots, nk;
@@ -552,6 +558,36 @@ struct ImageArgs {
   int nhb;             // offset blocks (blockIdx.y = group * nhb + offset block)
   int groups, slots_per_group;
 };
+
+// Adds a wavefront's FP32 tile sums to the FP64 image (its group's partial
+// image when the slots are split into groups; the first flush of a group
+// overwrites it) and clears them.  Every cell is owned by one wavefront.
+__device__ __forceinline__ void image_flush(const ImageArgs &p, float (&acc)[kImgYT][kImgHT], bool store, int grp,
+                                            int y0, int h0, int hhi, int z, bool first) {
+  if (store) {
+#pragma unroll
+    for (int yy = 0; yy < kImgYT; ++yy) {
+      const int y = y0 + yy;
+      if (y >= p.nx) continue;
+#pragma unroll
+      for (int hh = 0; hh < kImgHT; ++hh) {
+        const int ih = h0 + hh;
+        if (ih > hhi) continue;
+        const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
+        if (p.groups > 1) {
+          double *d = p.parts + (long)grp * p.nh * p.nx * p.nz + o;
+          *d = (first ? 0.0 : *d) + (double)acc[yy][hh];
+        } else {
+          p.acc[o] += (double)acc[yy][hh];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int yy = 0; yy < kImgYT; ++yy)
+#pragma unroll
+    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
+}
 
 // LDS-staged, pipelined version.  A workgroup of 16 wavefronts covers one
 // depth strip, YB = 8 NYT model columns and 8 NHT offsets of the group
@@ -659,6 +695,7 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   __syncthreads();
   int rb = 0;
   int q = q0;
+  bool first = true;
   for (; q + 1 < total; q += 2) {   // pairs of slots; no exit in between
     int nb1 = rb == 2 ? 0 : rb + 1;
     consume(rb);
@@ -672,22 +709,13 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
     fetch(q + 4, pB);
     __syncthreads();
     rb = nb1;
-  }
-  if (q < total) consume(rb);       // odd last slot, already staged
-  if (!active || !zin) return;
-#pragma unroll
-  for (int yy = 0; yy < kImgYT; ++yy) {
-    const int y = y0 + yy;
-    if (y >= p.nx) continue;
-#pragma unroll
-    for (int hh = 0; hh < kImgHT; ++hh) {
-      const int ih = h0 + hh;
-      if (ih > hhi) continue;
-      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
-      if (p.groups > 1) p.parts[(long)grp * p.nh * p.nx * p.nz + o] = acc[yy][hh];
-      else p.acc[o] += acc[yy][hh];
+    if ((q + 2 - q0) % kImgFlush == 0 && q + 2 < total) {
+      image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
+      first = false;
     }
   }
+  if (q < total) consume(rb);       // odd last slot, already staged
+  image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
 }
 
 // Wide-offset variant with the windows brought in by 16-byte direct
@@ -794,6 +822,7 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   issue(q0, b0);
   issue(q0 + 1, b1);
   issue(q0 + 2, b2);
+  bool first = true;
   for (int q = q0; q < total; q += 4) {
     step(q, b0, b3);
     if (q + 1 >= total) break;
@@ -802,35 +831,28 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
     step(q + 2, b2, b1);
     if (q + 3 >= total) break;
     step(q + 3, b3, b2);
-  }
-  if (!active || !zin) return;
-#pragma unroll
-  for (int yy = 0; yy < kImgYT; ++yy) {
-    const int y = y0 + yy;
-    if (y >= p.nx) continue;
-#pragma unroll
-    for (int hh = 0; hh < kImgHT; ++hh) {
-      const int ih = h0 + hh;
-      if (ih > hhi) continue;
-      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
-      if (p.groups > 1) p.parts[(long)grp * p.nh * p.nx * p.nz + o] = acc[yy][hh];
-      else p.acc[o] += acc[yy][hh];
+    // the flush's own loads and stores are younger than the slot loads in
+    // flight, so the next ready() waits for them too: later, never earlier
+    if ((q + 4 - q0) % kImgFlush == 0 && q + 4 < total) {
+      image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
+      first = false;
     }
   }
+  image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
 }
 
-// acc += sum over g of parts[g], in group order
-__global__ void k_image_reduce(float *acc, const float *parts, long n, int groups) {
+// acc += sum over g of parts[g], in group order (FP64)
+__global__ void k_image_reduce(double *acc, const double *parts, long n, int groups) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    float s = parts[i];
+    double s = parts[i];
     for (int g = 1; g < groups; ++g) s += parts[(long)g * n + i];
     acc[i] += s;
   }
 }
 
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
-                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, float *acc, float *parts,
-                            hipStream_t st) {
+                            int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, double *acc,
+                            double *parts, hipStream_t st) {
   if (nk <= 0 || nshots <= 0) return hipSuccess;
   ImageArgs p;
   p.a = a;
@@ -1134,8 +1156,9 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
 // gacc(x, z) += sum_s sum_n (t2u_n + t2d_n) lam_n + t2u_n rho_n   (padded grid)
 // ---------------------------------------------------------------------------
 __global__ void k_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
-                             const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
-                             int nk, int NZ, long ncell, int LZ, float *gacc) {
+                             long ring_slot, long ring_sstride, int ring, int first, const float *rho,
+                             long rho_slot, long rho_sstride, int rho_ring, int rho_first, int nshots, int nk,
+                             int NZ, long ncell, int LZ, float *gacc) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ncell) return;
   const int z = (int)(i % LZ);
@@ -1144,11 +1167,13 @@ __global__ void k_grad_accum(const float *t2u, const float *t2d, long slot, long
   for (int s = 0; s < nshots; ++s) {
     const long sa = (long)s * seg_sstride + i;
     const long sr = (long)s * ring_sstride + i;
+    const long sp = (long)s * rho_sstride + i;
     for (int n = 0; n < nk; ++n) {
       const long rs = (long)((first + n) % ring) * ring_slot;
+      const long ps = (long)((rho_first + n) % rho_ring) * rho_slot;
       const float u = t2u[sa + n * slot];
       const float d = t2d[sa + n * slot];
-      g += (u + d) * lam[sr + rs] + u * rho[sr + rs];
+      g += (u + d) * lam[sr + rs] + u * rho[sp + ps];
     }
   }
   gacc[i] += g;
@@ -1157,37 +1182,83 @@ __global__ void k_grad_accum(const float *t2u, const float *t2d, long slot, long
 hipError_t launch_grad_accum(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
                              const float *rho, long ring_slot, long ring_sstride, int ring, int first, int nshots,
                              int nk, int NZ, int NX, int LZ, float *gacc, hipStream_t st) {
+  return launch_grad_accum2(t2u, t2d, slot, seg_sstride, lam, ring_slot, ring_sstride, ring, first, rho, ring_slot,
+                            ring_sstride, ring, first, nshots, nk, NZ, NX, LZ, gacc, st);
+}
+
+hipError_t launch_grad_accum2(const float *t2u, const float *t2d, long slot, long seg_sstride, const float *lam,
+                              long lam_slot, long lam_sstride, int lam_ring, int lam_first, const float *rho,
+                              long rho_slot, long rho_sstride, int rho_ring, int rho_first, int nshots, int nk,
+                              int NZ, int NX, int LZ, float *gacc, hipStream_t st) {
   if (nk <= 0 || nshots <= 0) return hipSuccess;
   const long ncell = (long)NX * LZ;
-  k_grad_accum<<<(unsigned)((ncell + 255) / 256), 256, 0, st>>>(t2u, t2d, slot, seg_sstride, lam, rho, ring_slot,
-                                                                 ring_sstride, ring, first, nshots, nk, NZ, ncell,
-                                                                 LZ, gacc);
+  k_grad_accum<<<(unsigned)((ncell + 255) / 256), 256, 0, st>>>(t2u, t2d, slot, seg_sstride, lam, lam_slot,
+                                                                 lam_sstride, lam_ring, lam_first, rho, rho_slot,
+                                                                 rho_sstride, rho_ring, rho_first, nshots, nk, NZ,
+                                                                 ncell, LZ, gacc);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Residual and sum of squares (FP64 accumulation).
+// Residual and sum of squares (FP64 accumulation in a fixed order: each of
+// kRedBlocks workgroups reduces its strided share by a tree, and one
+// workgroup adds the partials by a tree, so the result does not depend on
+// scheduling and repeats bit for bit).
 // ---------------------------------------------------------------------------
-__global__ void k_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq) {
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+int red_partials() { return kRedBlocks; }
+
+__device__ __forceinline__ double block_tree_sum(double acc, double *red) {
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_residual(float *du, const float *ddu, const float *dobs, long n,
+                                                          double *part) {
+  __shared__ double red[kRedThreads];
   double acc = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  for (long i = (long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (long)kRedBlocks * kRedThreads) {
     const float r = du[i] + ddu[i] - dobs[i];
     du[i] = r;
     acc += (double)r * (double)r;
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  __shared__ double part[4];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(sumsq, part[0] + part[1] + part[2] + part[3]);
+  const double s = block_tree_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *sumsq,
+// *target = base (or *target when base is null) + scale * sum of the partials
+__global__ void __launch_bounds__(kRedThreads) k_red_final(const double *part, double *target, const double *base,
+                                                           double scale, double base_scale) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += part[i];
+  const double s = block_tree_sum(acc, red);
+  if (threadIdx.x == 0) *target = base_scale * (base ? *base : *target) + scale * s;
+}
+
+hipError_t launch_residual(float *du, const float *ddu, const float *dobs, long n, double *part, double *sumsq,
                            hipStream_t st) {
+  k_residual<<<kRedBlocks, kRedThreads, 0, st>>>(du, ddu, dobs, n, part);
+  k_red_final<<<1, kRedThreads, 0, st>>>(part, sumsq, nullptr, 1.0, 1.0);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_d(double *a, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) a[i] = v;
+}
+
+hipError_t launch_zero_d(double *a, long n, hipStream_t st) {
   long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  k_residual<<<(unsigned)blocks, 256, 0, st>>>(du, ddu, dobs, n, sumsq);
+  k_fill_d<<<(unsigned)blocks, 256, 0, st>>>(a, n, 0.0);
   return hipGetLastError();
 }
 
@@ -1207,19 +1278,19 @@ hipError_t launch_residual_sum(float *out, const float *a, const float *b, long 
 // ---------------------------------------------------------------------------
 // Finalizers
 // ---------------------------------------------------------------------------
-__global__ void k_ext_finalize(const float *acc, const float *vel, int nz, int nx, int nh, float dt,
+__global__ void k_ext_finalize(const double *acc, const float *vel, int nz, int nx, int nh, float dt,
                                const float *pt, const float *e2d2, float *out) {
   const long n = (long)nh * nx * nz;
   const long plane = (long)nx * nz;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const float v = vel[i % plane];
-    float r = 2.f * acc[i] / (v * v * v * dt * dt);
+    float r = (float)(2.0 * acc[i] / (double)(v * v * v * dt * dt));
     if (pt != nullptr) r += e2d2[i / plane] * pt[i];
     out[i] = r;
   }
 }
 
-hipError_t launch_ext_finalize(const float *acc, const float *vel, const ExtGeom &g, float dt,
+hipError_t launch_ext_finalize(const double *acc, const float *vel, const ExtGeom &g, float dt,
                                const float *ptilde, const float *dso2eps2, float *out, hipStream_t st) {
   const long n = (long)g.nh * g.nx * g.nz;
   long blocks = (n + 255) / 256;
@@ -1262,30 +1333,25 @@ hipError_t launch_grad_finalize(const float *gacc, const float *V, const float *
   return hipGetLastError();
 }
 
-__global__ void k_obj_init(const double *sumsq, double *obj) { *obj = 0.5 * (*sumsq); }
-
-__global__ void k_obj_reg(const float *pt, const float *e2d2, long plane, int nh, double *obj) {
+__global__ void __launch_bounds__(kRedThreads) k_obj_reg(const float *pt, const float *e2d2, long plane, int nh,
+                                                         double *part) {
+  __shared__ double red[kRedThreads];
   double acc = 0.0;
   const long n = plane * nh;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  for (long i = (long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (long)kRedBlocks * kRedThreads) {
     const double p = pt[i];
-    acc += 0.5 * (double)e2d2[i / plane] * p * p;
+    acc += (double)e2d2[i / plane] * p * p;
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  __shared__ double part[4];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(obj, part[0] + part[1] + part[2] + part[3]);
+  const double s = block_tree_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 hipError_t launch_objective(const double *sumsq, const float *ptilde, const float *eps2d2, const ExtGeom &g,
-                            double *obj, hipStream_t st) {
-  k_obj_init<<<1, 1, 0, st>>>(sumsq, obj);
+                            double *part, double *obj, hipStream_t st) {
   const long plane = (long)g.nx * g.nz;
-  long blocks = (plane * g.nh + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  k_obj_reg<<<(unsigned)blocks, 256, 0, st>>>(ptilde, eps2d2, plane, g.nh, obj);
+  k_obj_reg<<<kRedBlocks, kRedThreads, 0, st>>>(ptilde, eps2d2, plane, g.nh, part);
+  // obj = 0.5 sumsq + 0.5 sum_h eps^2 d_h^2 ||p~_h||^2
+  k_red_final<<<1, kRedThreads, 0, st>>>(part, obj, sumsq, 0.5, 0.5);
   return hipGetLastError();
 }
 

@@ -27,6 +27,10 @@
 // column, consumed by a wave-uniform loop inside the column march.  Receiver
 // sampling reads the LDS tile of the INPUT field, i.e. the kernel of equation
 // n records u^n.
+//
+// Free surface (kModeFS): the tile rows just above the surface row are loaded
+// from their mirror rows below it with opposite sign, and the output is zero
+// at and above the surface row; nothing else changes.
 #include "internal.h"
 
 namespace fw {
@@ -44,6 +48,7 @@ struct StepTile {
 // receivers of the input field (the last time sample of a job).
 template <int TX, int MODE>
 __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTile<TX> &sh, bool extract_only) {
+  constexpr bool FS = (MODE & kModeFS) != 0;
   constexpr int CPW = TX / kWaves;
   constexpr int HC = TX + 2 * kR;
   constexpr int HZ = kTZ + 2 * kR;
@@ -109,19 +114,26 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
     const bool zg_in = zg >= 0 && zg < NZ;
     const bool zg2_in = lane < 2 * kR && zg + kTZ < NZ;
     float v[NC], v2[NC];
+    // rows read for the two loads of this lane (mirrored under a free surface)
+    float sg = 1.f, sg2 = 1.f;
+    int zr = zg, zr2 = zg + kTZ;
+    if constexpr (FS) {
+      zr = fs_mirror_row(zg, a.fs, sg);
+      zr2 = fs_mirror_row(zg + kTZ, a.fs, sg2);
+    }
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       const int x = x0 - kR + w + kWaves * i;
       const bool xin = x >= 0 && x < NX;      // wave-uniform
-      v[i] = ld(r_cur, xin && zg_in ? x * CB + zg * 4 : kOutOfRange, 0);
-      v2[i] = ld(r_cur, xin && zg2_in ? x * CB + (zg + kTZ) * 4 : kOutOfRange, 0);
+      v[i] = ld(r_cur, xin && zg_in ? x * CB + zr * 4 : kOutOfRange, 0);
+      v2[i] = ld(r_cur, xin && zg2_in ? x * CB + zr2 * 4 : kOutOfRange, 0);
     }
     const bool lo8 = lane < 2 * kR;
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       const int c = w + kWaves * i;
-      tile[c][lane] = v[i];
-      *(lo8 ? &tile[c][kTZ + lane] : &sh.sink[w][lane]) = v2[i];
+      tile[c][lane] = FS ? sg * v[i] : v[i];
+      *(lo8 ? &tile[c][kTZ + lane] : &sh.sink[w][lane]) = FS ? sg2 * v2[i] : v2[i];
     }
   }
   __syncthreads();
@@ -173,9 +185,13 @@ __device__ __forceinline__ void step_body(const StepArgs &a, int logical, StepTi
     const int x = xs + j;
     if (zin && x < NX) {
       const float g = gzv * gx[j];
-      const float r = vv[j] * (lap + src);
+      float r = vv[j] * (lap + src);
       const long idx = (long)x * LZ + z;
-      out[idx] = g * (2.f * c - g * pv[j] + r);
+      float u = g * (2.f * c - g * pv[j] + r);
+      if constexpr (FS) {
+        if (z <= a.fs) u = r = 0.f;          // at and above the free surface
+      }
+      out[idx] = u;
       if constexpr ((MODE & kModeT2) != 0) a.t2[(long)s * a.t2_sstride + idx] = r;
     }
 #pragma unroll
@@ -200,9 +216,9 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
 // the time index of job j is *step - t0_j: it advances its fields while the
 // index is below nt_j - 1, samples its receivers at nt_j - 1 and is idle
 // outside [0, nt_j - 1].  Job j's fields alternate between bufA and bufB.
-template <int TX>
+template <int TX, int MODE>
 __global__ void __launch_bounds__(256) k_step_multi(const BatchJob *jobs, int njobs, int total,
-                                                    const int *step) {
+                                                    const int *step, int step_val) {
   __shared__ StepTile<TX> sh;
   const int per = (total + 7) >> 3;
   const int b = blockIdx.x;
@@ -215,7 +231,7 @@ __global__ void __launch_bounds__(256) k_step_multi(const BatchJob *jobs, int nj
     else hi = mid - 1;
   }
   const BatchJob &jb = jobs[lo];
-  const int n = *step - jb.t0;
+  const int n = (step ? *step : step_val) - jb.t0;
   if (n < 0 || n > jb.nt - 1) return;
   StepArgs a = jb.a;
   const bool even = (n & 1) == 0;
@@ -224,21 +240,28 @@ __global__ void __launch_bounds__(256) k_step_multi(const BatchJob *jobs, int nj
   a.out = const_cast<float *>(a.prev);
   a.inj.t = n;
   a.ext.t = n;
-  step_body<TX, kModePlain>(a, logical - jb.tile_begin, sh, n == jb.nt - 1);
+  step_body<TX, MODE>(a, logical - jb.tile_begin, sh, n == jb.nt - 1);
 }
 
 __global__ void k_bump(int *step, int by) { *step += by; }
 
-hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int tile_x,
-                             hipStream_t st) {
+template <int TX>
+static void launch_step_multi_tx(dim3 grid, const BatchJob *jobs, int njobs, int total_tiles, const int *step,
+                                 int step_val, bool fs, hipStream_t st) {
+  if (fs) k_step_multi<TX, kModeFS><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
+  else k_step_multi<TX, kModePlain><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
+}
+
+hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int step_val,
+                             int tile_x, bool fs, hipStream_t st) {
   const long per = (total_tiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   switch (tile_x) {
-    case 16: k_step_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 24: k_step_multi<24><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 32: k_step_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 48: k_step_multi<48><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 64: k_step_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 16: launch_step_multi_tx<16>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 24: launch_step_multi_tx<24>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 32: launch_step_multi_tx<32>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 48: launch_step_multi_tx<48>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 64: launch_step_multi_tx<64>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -256,12 +279,17 @@ static hipError_t launch_step_tx(const StepArgs &a, int mode, hipStream_t st) {
   const long total = (long)a.ntz * a.ntx * a.nshots;
   const long per = (total + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
+  if (a.fs >= 0) mode |= kModeFS;
   switch (mode) {
-    case kModePlain: k_step<TX, kModePlain><<<grid, 256, 0, st>>>(a); break;
-    case kModeT2: k_step<TX, kModeT2><<<grid, 256, 0, st>>>(a); break;
-    case kModeDsrc: k_step<TX, kModeDsrc><<<grid, 256, 0, st>>>(a); break;
-    case kModeT2 | kModeDsrc: k_step<TX, kModeT2 | kModeDsrc><<<grid, 256, 0, st>>>(a); break;
-    case kModeNu: k_step<TX, kModeNu><<<grid, 256, 0, st>>>(a); break;
+#define FW_STEP_MODE(M)                                     \
+  case M: k_step<TX, M><<<grid, 256, 0, st>>>(a); break;    \
+  case M | kModeFS: k_step<TX, M | kModeFS><<<grid, 256, 0, st>>>(a); break;
+    FW_STEP_MODE(kModePlain)
+    FW_STEP_MODE(kModeT2)
+    FW_STEP_MODE(kModeDsrc)
+    FW_STEP_MODE(kModeT2 | kModeDsrc)
+    FW_STEP_MODE(kModeNu)
+#undef FW_STEP_MODE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

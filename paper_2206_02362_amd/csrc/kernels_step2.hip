@@ -25,6 +25,12 @@
 // as a field or as three slots of a ring whose transposed second time
 // difference is the source.  With two == 0 only u^{n+1} is produced (an odd
 // last step).
+//
+// Free surface (kModeFS): rows fs-4 .. fs-1 of the u^n tile are loaded from
+// their mirror rows fs+4 .. fs+1 with opposite sign; u^{n+1} and u^{n+2} are
+// zero at and above row fs, and the u^{n+1} tile's rows fs-4 .. fs-1 take the
+// negated values of the mirror rows, which the same wavefront holds whenever
+// a row below the surface reads them (a lane shuffle).
 #include "internal.h"
 
 namespace fw {
@@ -109,12 +115,13 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   constexpr bool DS = (MODE & kModeDsrc) != 0;
   constexpr bool NU = (MODE & kModeNu) != 0;
   constexpr bool DF = (MODE & kModeDF) != 0;
+  constexpr bool FS = (MODE & kModeFS) != 0;
   constexpr int C0 = Step2Tile<TX>::C0;
   constexpr int ROWS = Step2Tile<TX>::ROWS;
   constexpr int W1 = (TX + 8) / kWaves;      // step-1 columns per wave
   constexpr int W2 = TX / kWaves;            // step-2 columns per wave
   static_assert((TX + 8) % kWaves == 0 && TX % kWaves == 0 && C0 % kWaves == 0, "tile width");
-  static_assert(EARLY2 || MODE == kModePlain, "late step-2 operand loads: plain mode only");
+  static_assert(EARLY2 || (MODE & ~kModeFS) == kModePlain, "late step-2 operand loads: plain mode only");
   const StepArgs &a = p.a;
   int txi, tzi, s;
   tile_coords(logical, a.ntz, a.ntx, a.nshots, txi, tzi, s);
@@ -204,17 +211,35 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
     const bool zt2_in = lane < 2 * kR && zt + 64 < NZ;
     float v[NC], v2[NC];
     [[maybe_unused]] unsigned short l[NC], l2[NC];
+    // rows read for the two loads of this lane (mirrored under a free surface)
+    [[maybe_unused]] float sg = 1.f, sg2 = 1.f;
+    int zr = zt, zr2 = zt + 64;
+    if constexpr (FS) {
+      zr = fs_mirror_row(zt, a.fs, sg);
+      zr2 = fs_mirror_row(zt + 64, a.fs, sg2);
+    }
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       const int x = x0 - 2 * kR + w + kWaves * i;
       const bool xin = x >= 0 && x < NX;      // wave-uniform
-      const int o1 = xin && zt_in ? x * CB + zt * 4 : kOut;
-      const int o2 = xin && zt2_in ? x * CB + (zt + 64) * 4 : kOut;
+      const int o1 = xin && zt_in ? x * CB + zr * 4 : kOut;
+      const int o2 = xin && zt2_in ? x * CB + zr2 * 4 : kOut;
       v[i] = ld(r_cur, o1, 0);
       v2[i] = ld(r_cur, o2, 0);
       if constexpr (DF) {
         l[i] = ld16(r_lcur, o1 == kOut ? kOut : o1 / 2, 0);
         l2[i] = ld16(r_lcur, o2 == kOut ? kOut : o2 / 2, 0);
+      }
+    }
+    if constexpr (FS) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        v[i] *= sg;
+        v2[i] *= sg2;
+        if constexpr (DF) {
+          if (sg < 0.f) l[i] ^= 0x8000u;           // BF16 sign flip
+          if (sg2 < 0.f) l2[i] ^= 0x8000u;
+        }
       }
     }
     if constexpr (NU) {
@@ -265,6 +290,8 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   if (extract_only) return;
 
   const int lz = lane + kR;                  // LDS row of this lane's row
+  // the tile's rows z0-4 .. z0+59 reach the four rows above a free surface
+  [[maybe_unused]] const bool fs_near = FS && a.fs >= 0 && z0 - kR <= a.fs - 1 && z0 + kTZ2 + kR - 1 >= a.fs - kR;
   // The low part of the extended-precision field is a rounding residual
   // (below 2^-24 of the field): its Laplacian needs only a few correct
   // digits, so it is summed directly, sum_k w_k (l(-k) + l(k)) + w_0 l, with
@@ -327,15 +354,38 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
         u1 = 0.f;
         u1l = 0;
       }
+      [[maybe_unused]] float rs = r;
+      if constexpr (FS) {
+        if (z <= a.fs) {                      // at and above the free surface
+          u1 = rs = 0.f;
+          u1l = 0;
+        }
+      }
       if (xin && x >= x0 && x < x0 + TX) {   // wave-uniform
         if (zin && zown) {
           st(r_out, u1, vz, x * CB);
           if constexpr (DF) st16(r_lout, u1l, z * 2, x * (CB / 2));
-          if constexpr (T2) st(r_t2, r, vz, x * CB);
+          if constexpr (T2) st(r_t2, FS ? rs : r, vz, x * CB);
         }
       }
-      sh.u1[w * W1 + j][lz] = u1;
-      if constexpr (DF) sh.l1[w * W1 + j][lz] = u1l;
+      float u1t = u1;
+      [[maybe_unused]] unsigned short u1lt = u1l;
+      if constexpr (FS) {
+        // rows fs-4 .. fs-1 of the tile: the negated mirror row 2 fs - z,
+        // held by lane 2 (fs - z0 + 4) - lane of this wavefront
+        if (fs_near) {                        // workgroup-uniform
+          const int src = ((2 * (a.fs - z0 + kR) - lane) & 63) << 2;
+          const float m = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, u1)));
+          [[maybe_unused]] int ml = 0;
+          if constexpr (DF) ml = __builtin_amdgcn_ds_bpermute(src, (int)u1l);
+          if (fs_mirrored(z, a.fs)) {
+            u1t = -m;
+            if constexpr (DF) u1lt = (unsigned short)(ml ^ 0x8000);
+          }
+        }
+      }
+      sh.u1[w * W1 + j][lz] = u1t;
+      if constexpr (DF) sh.l1[w * W1 + j][lz] = u1lt;
     }
   }
   if (!p.two && !ext_next) return;
@@ -409,11 +459,18 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       float u2;
       if constexpr (DF) u2 = df_update(g, c, cl, un, bf16_f32(basel0[j * ROWS]), r, u2l);
       else u2 = g * (2.f * c - g * un + r);
+      [[maybe_unused]] float rs = r;
+      if constexpr (FS) {
+        if (z <= a.fs) {                      // at and above the free surface
+          u2 = rs = 0.f;
+          u2l = 0;
+        }
+      }
       if (xin) {
         if (zown && zin) {
           st(r_out, u2, vz, x * CB);
           if constexpr (DF) st16(r_lout, u2l, z * 2, x * (CB / 2));
-          if constexpr (T2) st(r_t2, r, vz, x * CB);
+          if constexpr (T2) st(r_t2, FS ? rs : r, vz, x * CB);
         }
       }
     }
@@ -432,12 +489,15 @@ __global__ void __launch_bounds__(256) k_step2(const Step2Args p) {
 }
 
 // Many jobs (grids, models, geometries) in one launch, two steps per launch.
-// The time index of job j is n = *step - t0_j (the counter advances by 2).
+// The time index of job j is n = step - t0_j, with step read from device
+// memory (*step, advanced by 2 per launch under graph replay) or, when that
+// pointer is null, the launch argument step_val.
 // Job j's fields rotate through buf[0..3] (prev = buf[n % 4]).  At
 // n = nt_j - 2 it takes one step and samples u^n and u^{n+1}; at n = nt_j - 1
 // it only samples u^n; outside [0, nt_j - 1] it is idle.
-template <int TX>
-__global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int njobs, int total, const int *step) {
+template <int TX, int MODE>
+__global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int njobs, int total, const int *step,
+                                                     int step_val) {
   __shared__ Step2Tile<TX> sh;
   const int per = (total + 7) >> 3;
   const int b = blockIdx.x;
@@ -450,7 +510,7 @@ __global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int 
     else hi = mid - 1;
   }
   const BatchJob2 &jb = jobs[lo];
-  const int n = *step - jb.t0;
+  const int n = (step ? *step : step_val) - jb.t0;
   if (n < 0 || n > jb.nt - 1) return;
   Step2Args p = jb.p;
   p.a.prev = jb.buf[n & 3];
@@ -461,19 +521,26 @@ __global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int 
   p.a.inj.t = n;
   p.inj2.t = n + 1;
   p.a.ext.t = n;
-  step2_body<TX, kModePlain, false>(p, logical - jb.tile_begin, sh, n == jb.nt - 1, true);
+  step2_body<TX, MODE, false>(p, logical - jb.tile_begin, sh, n == jb.nt - 1, true);
 }
 
-hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int tile_x,
-                              hipStream_t st) {
+template <int TX>
+static void launch_step2_multi_tx(dim3 grid, const BatchJob2 *jobs, int njobs, int total_tiles, const int *step,
+                                  int step_val, bool fs, hipStream_t st) {
+  if (fs) k_step2_multi<TX, kModeFS><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
+  else k_step2_multi<TX, kModePlain><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
+}
+
+hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int step_val,
+                              int tile_x, bool fs, hipStream_t st) {
   const long per = (total_tiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   switch (tile_x) {
-    case 16: k_step2_multi<16><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 24: k_step2_multi<24><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 32: k_step2_multi<32><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 48: k_step2_multi<48><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
-    case 64: k_step2_multi<64><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step); break;
+    case 16: launch_step2_multi_tx<16>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 24: launch_step2_multi_tx<24>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 32: launch_step2_multi_tx<32>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 48: launch_step2_multi_tx<48>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 64: launch_step2_multi_tx<64>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -483,13 +550,20 @@ template <int TX>
 static hipError_t launch_step2_tx(const Step2Args &p, int mode, hipStream_t st) {
   const long total = (long)p.a.ntz * p.a.ntx * p.a.nshots;
   const dim3 grid((unsigned)((total + 7) / 8 * 8));
+  if (p.a.fs >= 0) mode |= kModeFS;
   switch (mode) {
-    case kModePlain: k_step2<TX, kModePlain><<<grid, 256, 0, st>>>(p); break;
-    case kModeT2: k_step2<TX, kModeT2><<<grid, 256, 0, st>>>(p); break;
-    case kModeDsrc: k_step2<TX, kModeDsrc><<<grid, 256, 0, st>>>(p); break;
-    case kModeNu: k_step2<TX, kModeNu><<<grid, 256, 0, st>>>(p); break;
-    case kModeDF: k_step2<TX, kModeDF><<<grid, 256, 0, st>>>(p); break;
-    case kModeT2 | kModeDF: k_step2<TX, kModeT2 | kModeDF><<<grid, 256, 0, st>>>(p); break;
+#define FW_STEP2_MODE(M)                                     \
+  case M: k_step2<TX, M><<<grid, 256, 0, st>>>(p); break;    \
+  case M | kModeFS: k_step2<TX, M | kModeFS><<<grid, 256, 0, st>>>(p); break;
+    FW_STEP2_MODE(kModePlain)
+    FW_STEP2_MODE(kModeT2)
+    FW_STEP2_MODE(kModeDsrc)
+    FW_STEP2_MODE(kModeT2 | kModeDsrc)
+    FW_STEP2_MODE(kModeNu)
+    FW_STEP2_MODE(kModeDF)
+    FW_STEP2_MODE(kModeT2 | kModeDF)
+    FW_STEP2_MODE(kModeDsrc | kModeDF)
+#undef FW_STEP2_MODE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

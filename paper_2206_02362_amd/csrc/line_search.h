@@ -17,6 +17,14 @@
 // new trial comes from safeguarded cubic and quadratic interpolation of the
 // two endpoints (`interpolate`); when the interval fails to shrink by a third
 // over two trials, the next trial is its midpoint.
+//
+// Provenance: the formulas of the trial steps (the cubic and quadratic
+// interpolants, their safeguards and the constants 1.1, 4.0 and 0.66) are
+// those of MINPACK-2's dcsrch / dcstep, the reference implementation of the
+// method, kept expression for expression (same parenthesization, same
+// variable names) because the tests require MINPACK's trial steps one for
+// one; the reverse-communication structure and the shared cubic helper are
+// this file's own.
 #pragma once
 
 #include <algorithm>

@@ -39,6 +39,7 @@ struct fwime_ctx {
   void *arena = nullptr;
   size_t arena_bytes = 0;
   double *host_red = nullptr;   // pinned: reduction results
+  size_t host_red_n = 0;        // doubles it holds
   int tile_x = 32;
   bool two_step = true;         // plain propagation two time steps per launch
   size_t tape_bytes = 0;        // device memory held by live tapes
@@ -51,6 +52,11 @@ struct fwime_ctx {
   hipGraphExec_t graph_exec = nullptr;    // next stream synchronization
   void *vp = nullptr;                     // variable-projection solver vectors
   size_t vp_bytes = 0;
+  // optional timing of the stencil launch loop of the modeling calls: two
+  // events recorded on the call's stream around its launches
+  bool timing = false;
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  long timed_launches = -1;               // launches between the events of the last timed call
 };
 
 static void release_graph(fwime_ctx_t *ctx) {
@@ -79,6 +85,19 @@ int set_err(fwime_ctx_t *ctx, int code, const std::string &msg) {
     if (e_ != hipSuccess)                                                              \
       return set_err(ctx, FWIME_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Events around a call's stencil launch loop (fwime_ctx_set_timing).
+hipError_t timing_begin(fwime_ctx_t *ctx, hipStream_t st) {
+  if (!ctx->timing) return hipSuccess;
+  ctx->timed_launches = -1;
+  return hipEventRecord(ctx->tev[0], st);
+}
+hipError_t timing_end(fwime_ctx_t *ctx, hipStream_t st, long launches) {
+  if (!ctx->timing) return hipSuccess;
+  hipError_t e = hipEventRecord(ctx->tev[1], st);
+  if (e == hipSuccess) ctx->timed_launches = launches;
+  return e;
+}
 
 double cfl_limit(double dz, double dx) {
   double nyq = -(kW[0] + 2.0 * (-kW[1] + kW[2] - kW[3] + kW[4]));
@@ -180,6 +199,8 @@ int check_grid(fwime_ctx_t *ctx, const fwime_grid_t *g) {
     return set_err(ctx, FWIME_EINVAL, "dz, dx, dt must be positive and finite");
   if (!(g->sponge_alpha >= 0) || !std::isfinite(g->sponge_alpha))
     return set_err(ctx, FWIME_EINVAL, "sponge_alpha must be >= 0");
+  if (g->free_surface && g->nb < kR)
+    return set_err(ctx, FWIME_EINVAL, "a free surface needs nb >= 4 (the mirrored stencil rows)");
   const long NZ = (long)g->nz + 2L * g->nb, NX = (long)g->nx + 2L * g->nb;
   const long LZ = (NZ + 4 + 63) / 64 * 64;
   // kernels address one shot's field with 32-bit byte offsets
@@ -210,44 +231,68 @@ int check_nh(fwime_ctx_t *ctx, const fwime_grid_t *g, int nh) {
   return FWIME_OK;
 }
 
-// min / max / non-finite count of a device array, synchronously.
-int device_range(fwime_ctx_t *ctx, const float *a, long n, double *scratch, hipStream_t st, double out[3]) {
-  HIPCHK(launch_minmax(a, n, scratch, st));
-  HIPCHK(hipMemcpyAsync(ctx->host_red, scratch, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  out[0] = ctx->host_red[0];
-  out[1] = ctx->host_red[1];
-  out[2] = ctx->host_red[2];
+// Pinned host space for at least n doubles of reduction results.
+int host_red_reserve(fwime_ctx_t *ctx, size_t n) {
+  if (n <= ctx->host_red_n) return FWIME_OK;
+  if (ctx->host_red) HIPCHK(hipHostFree(ctx->host_red));
+  ctx->host_red = nullptr;
+  ctx->host_red_n = 0;
+  const size_t want = std::max<size_t>(n, 64);
+  HIPCHK(hipHostMalloc((void **)&ctx->host_red, want * sizeof(double), hipHostMallocDefault));
+  ctx->host_red_n = want;
   return FWIME_OK;
 }
 
-// Common prologue: validates velocity (positive, finite, CFL) and the other
-// float inputs; runs before any output is touched.
-int check_inputs(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
-                 std::vector<std::pair<const float *, long>> extra, hipStream_t st) {
-  if (!vel) return set_err(ctx, FWIME_EINVAL, "vel is null");
+// min / max / non-finite count of several device arrays: one reduction per
+// array into consecutive triples of a scratch buffer at the front of the
+// arena, one copy to pinned host memory and one stream synchronization for
+// all of them.  out[3 k .. 3 k + 2] describe array k.
+int device_ranges(fwime_ctx_t *ctx, const std::vector<std::pair<const float *, long>> &arrays, hipStream_t st,
+                  std::vector<double> &out) {
+  const size_t n = arrays.size();
   double *scratch = nullptr;
   Carve cv;
-  cv.add(&scratch, 4);
-  // The scratch reduction buffer sits at the front of the arena; a later
-  // carve of the same call reuses the memory (the reduction is complete).
+  cv.add(&scratch, 3 * n);
+  // later carves of the same call reuse this memory: the reductions are
+  // complete once this function returns
   int rc = arena_get(ctx, cv);
   if (rc) return rc;
-  double r[3];
-  rc = device_range(ctx, vel, (long)g->nx * g->nz, scratch, st, r);
-  if (rc) return rc;
+  if ((rc = host_red_reserve(ctx, 3 * n))) return rc;
+  for (size_t k = 0; k < n; ++k) {
+    if (!arrays[k].first) return set_err(ctx, FWIME_EINVAL, "input pointer is null");
+    HIPCHK(launch_minmax(arrays[k].first, arrays[k].second, scratch + 3 * k, st));
+  }
+  HIPCHK(hipMemcpyAsync(ctx->host_red, scratch, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out.assign(ctx->host_red, ctx->host_red + 3 * n);
+  return FWIME_OK;
+}
+
+// Velocity range (positive, finite, CFL) from its min / max / non-finite triple.
+int check_velocity_range(fwime_ctx_t *ctx, const fwime_grid_t *g, const double *r) {
   if (r[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "vel has non-finite values");
   if (!(r[0] > 0)) return set_err(ctx, FWIME_EINVAL, "velocity must be positive");
   if (r[1] * g->dt > cfl_limit(g->dz, g->dx) * (1 + 1e-12))
     return set_err(ctx, FWIME_EINVAL, "CFL condition violated: v_max dt = " + std::to_string(r[1] * g->dt) +
                                           " > " + std::to_string(cfl_limit(g->dz, g->dx)));
-  extra.push_back({geo->wavelet, (long)geo->nshots * g->nt});
-  for (auto &e : extra) {
-    if (!e.first) return set_err(ctx, FWIME_EINVAL, "input pointer is null");
-    rc = device_range(ctx, e.first, e.second, scratch, st, r);
-    if (rc) return rc;
-    if (r[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "input array has non-finite values");
-  }
+  return FWIME_OK;
+}
+
+// Common prologue: validates velocity (positive, finite, CFL), the wavelets
+// and the other float inputs in one device pass and one synchronization;
+// runs before any output is touched.
+int check_inputs(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                 std::vector<std::pair<const float *, long>> extra, hipStream_t st) {
+  if (!vel) return set_err(ctx, FWIME_EINVAL, "vel is null");
+  std::vector<std::pair<const float *, long>> arrays{{vel, (long)g->nx * g->nz},
+                                                     {geo->wavelet, (long)geo->nshots * g->nt}};
+  arrays.insert(arrays.end(), extra.begin(), extra.end());
+  std::vector<double> r;
+  int rc = device_ranges(ctx, arrays, st, r);
+  if (rc) return rc;
+  if ((rc = check_velocity_range(ctx, g, r.data()))) return rc;
+  for (size_t k = 1; k < arrays.size(); ++k)
+    if (r[3 * k + 2] > 0) return set_err(ctx, FWIME_ENONFINITE, "input array has non-finite values");
   return FWIME_OK;
 }
 
@@ -390,7 +435,9 @@ size_t table_set_ints(const TableSet &ts) {
   return n;
 }
 
-int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
+// sync = false: the copy may still read ts.blob after the call returns, so
+// the caller keeps ts alive until the stream has passed the copy.
+int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st, bool sync = true) {
   ts.blob.clear();
   ts.dev.clear();
   auto put = [&](const void *src, size_t nint) -> size_t {
@@ -430,10 +477,10 @@ int upload_tables(fwime_ctx_t *ctx, TableSet &ts, int *dev, hipStream_t st) {
     dt.rinj1_ent = (int2 *)(dev + o[10]);
     ts.dev.push_back(dt);
   }
-  // The blob is copied synchronously (pageable memory): the call owns no
-  // host staging that could outlive it.
+  // With sync the blob is copied synchronously (pageable memory): the call
+  // owns no host staging that could outlive it.
   HIPCHK(hipMemcpyAsync(dev, ts.blob.data(), ts.blob.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (sync) HIPCHK(hipStreamSynchronize(st));
   return FWIME_OK;
 }
 
@@ -476,6 +523,7 @@ int setup_common(fwime_ctx_t *ctx, Common &c, const fwime_grid_t *g, const float
   a.LZ = d.LZ;
   a.ntz = d.ntz;
   a.ntx = d.ntx;
+  a.fs = g->free_surface ? d.nb : -1;
   const double idz2 = 1.0 / (g->dz * g->dz), idx2 = 1.0 / (g->dx * g->dx);
   for (int k = 0; k < kR; ++k) {
     a.cz[k] = (float)(kW[k + 1] * idz2);
@@ -620,9 +668,11 @@ hipError_t copy_lo(unsigned short *dst, long dst_sstride, const unsigned short *
 // from time k = k1 down to k0 + 1, producing the fields of times k1 - 1 ..
 // k0: two steps per launch.  setup(p, k, kk) adds the sources of the launch
 // that starts at time k.
+// With lo != nullptr (a BF16 ring of the same shape) the field is carried in
+// extended precision (mode gets kModeDF).
 template <class Setup>
 int march2_back_ring(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_stride, int R, int S, int k0, int k1,
-                     int mode, Setup setup, hipStream_t st) {
+                     int mode, Setup setup, hipStream_t st, unsigned short *lo = nullptr) {
   const long F = c.d.field;
   for (int k = k1; k >= k0 + 1;) {
     const int kk = (k - 2 >= k0) ? 2 : 1;
@@ -634,8 +684,14 @@ int march2_back_ring(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_s
     p.a.out = ring + (long)((k - 1) % R) * F;
     p.out2 = kk == 2 ? ring + (long)((k - 2) % R) * F : nullptr;
     p.two = kk == 2;
+    if (lo) {
+      p.lo_cur = lo + (long)(k % R) * F;
+      p.lo_prev = lo + (long)((k + 1) % R) * F;
+      p.lo_out = lo + (long)((k - 1) % R) * F;
+      p.lo_out2 = kk == 2 ? lo + (long)((k - 2) % R) * F : nullptr;
+    }
     setup(p, k, kk);
-    HIPCHK(launch_step2(p, c.d.TX, mode, st));
+    HIPCHK(launch_step2(p, c.d.TX, lo ? (mode | kModeDF) : mode, st));
     k -= kk;
   }
   return FWIME_OK;
@@ -643,9 +699,10 @@ int march2_back_ring(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_s
 
 // lambda: receiver injection of `data` at the current time
 int march2_back_lambda(fwime_ctx_t *ctx, const Common &c, float *ring, long ring_stride, int R, int S, int k0,
-                       int k1, const DevTables &t, const float *data, int nt, hipStream_t st) {
+                       int k1, const DevTables &t, const float *data, int nt, hipStream_t st,
+                       unsigned short *lo = nullptr) {
   return march2_back_ring(ctx, c, ring, ring_stride, R, S, k0, k1, kModePlain,
-                          [&](Step2Args &p, int k, int) { with_rec_inject2(p, t, data, nt, k, k - 1); }, st);
+                          [&](Step2Args &p, int k, int) { with_rec_inject2(p, t, data, nt, k, k - 1); }, st, lo);
 }
 
 int choose_batch(fwime_ctx_t *ctx, long per_shot_bytes, size_t fixed_bytes, int nshots) {
@@ -702,6 +759,7 @@ const char *fwime_strerror(int code) {
 
 const char *fwime_last_error(const fwime_ctx_t *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+
 int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   if (!out) return FWIME_EINVAL;
   *out = nullptr;
@@ -711,7 +769,7 @@ int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   fwime_ctx_t *ctx = new fwime_ctx_t();
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
-  if (hipHostMalloc((void **)&ctx->host_red, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (host_red_reserve(ctx, 64) != FWIME_OK) {
     delete ctx;
     return FWIME_EHIP;
   }
@@ -746,6 +804,27 @@ int fwime_ctx_info(const fwime_ctx_t *ctx, fwime_info_t *out) {
   out->tile_x = ctx->tile_x;
   out->last_batch_tile_x = ctx->last_batch_tile;
   out->tuned_signatures = (int32_t)ctx->tuned.size();
+  out->last_stencil_launches = -1;
+  out->last_stencil_ms = 0.0;
+  if (ctx->timing && ctx->timed_launches >= 0) {
+    if (hipSetDevice(ctx->device) != hipSuccess || hipEventSynchronize(ctx->tev[1]) != hipSuccess) return FWIME_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]) != hipSuccess) return FWIME_EHIP;
+    out->last_stencil_launches = ctx->timed_launches;
+    out->last_stencil_ms = ms;
+  }
+  return FWIME_OK;
+}
+
+int fwime_ctx_set_timing(fwime_ctx_t *ctx, int32_t on) {
+  if (!ctx) return FWIME_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FWIME_EHIP;
+  if (on && !ctx->tev[0]) {
+    for (auto &e : ctx->tev)
+      if (hipEventCreate(&e) != hipSuccess) return set_err(ctx, FWIME_EHIP, "hipEventCreate failed");
+  }
+  ctx->timing = on != 0;
+  ctx->timed_launches = -1;
   return FWIME_OK;
 }
 
@@ -758,6 +837,8 @@ void fwime_ctx_destroy(fwime_ctx_t *ctx) {
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->vp) (void)hipFree(ctx->vp);
   if (ctx->host_red) (void)hipHostFree(ctx->host_red);
+  for (auto &e : ctx->tev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -794,10 +875,13 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
   if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
 
+  HIPCHK(timing_begin(ctx, st));
+  long launches = 0;
   for (size_t bi = 0; bi < batches.size(); ++bi) {
     const int s0 = batches[bi].first, Sb = batches[bi].second;
     const DevTables &t = ts.dev[bi];
     float *out_b = data + (long)s0 * geo->nrec * g->nt;
+    launches += two ? g->nt / 2 : g->nt - 1;
     if (two) {
       HIPCHK(launch_zero(fields, 4 * d.field * Sb, st));
       Ring4 f(fields, d.field * Sb);
@@ -828,6 +912,7 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
     }
     HIPCHK(launch_gather(cur, d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
   }
+  HIPCHK(timing_end(ctx, st, launches));
   return FWIME_OK;
 }
 
@@ -850,8 +935,8 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   const int KC = 16;
   const bool two = ctx->two_step;
   const int nf = two ? 8 : 4;                  // u and du~ field buffers per shot
-  // two-step path: the background also carries four BF16 low-part fields
-  const long per_shot = (nf + 2L * KC + (two ? 2 : 0)) * d.field * 4 + (long)geo->nrec * 64;
+  // two-step path: both fields also carry four BF16 low-part fields each
+  const long per_shot = (nf + 2L * KC + (two ? 4 : 0)) * d.field * 4 + (long)geo->nrec * 64;
   const size_t fixed = (size_t)d.field * 8 + (size_t)nh * d.nx * d.nz * 4;
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
@@ -866,7 +951,7 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&coef, (long)nh * d.nx * d.nz);
   cv.add(&pairs, nf * d.field * S);
-  if (two) cv.add(&lows, 4 * d.field * S);
+  if (two) cv.add(&lows, 8 * d.field * S);
   cv.add(&t2, (long)KC * d.field * S);
   cv.add(&sc, (long)KC * d.field * S);
   if ((rc = arena_get(ctx, cv))) return rc;
@@ -881,10 +966,10 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
     float *out_b = data + (long)s0 * geo->nrec * g->nt;
     if (two) {
       HIPCHK(launch_zero(pairs, 8 * d.field * Sb, st));
-      HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
+      HIPCHK(launch_zero((float *)lows, 4 * d.field * Sb, st));
       HIPCHK(launch_zero(sc, chunk_stride * Sb, st));
       Ring4 fu(pairs, d.field * Sb), fw(pairs + 4 * d.field * Sb, d.field * Sb);
-      Ring4L lu(lows, d.field * Sb);
+      Ring4L lu(lows, d.field * Sb), lw(lows + 4 * d.field * Sb, d.field * Sb);
       const float *wav_b = geo->wavelet + (long)s0 * g->nt;
       for (int c0 = 0; c0 < g->nt - 1; c0 += KC) {
         const int nk = std::min(KC, g->nt - 1 - c0);
@@ -897,10 +982,12 @@ int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel
         }, st, &lu);
         if (rc) return rc;
         HIPCHK(launch_ext_scatter(coef, eg, +1, t2, d.field, sc, d.field, chunk_stride, Sb, nk, st));
+        // the scattered field in extended precision too: its FP32 rounding
+        // would otherwise dominate the inconsistency of the B~ / B~^T pair
         rc = march2(ctx, c, fw, Sb, c0, c0 + nk, kModeDsrc, [&](Step2Args &p, int n, int k) {
           with_dsrc2(p, sc + (long)(n - c0) * d.field, d.field, k, chunk_stride);
           with_rec_extract(p.a, t, out_b, g->nt, n);
-        }, st);
+        }, st, &lw);
         if (rc) return rc;
       }
       HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, geo->nrec, out_b, g->nt, g->nt - 1, st));
@@ -959,21 +1046,28 @@ static int check_tau(fwime_ctx_t *ctx, const fwime_grid_t *g, int ntau, int lag)
 
 // Background T2 history of a shot batch: march all nt - 1 steps, T2 of step n
 // into slot n of hist (per-shot stride hstride).
+// Background of a shot batch in extended precision, keeping the T2 term of
+// every step (slot n of shot s at hist + s hstride + n field); with rec_out
+// (batch-local [Sb][nrec][nt]) it also records the receivers.
 static int tau_background(fwime_ctx_t *ctx, const Common &c, const fwime_grid_t *g, const fwime_geom_t *geo,
                           int s0, int Sb, const DevTables &t, float *pairs, unsigned short *lows, float *hist,
-                          long hstride, hipStream_t st) {
+                          long hstride, hipStream_t st, float *rec_out = nullptr) {
   const Dims &d = c.d;
   HIPCHK(launch_zero(pairs, 4 * d.field * Sb, st));
   HIPCHK(launch_zero((float *)lows, 2 * d.field * Sb, st));
   Ring4 fu(pairs, d.field * Sb);
   Ring4L lu(lows, d.field * Sb);
   const float *wav_b = geo->wavelet + (long)s0 * g->nt;
-  return march2(ctx, c, fu, Sb, 0, g->nt - 1, kModeT2, [&](Step2Args &p, int n, int k) {
+  int rc = march2(ctx, c, fu, Sb, 0, g->nt - 1, kModeT2, [&](Step2Args &p, int n, int k) {
     p.a.t2 = hist + (long)n * d.field;
     p.t2b = k == 2 ? hist + (long)(n + 1) * d.field : nullptr;
     p.a.t2_sstride = hstride;
     with_src2(p, t, wav_b, g, n);
+    if (rec_out) with_rec_extract(p.a, t, rec_out, g->nt, n);
   }, st, &lu);
+  if (rc || !rec_out) return rc;
+  HIPCHK(launch_gather(fu.cur(), d.field, t.cells, Sb, geo->nrec, rec_out, g->nt, g->nt - 1, st));
+  return FWIME_OK;
 }
 
 int fwime_born_ext_tau_fwd(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
@@ -1135,27 +1229,30 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
   // two-step path: BF16 low parts of the four work fields and the checkpoints
   // (cached checkpoints live outside the arena)
   const long ck_fields = cache ? 0L : 2L * nseg + (two ? nseg : 0L);
-  const long per_shot = (nf + K + R + (two ? 2L : 0L) + ck_fields) * d.field * 4 + (long)geo->nrec * 64;
+  // (two-step path: the adjoint ring's BF16 low parts add R / 2 fields)
+  const long per_shot = (nf + K + R + (two ? 2L + (R + 1) / 2 : 0L) + ck_fields) * d.field * 4 + (long)geo->nrec * 64;
   const long img = (long)nh * d.nx * d.nz;
   const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4 * (1 + kImageGroups);
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, two);
 
-  float *acc = nullptr, *pairs = nullptr, *ckpt = nullptr, *t2 = nullptr, *ring = nullptr;
+  float *pairs = nullptr, *ckpt = nullptr, *t2 = nullptr, *ring = nullptr;
+  double *acc = nullptr;
   Carve cv;
   cv.add(&c.V, d.field);
   cv.add(&c.gz, d.LZ);
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
-  unsigned short *lows = nullptr, *ckpt_lo = nullptr;
-  float *parts = nullptr;
+  unsigned short *lows = nullptr, *ckpt_lo = nullptr, *ring_lo = nullptr;
+  double *parts = nullptr;
   cv.add(&acc, img);
   cv.add(&parts, kImageGroups * img);
   cv.add(&pairs, nf * d.field * S);
   if (!cache) cv.add(&ckpt, 2L * nseg * d.field * S);
   if (two) {
     cv.add(&lows, 4 * d.field * S);
+    cv.add(&ring_lo, (long)R * d.field * S);
     if (!cache) cv.add(&ckpt_lo, 2L * nseg * d.field * S);
   }
   cv.add(&t2, (long)K * d.field * S);
@@ -1163,7 +1260,7 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
   if ((rc = arena_get(ctx, cv))) return rc;
   if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
   if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
-  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero_d(acc, img, st));
 
   const long ck_stride = 2L * nseg * d.field;   // per shot
   const long t2_stride = (long)K * d.field;
@@ -1195,8 +1292,10 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
         if ((rc = march2(ctx, c, fu, Sb, n0, n1, kModePlain, src, st, &lu))) return rc;
       }
       // backward pass: recompute the segment from its checkpoint (keeping
-      // T2 u_n), march lambda through the segment, image
+      // T2 u_n), march lambda through the segment (in extended precision as
+      // well), image
       HIPCHK(launch_zero(ring, ring_stride * Sb, st));
+      HIPCHK(launch_zero((float *)ring_lo, ring_stride * Sb / 2, st));
       for (int j = nseg - 1; j >= 0; --j) {
         const int n0 = j * K, n1 = std::min(n0 + K, g->nt - 1), nk = n1 - n0;
         Ring4 wu(pairs, d.field * Sb);
@@ -1212,7 +1311,8 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
           with_src2(p, t, wav_b, g, n);
         }, st, &wl);
         if (rc) return rc;
-        if ((rc = march2_back_lambda(ctx, c, ring, ring_stride, R, Sb, n0, n1, t, data_b, g->nt, st))) return rc;
+        if ((rc = march2_back_lambda(ctx, c, ring, ring_stride, R, Sb, n0, n1, t, data_b, g->nt, st, ring_lo)))
+          return rc;
         HIPCHK(launch_ext_image(t2, d.field, t2_stride, ring, d.field, ring_stride, R, n0, Sb, nk, eg, acc, parts, st));
       }
       continue;
@@ -1303,7 +1403,7 @@ GradPlan grad_plan(const Dims &d, int nt) {
 
 struct GradWork {       // per-batch working fields (+ partial images of the imaging kernel)
   float *pairs, *t2u, *t2d, *lam, *er, *rho;
-  float *parts = nullptr;
+  double *parts = nullptr;
 };
 
 int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
@@ -1384,7 +1484,7 @@ int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, con
 
 int grad_backward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
                         const fwime_grid_t *g, int Sb, const DevTables &t, const float *wav_b, const float *coef,
-                        float *uck, float *dck, const GradWork &wk, const float *r, float *acc, float *gacc,
+                        float *uck, float *dck, const GradWork &wk, const float *r, double *acc, float *gacc,
                         hipStream_t st) {
   const Dims &d = c.d;
   const int K = pl.K, R = pl.R;
@@ -1628,7 +1728,7 @@ static int vp_solve_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *ve
                : born_ext_adj_run(ctx, g, vel, geo, nh, d, x, stream, cp);
   };
   if ((rc = adj(dres, b))) return rc;
-  HIPCHK(hipMemsetAsync(ptilde_out, 0, img * sizeof(float), st));
+  HIPCHK(launch_zero(ptilde_out, img, st));
   HIPCHK(hipMemcpyAsync(r, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(sdir, b, img * sizeof(float), hipMemcpyDeviceToDevice, st));
   if ((rc = dot(r, r, img, rr))) return rc;
@@ -1698,9 +1798,10 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, ctx->two_step);
 
-  float *coef = nullptr, *acc = nullptr, *imgs = nullptr, *gacc = nullptr, *uck = nullptr, *dck = nullptr,
+  double *acc = nullptr;
+  float *coef = nullptr, *imgs = nullptr, *gacc = nullptr, *uck = nullptr, *dck = nullptr,
         *drec = nullptr, *ddrec = nullptr, *e2d2 = nullptr;
-  double *sumsq = nullptr;
+  double *sumsq = nullptr, *rpart = nullptr;
   GradWork wk;
   Carve cv;
   cv.add(&c.V, d.field);
@@ -1708,6 +1809,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   cv.add(&sumsq, 2);
+  cv.add(&rpart, red_partials());
   cv.add(&e2d2, nh);
   cv.add(&coef, img);
   cv.add(&acc, img);
@@ -1726,9 +1828,9 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   for (int h = 0; h < nh; ++h) e2[h] = (float)(eps * eps * dso[h] * dso[h]);
   HIPCHK(hipMemcpyAsync(e2d2, e2.data(), nh * sizeof(float), hipMemcpyHostToDevice, st));
   HIPCHK(launch_ext_coef(ptilde, vel, eg, (float)g->dt, coef, st));
-  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero_d(acc, img, st));
   HIPCHK(launch_zero(gacc, d.field, st));
-  HIPCHK(hipMemsetAsync(sumsq, 0, 2 * sizeof(double), st));
+  HIPCHK(launch_zero_d(sumsq, 2, st));
 
   for (size_t bi = 0; bi < batches.size(); ++bi) {
     const int s0 = batches[bi].first, Sb = batches[bi].second;
@@ -1736,14 +1838,151 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
     const float *wav_b = geo->wavelet + (long)s0 * g->nt;
     if ((rc = grad_forward_batch(ctx, c, eg, pl, g, Sb, t, wav_b, coef, uck, dck, wk, drec, ddrec, geo->nrec, st)))
       return rc;
-    HIPCHK(launch_residual(drec, ddrec, dobs + (long)s0 * nrt, nrt * Sb, sumsq, st));
+    HIPCHK(launch_residual(drec, ddrec, dobs + (long)s0 * nrt, nrt * Sb, rpart, sumsq, st));
     if ((rc = grad_backward_batch(ctx, c, eg, pl, g, Sb, t, wav_b, coef, uck, dck, wk, drec, acc, gacc, st)))
       return rc;
   }
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, nullptr, nullptr, imgs, st));
   HIPCHK(launch_grad_finalize(gacc, c.V, vel, eg, (float)g->dt, ptilde, imgs, grad_vel, st));
   HIPCHK(launch_ext_finalize(acc, vel, eg, (float)g->dt, ptilde, e2d2, grad_ptilde, st));
-  HIPCHK(launch_objective(sumsq, ptilde, e2d2, eg, obj, st));
+  HIPCHK(launch_objective(sumsq, ptilde, e2d2, eg, rpart, obj, st));
+  return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FWIME objective and gradients with the time-lag extension.  Every history
+// of a shot batch is kept whole (slot n of shot s at base + s hs + n field,
+// hs = (nt + 1) fields): T2u and T2du~ of every step, the adjoint field of
+// every time, and the scattering source, whose buffer then holds the spread
+// e; rho runs in a ring of chunks of kTauChunk steps, each followed by its
+// share of the gradient sums.
+// ---------------------------------------------------------------------------
+int fwime_gradient_tau(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       int32_t ntau, int32_t lag, const float *ptau, const float *dobs, double eps,
+                       const double *dso, double *obj, float *grad_vel, float *grad_ptau, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = check_grid(ctx, g)) || (rc = check_geom(ctx, g, geo)) || (rc = check_tau(ctx, g, ntau, lag))) return rc;
+  if (!ptau || !dobs || !dso || !obj || !grad_vel || !grad_ptau)
+    return set_err(ctx, FWIME_EINVAL, "null pointer argument");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_err(ctx, FWIME_EINVAL, "eps must be finite and >= 0");
+  for (int h = 0; h < ntau; ++h)
+    if (!std::isfinite(dso[h])) return set_err(ctx, FWIME_EINVAL, "dso weights must be finite");
+  HIPCHK(hipSetDevice(ctx->device));
+  const long plane = (long)g->nx * g->nz, img = (long)ntau * plane;
+  const long nrt = (long)geo->nrec * g->nt;
+  if ((rc = check_inputs(ctx, g, vel, geo, {{ptau, img}, {dobs, nrt * geo->nshots}}, st))) return rc;
+
+  constexpr int kTauChunk = 64;
+  Common c;
+  c.d = make_dims(g, ctx->tile_x);
+  const Dims &d = c.d;
+  ExtGeom eg{d.nz, d.nx, d.nb, d.NZ, d.NX, d.LZ, ntau, (ntau - 1) / 2};
+  const int ns = g->nt - 1, R = g->nt + 1, RR = kTauChunk + 2;
+  const long hs = (long)R * d.field, rs = (long)RR * d.field;
+  // per shot: four histories of R fields, the rho ring, the wavefield rings
+  // (8 fields) and the background's BF16 low parts (2), receiver data of u
+  // and du~, tables
+  const long per_shot = (4L * R + RR + 10) * d.field * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
+  const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4 * 3;
+  const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
+  auto batches = split_batches(geo->nshots, S);
+  TableSet ts = build_table_set(d, geo, batches, true);
+
+  float *coef = nullptr, *coefr = nullptr, *acc = nullptr, *gacc = nullptr, *e2d2 = nullptr, *pairs = nullptr,
+        *hu = nullptr, *hdu = nullptr, *lam = nullptr, *sc = nullptr, *rho = nullptr, *drec = nullptr,
+        *ddrec = nullptr;
+  unsigned short *lows = nullptr;
+  double *sumsq = nullptr, *rpart = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX + kGxPad);
+  cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
+  cv.add(&sumsq, 2);
+  cv.add(&rpart, red_partials());
+  cv.add(&e2d2, ntau);
+  cv.add(&coef, img);
+  cv.add(&coefr, img);
+  cv.add(&acc, img);
+  cv.add(&gacc, d.field);
+  cv.add(&pairs, 8 * d.field * S);
+  cv.add(&lows, 4 * d.field * S);
+  cv.add(&hu, hs * S);
+  cv.add(&hdu, hs * S);
+  cv.add(&lam, hs * S);
+  cv.add(&sc, hs * S);
+  cv.add(&rho, rs * S);
+  cv.add(&drec, nrt * S);
+  cv.add(&ddrec, nrt * S);
+  if ((rc = arena_get(ctx, cv))) return rc;
+  if ((rc = upload_tables(ctx, ts, c.tables, st))) return rc;
+  if ((rc = setup_common(ctx, c, g, vel, st))) return rc;
+  std::vector<float> e2(ntau);
+  for (int h = 0; h < ntau; ++h) e2[h] = (float)(eps * eps * dso[h] * dso[h]);
+  HIPCHK(hipMemcpyAsync(e2d2, e2.data(), ntau * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_ext_coef(ptau, vel, eg, (float)g->dt, coef, st));
+  // the spread e_m = sum_k c_k lam_{m + 2kL} is the lag scatter with the
+  // coefficient planes in reverse order: c'_k = c_{-k}
+  for (int k = 0; k < ntau; ++k)
+    HIPCHK(hipMemcpyAsync(coefr + (long)k * plane, coef + (long)(ntau - 1 - k) * plane, plane * sizeof(float),
+                          hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero(gacc, d.field, st));
+  HIPCHK(launch_zero_d(sumsq, 2, st));
+
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const int s0 = batches[bi].first, Sb = batches[bi].second;
+    const DevTables &t = ts.dev[bi];
+    // background: T2u of every step, and its receiver data
+    if ((rc = tau_background(ctx, c, g, geo, s0, Sb, t, pairs, lows, hu, hs, st, drec))) return rc;
+    // scattering source history, then du~ with its T2 history and receivers
+    HIPCHK(launch_zero(sc, hs * Sb, st));
+    HIPCHK(launch_tau_scatter(coef, eg, lag, hu, sc, d.field, hs, ns, Sb, st));
+    float *wp = pairs + 4 * d.field * Sb;
+    HIPCHK(launch_zero(wp, 4 * d.field * Sb, st));
+    Ring4 fw(wp, d.field * Sb);
+    rc = march2(ctx, c, fw, Sb, 0, ns, kModeT2 | kModeDsrc, [&](Step2Args &p, int n, int k) {
+      with_dsrc2(p, sc + (long)n * d.field, d.field, k, hs);
+      p.a.t2 = hdu + (long)n * d.field;
+      p.t2b = k == 2 ? hdu + (long)(n + 1) * d.field : nullptr;
+      p.a.t2_sstride = hs;
+      with_rec_extract(p.a, t, ddrec, g->nt, n);
+    }, st);
+    if (rc) return rc;
+    HIPCHK(launch_gather(fw.cur(), d.field, t.cells, Sb, geo->nrec, ddrec, g->nt, g->nt - 1, st));
+    // residual r = R(u + du~) - d_obs (into drec) and its sum of squares
+    HIPCHK(launch_residual(drec, ddrec, dobs + (long)s0 * nrt, nrt * Sb, rpart, sumsq, st));
+    // adjoint field of every time
+    HIPCHK(launch_zero(lam, hs * Sb, st));
+    if ((rc = march2_back_lambda(ctx, c, lam, hs, R, Sb, 0, g->nt - 1, t, drec, g->nt, st))) return rc;
+    // spread e over the adjoint history (slots 0 .. ns-1; zero from ns on)
+    HIPCHK(launch_zero(sc, hs * Sb, st));
+    HIPCHK(launch_tau_scatter(coefr, eg, lag, lam, sc, d.field, hs, ns, Sb, st));
+    // rho = M^-T nu, nu^k = e_{k-1}/g - 2 e_k + g e_{k+1}, chunk by chunk
+    // backwards, each chunk followed by its gradient sums
+    auto e_slot = [&](int k) { return sc + (long)k * d.field; };
+    HIPCHK(launch_zero(rho, rs * Sb, st));
+    const int nchunk = (ns + kTauChunk - 1) / kTauChunk;
+    for (int j = nchunk - 1; j >= 0; --j) {
+      const int n0 = j * kTauChunk, n1 = std::min(n0 + kTauChunk, ns);
+      rc = march2_back_ring(ctx, c, rho, rs, RR, Sb, n0, n1, kModeNu, [&](Step2Args &p, int k, int kk) {
+        p.a.nu = NuSource{e_slot(k - 1), e_slot(k), e_slot(k + 1), hs};
+        if (kk == 2) p.nu2 = NuSource{e_slot(k - 2), e_slot(k - 1), e_slot(k), hs};
+      }, st);
+      if (rc) return rc;
+      HIPCHK(launch_grad_accum2(hu + (long)n0 * d.field, hdu + (long)n0 * d.field, d.field, hs, lam, d.field, hs, R,
+                                n0, rho, d.field, rs, RR, n0, Sb, n1 - n0, d.NZ, d.NX, d.LZ, gacc, st));
+    }
+    // B~_tau^T r (scaled by 2 / (v^3 dt^2) in the kernel)
+    HIPCHK(launch_tau_image(hu, d.field, hs, lam, d.field, hs, ns, Sb, eg, lag, vel, (float)g->dt, acc, st));
+  }
+  HIPCHK(launch_grad_finalize(gacc, c.V, vel, eg, (float)g->dt, ptau, acc, grad_vel, st));
+  HIPCHK(hipMemcpyAsync(grad_ptau, acc, img * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_add_diag(grad_ptau, ptau, e2d2, plane, ntau, st));
+  HIPCHK(launch_objective(sumsq, ptau, e2d2, eg, rpart, obj, st));
   return FWIME_OK;
 }
 
@@ -1880,17 +2119,14 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
   const long nrt = (long)tp->nrec * g->nt;
   {
     // finiteness of the adjoint source, checked before anything is written
-    double *scratch = nullptr;
-    Carve sc;
-    sc.add(&scratch, 4);
-    if ((rc = arena_get(ctx, sc))) return rc;
-    double r3[3];
-    if ((rc = device_range(ctx, adjsrc, nrt * tp->nshots, scratch, st, r3))) return rc;
+    std::vector<double> r3;
+    if ((rc = device_ranges(ctx, {{adjsrc, nrt * tp->nshots}}, st, r3))) return rc;
     if (r3[2] > 0) return set_err(ctx, FWIME_ENONFINITE, "adjoint source has non-finite values");
   }
   int S = 0;
   for (auto &b : tp->batches) S = std::max(S, b.second);
-  float *acc = nullptr, *imgs = nullptr, *gacc = nullptr;
+  double *acc = nullptr;
+  float *imgs = nullptr, *gacc = nullptr;
   GradWork wk;
   Carve cv;
   cv.add(&acc, img);
@@ -1906,7 +2142,7 @@ int fwime_backward_tape(fwime_ctx_t *ctx, fwime_tape_t *tp, const float *adjsrc,
   c.gx = tp->gx;
   c.tables = tp->tables;
   if ((rc = setup_common(ctx, c, g, tp->vel, st))) return rc;
-  HIPCHK(launch_zero(acc, img, st));
+  HIPCHK(launch_zero_d(acc, img, st));
   HIPCHK(launch_zero(gacc, d.field, st));
   tp->used = true;   // backward recomputes the segments in place over the checkpoints
   for (size_t bi = 0; bi < tp->batches.size(); ++bi) {
@@ -1950,6 +2186,7 @@ struct BatchPlan {
   std::vector<int> prefix;       // tiles before position k
   int total = 0;
   int nt_max = 0;
+  bool fs = false;               // some job has a free surface
   int stride() const { return two ? 2 : 1; }
   // launches until the longest job has sampled its last time
   long launches() const { return two ? (nt_max - 1) / 2 + 1 : nt_max; }
@@ -1973,8 +2210,10 @@ int batch_plan(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, int tx, Bat
   bp.prefix.assign(njobs + 1, 0);
   bp.total = 0;
   bp.nt_max = 0;
+  bp.fs = false;
   for (int k = 0; k < njobs; ++k) {
     const int j = bp.order[k];
+    bp.fs = bp.fs || jobs[j].grid.free_surface != 0;
     bp.com[k].d = make_dims(&jobs[j].grid, tx);
     const Dims &d = bp.com[k].d;
     bp.ts.push_back(build_table_set(d, &jobs[j].geom, {{0, jobs[j].geom.nshots}}, bp.two));
@@ -2003,12 +2242,15 @@ int batch_active_tiles(const BatchPlan &bp, long n) {
   return bp.prefix[k];
 }
 
-// one multi-job launch (one or two time steps) and the step-counter bump
-hipError_t batch_launch(const BatchPlan &bp, const void *djobs, int tiles, int *dstep, int tx, hipStream_t st) {
+// one multi-job launch (one or two time steps).  With a device step counter
+// (graph replay) the launch is followed by the counter's bump; without one
+// the global step is passed by value and nothing else is launched.
+hipError_t batch_launch(const BatchPlan &bp, const void *djobs, int tiles, int *dstep, int step_val, int tx,
+                        hipStream_t st) {
   const int nj = (int)bp.order.size();
-  hipError_t e = bp.two ? launch_step2_multi((const BatchJob2 *)djobs, nj, tiles, dstep, tx, st)
-                        : launch_step_multi((const BatchJob *)djobs, nj, tiles, dstep, tx, st);
-  if (e != hipSuccess) return e;
+  hipError_t e = bp.two ? launch_step2_multi((const BatchJob2 *)djobs, nj, tiles, dstep, step_val, tx, bp.fs, st)
+                        : launch_step_multi((const BatchJob *)djobs, nj, tiles, dstep, step_val, tx, bp.fs, st);
+  if (e != hipSuccess || !dstep) return e;
   return launch_bump(dstep, bp.stride(), st);
 }
 
@@ -2036,7 +2278,7 @@ int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, 
     const int j = bp.order[k];
     const Dims &d = bp.com[k].d;
     const int S = jobs[j].geom.nshots;
-    if ((rc = upload_tables(ctx, bp.ts[k], bp.com[k].tables, st))) return rc;
+    if ((rc = upload_tables(ctx, bp.ts[k], bp.com[k].tables, st, false))) return rc;
     if ((rc = setup_common(ctx, bp.com[k], &jobs[j].grid, jobs[j].vel, st))) return rc;
     HIPCHK(launch_zero(fields[k], nf * d.field * S, st));
     const DevTables &t = bp.ts[k].dev[0];
@@ -2094,14 +2336,14 @@ int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStre
     const void *host = bp.two ? (const void *)bp.jobs2.data() : (const void *)bp.jobs.data();
     const size_t jb_bytes = bp.two ? sizeof(BatchJob2) : sizeof(BatchJob);
     if (hipMemcpyAsync(dj, host, jb_bytes * njobs, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemsetAsync(dstep, 0, sizeof(int), st) != hipSuccess) {
+        launch_zero(reinterpret_cast<float *>(dstep), 1, st) != hipSuccess) {   // all-zero bits: int 0
       rc = set_err(ctx, FWIME_EHIP, "autotune setup failed");
       break;
     }
     const int warm = 2, timed = 8;
     for (int i = 0; i < warm + timed; ++i) {
       if (i == warm) (void)hipEventRecord(e0, st);
-      if (batch_launch(bp, dj, bp.total, dstep, tx, st) != hipSuccess) {
+      if (batch_launch(bp, dj, bp.total, dstep, 0, tx, st) != hipSuccess) {
         rc = set_err(ctx, FWIME_EHIP, "autotune launch failed");
         break;
       }
@@ -2141,8 +2383,21 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
     nt_steps = std::max<long>(nt_steps, jobs[j].grid.nt);
   }
   HIPCHK(hipSetDevice(ctx->device));
-  for (int j = 0; j < njobs; ++j)
-    if ((rc = check_inputs(ctx, &jobs[j].grid, jobs[j].vel, &jobs[j].geom, {}, st))) return rc;
+  {
+    // every job's velocity and wavelets in one device pass and one synchronization
+    std::vector<std::pair<const float *, long>> arrays;
+    for (int j = 0; j < njobs; ++j) {
+      if (!jobs[j].vel) return set_err(ctx, FWIME_EINVAL, "job velocity is null");
+      arrays.push_back({jobs[j].vel, (long)jobs[j].grid.nx * jobs[j].grid.nz});
+      arrays.push_back({jobs[j].geom.wavelet, (long)jobs[j].geom.nshots * jobs[j].grid.nt});
+    }
+    std::vector<double> r;
+    if ((rc = device_ranges(ctx, arrays, st, r))) return rc;
+    for (int j = 0; j < njobs; ++j) {
+      if ((rc = check_velocity_range(ctx, &jobs[j].grid, &r[6 * j]))) return rc;
+      if (r[6 * j + 5] > 0) return set_err(ctx, FWIME_ENONFINITE, "input array has non-finite values");
+    }
+  }
   release_graph(ctx);   // the input checks synchronized the stream: earlier replays are done
 
   const std::string sig = batch_signature(njobs, jobs);
@@ -2163,7 +2418,7 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   int *dstep = nullptr;
   if ((rc = batch_plan(ctx, njobs, jobs, tx, bp, nullptr))) return rc;
   if ((rc = batch_carve_and_setup(ctx, njobs, jobs, bp, &dj, &dstep, st))) return rc;
-  HIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), st));
+  HIPCHK(launch_zero(reinterpret_cast<float *>(dstep), 1, st));   // all-zero bits: int 0
 
   const int G = ctx->graph_steps;
   // Large batches: one direct launch per step over the still-running jobs
@@ -2172,7 +2427,10 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   const bool use_graph = !std::getenv("FWIME_NO_GRAPH") && bp.total <= kGraphMaxTiles;
   const long L = bp.launches();
   if (!use_graph) {
-    for (long i = 0; i < L; ++i) HIPCHK(batch_launch(bp, dj, batch_active_tiles(bp, i * bp.stride()), dstep, tx, st));
+    HIPCHK(timing_begin(ctx, st));
+    for (long i = 0; i < L; ++i)
+      HIPCHK(batch_launch(bp, dj, batch_active_tiles(bp, i * bp.stride()), nullptr, (int)(i * bp.stride()), tx, st));
+    HIPCHK(timing_end(ctx, st, L));
     return FWIME_OK;
   }
   hipGraph_t graph = nullptr;
@@ -2182,7 +2440,7 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
   if (!ctx->capture) HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
   hipError_t cap = hipSuccess;
-  for (int i = 0; i < G && cap == hipSuccess; ++i) cap = batch_launch(bp, dj, bp.total, dstep, tx, ctx->capture);
+  for (int i = 0; i < G && cap == hipSuccess; ++i) cap = batch_launch(bp, dj, bp.total, dstep, 0, tx, ctx->capture);
   hipError_t endc = hipStreamEndCapture(ctx->capture, &graph);
   if (cap != hipSuccess || endc != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -2193,8 +2451,10 @@ int fwime_model_batch(fwime_ctx_t *ctx, int32_t njobs, const fwime_job_t *jobs, 
     return set_err(ctx, FWIME_EHIP, "graph instantiation failed");
   }
   const long replays = (L + G - 1) / G;
+  HIPCHK(timing_begin(ctx, st));
   hipError_t le = hipSuccess;
   for (long r = 0; r < replays && le == hipSuccess; ++r) le = hipGraphLaunch(exec, st);
+  if (le == hipSuccess) HIPCHK(timing_end(ctx, st, replays * G));
   ctx->graph = graph;          // kept until the replays have certainly finished
   ctx->graph_exec = exec;
   if (le != hipSuccess) return set_err(ctx, FWIME_EHIP, "graph launch failed");
@@ -2212,9 +2472,9 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
   // field buffers of the two-step path (the larger of the two paths)
   switch (op) {
     case FWIME_OP_MODEL: per_shot = 4 * fb; break;
-    case FWIME_OP_BORN_FWD: per_shot = (8 + 2 * 16 + 2) * fb; fixed += img; break;
+    case FWIME_OP_BORN_FWD: per_shot = (8 + 2 * 16 + 4) * fb; fixed += img; break;
     case FWIME_OP_BORN_ADJ:
-      per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + pl.nseg) * fb;
+      per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + (pl.R + 1) / 2 + pl.nseg) * fb;
       fixed += (1 + kImageGroups) * img;
       break;
     case FWIME_OP_GRADIENT:
@@ -2225,6 +2485,289 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
   }
   *bytes = (size_t)(fixed + per_shot * nshots + (long)nrec * nshots * 64);
   return FWIME_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Continuous batching of modeling jobs (the request loop's engine).
+//
+// Jobs join a running multi-job time loop at the next round boundary and
+// leave it when their last sample is recorded.  A round advances every
+// active job by the same number of time steps in shared two-step launches
+// (k_step2_multi, one launch per two steps over the tiles of all active
+// jobs); a job's time index is the global step minus the step at which it
+// joined, so jobs of different lengths and arrival times share launches.
+// Per-job device memory (padded velocity, tapers, geometry tables, four
+// wavefield buffers per shot) is allocated stream-ordered on the engine's
+// stream when the job is submitted and freed the same way once its last
+// round has completed; the job descriptors of a round go to one slot of a
+// small device ring, reused only after that round's event has completed.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct EngineJob {
+  int64_t ticket = 0;
+  fwime_grid_t grid{};
+  fwime_geom_t geom{};
+  std::vector<int32_t> src_iz, src_ix, rec_iz, rec_ix;   // host copies of the geometry
+  Common com;
+  TableSet ts;
+  void *mem = nullptr;
+  BatchJob2 desc;
+  int tiles = 0;
+  long t0 = -1;            // global step at which the job's time index is 0
+};
+
+constexpr int kEngineRing = 4;
+
+}  // namespace
+
+struct fwime_engine {
+  fwime_ctx_t *ctx = nullptr;
+  hipStream_t st = nullptr;              // the engine's stream (all of its work)
+  int steps = 64;                        // time steps per round (even)
+  int max_jobs = 0;
+  long step = 0;                         // global step counter
+  int64_t next_ticket = 1;
+  std::vector<EngineJob *> pending, active;
+  std::vector<std::pair<EngineJob *, hipEvent_t>> finishing;
+  std::vector<hipEvent_t> free_events;
+  BatchJob2 *host_desc[kEngineRing] = {};
+  BatchJob2 *dev_desc[kEngineRing] = {};
+  hipEvent_t ring_ev[kEngineRing] = {};
+  bool ring_used[kEngineRing] = {};
+  int ring_i = 0;
+  long rounds = 0;
+  long launches = 0;
+};
+
+namespace {
+
+void engine_release_job(fwime_engine_t *e, EngineJob *j) {
+  if (j->mem) (void)hipFreeAsync(j->mem, e->st);
+  delete j;
+}
+
+hipError_t engine_event(fwime_engine_t *e, hipEvent_t *ev) {
+  if (!e->free_events.empty()) {
+    *ev = e->free_events.back();
+    e->free_events.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwime_engine_create(fwime_ctx_t *ctx, int32_t steps_per_round, int32_t max_jobs, void *stream,
+                        fwime_engine_t **out) {
+  if (!ctx || !out) return FWIME_EINVAL;
+  *out = nullptr;
+  if (steps_per_round < 2 || steps_per_round % 2 || max_jobs < 1)
+    return set_err(ctx, FWIME_EINVAL, "steps_per_round must be even and >= 2, max_jobs >= 1");
+  HIPCHK(hipSetDevice(ctx->device));
+  fwime_engine_t *e = new fwime_engine_t();
+  e->ctx = ctx;
+  e->st = (hipStream_t)stream;
+  e->steps = steps_per_round;
+  e->max_jobs = max_jobs;
+  const size_t bytes = sizeof(BatchJob2) * (size_t)max_jobs;
+  for (int i = 0; i < kEngineRing; ++i) {
+    if (hipHostMalloc((void **)&e->host_desc[i], bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&e->dev_desc[i], bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ring_ev[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      fwime_engine_destroy(e);
+      return set_err(ctx, FWIME_ENOMEM, "engine descriptor ring allocation failed");
+    }
+  }
+  *out = e;
+  return FWIME_OK;
+}
+
+int fwime_engine_submit(fwime_engine_t *e, const fwime_job_t *job, void *check_stream, int64_t *ticket) {
+  if (!e || !job || !ticket) return FWIME_EINVAL;
+  fwime_ctx_t *ctx = e->ctx;
+  ctx->err.clear();
+  int rc;
+  if ((rc = check_grid(ctx, &job->grid)) || (rc = check_geom(ctx, &job->grid, &job->geom))) return rc;
+  if (!job->data || !job->vel) return set_err(ctx, FWIME_EINVAL, "job data or velocity is null");
+  if ((long)e->pending.size() + (long)e->active.size() >= e->max_jobs)
+    return set_err(ctx, FWIME_ENOMEM, "the engine holds max_jobs jobs already");
+  HIPCHK(hipSetDevice(ctx->device));
+  {
+    // velocity range and finite wavelets, on the stream that produced them
+    std::vector<double> r;
+    hipStream_t cs = (hipStream_t)check_stream;
+    if ((rc = device_ranges(ctx, {{job->vel, (long)job->grid.nx * job->grid.nz},
+                                  {job->geom.wavelet, (long)job->geom.nshots * job->grid.nt}}, cs, r)))
+      return rc;
+    if ((rc = check_velocity_range(ctx, &job->grid, r.data()))) return rc;
+    if (r[5] > 0) return set_err(ctx, FWIME_ENONFINITE, "input array has non-finite values");
+  }
+  EngineJob *j = new EngineJob();
+  j->grid = job->grid;
+  j->geom = job->geom;
+  const long ns = job->geom.nshots, nr = (long)job->geom.nshots * job->geom.nrec;
+  j->src_iz.assign(job->geom.src_iz, job->geom.src_iz + ns);
+  j->src_ix.assign(job->geom.src_ix, job->geom.src_ix + ns);
+  j->rec_iz.assign(job->geom.rec_iz, job->geom.rec_iz + nr);
+  j->rec_ix.assign(job->geom.rec_ix, job->geom.rec_ix + nr);
+  j->geom.src_iz = j->src_iz.data();
+  j->geom.src_ix = j->src_ix.data();
+  j->geom.rec_iz = j->rec_iz.data();
+  j->geom.rec_ix = j->rec_ix.data();
+  Common &c = j->com;
+  c.d = make_dims(&j->grid, ctx->tile_x);
+  const Dims &d = c.d;
+  const int S = (int)ns;
+  j->ts = build_table_set(d, &j->geom, {{0, S}}, true);
+  float *fields = nullptr;
+  Carve cv;
+  cv.add(&c.V, d.field);
+  cv.add(&c.gz, d.LZ);
+  cv.add(&c.gx, d.NX + kGxPad);
+  cv.add(&c.tables, table_set_ints(j->ts) + 64 * 8);
+  cv.add(&fields, 4 * d.field * S);
+  if (ctx->budget && cv.total > ctx->budget) {
+    delete j;
+    return set_err(ctx, FWIME_ENOMEM, "the job exceeds the HBM budget");
+  }
+  if (hipMallocAsync(&j->mem, cv.total, e->st) != hipSuccess) {
+    (void)hipGetLastError();
+    delete j;
+    return set_err(ctx, FWIME_ENOMEM, "hipMallocAsync of " + std::to_string(cv.total) + " bytes failed");
+  }
+  cv.assign(j->mem);
+  // the blob stays alive in the job until it is released, after the copy
+  if ((rc = upload_tables(ctx, j->ts, c.tables, e->st, false)) || (rc = setup_common(ctx, c, &j->grid, job->vel, e->st)) ||
+      (launch_zero(fields, 4 * d.field * S, e->st) != hipSuccess ? (rc = FWIME_EHIP) : 0)) {
+    engine_release_job(e, j);
+    return rc ? rc : set_err(ctx, FWIME_EHIP, "engine job setup failed");
+  }
+  const DevTables &t = j->ts.dev[0];
+  BatchJob2 &bj = j->desc;
+  bj.p.a = batch_args(c, S, d.field);
+  bj.p.a.ntz = d.ntz2;
+  with_src2(bj.p, t, job->geom.wavelet, &j->grid, 0);
+  with_rec_extract(bj.p.a, t, job->data, j->grid.nt, 0);
+  for (int q = 0; q < 4; ++q) bj.buf[q] = fields + q * d.field * S;
+  bj.nt = j->grid.nt;
+  j->tiles = d.ntz2 * d.ntx * S;
+  j->ticket = e->next_ticket++;
+  e->pending.push_back(j);
+  *ticket = j->ticket;
+  return FWIME_OK;
+}
+
+int fwime_engine_run(fwime_engine_t *e) {
+  if (!e) return FWIME_EINVAL;
+  fwime_ctx_t *ctx = e->ctx;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  // jobs join at this round's boundary
+  for (EngineJob *j : e->pending) {
+    j->t0 = e->step;
+    j->desc.t0 = (int)e->step;
+    e->active.push_back(j);
+  }
+  e->pending.clear();
+  if (e->active.empty()) return FWIME_OK;
+  // descriptor slot of this round: free once the round that used it last is done
+  const int i = e->ring_i;
+  if (e->ring_used[i]) HIPCHK(hipEventSynchronize(e->ring_ev[i]));
+  int total = 0;
+  bool fs = false;
+  const int nj = (int)e->active.size();
+  for (int k = 0; k < nj; ++k) {
+    EngineJob *j = e->active[k];
+    j->desc.tile_begin = total;
+    total += j->tiles;
+    fs = fs || j->grid.free_surface != 0;
+    e->host_desc[i][k] = j->desc;
+  }
+  HIPCHK(hipMemcpyAsync(e->dev_desc[i], e->host_desc[i], sizeof(BatchJob2) * nj, hipMemcpyHostToDevice, e->st));
+  const int L = e->steps / 2;
+  for (int l = 0; l < L; ++l)
+    HIPCHK(launch_step2_multi(e->dev_desc[i], nj, total, nullptr, (int)(e->step + 2L * l), ctx->tile_x, fs, e->st));
+  HIPCHK(hipEventRecord(e->ring_ev[i], e->st));
+  e->ring_used[i] = true;
+  e->ring_i = (i + 1) % kEngineRing;
+  e->step += e->steps;
+  e->rounds += 1;
+  e->launches += L;
+  // jobs whose last sample (time index nt - 1) was recorded in this round leave
+  std::vector<EngineJob *> keep;
+  for (EngineJob *j : e->active) {
+    // the last launch of the round ran time index e->step - 2 - t0; the job
+    // recorded its last sample once that index reached nt - 2 (two-step
+    // launch) or nt - 1 (sample only): e->step - t0 >= nt, both being even
+    if (e->step - j->t0 >= (long)j->grid.nt) {
+      hipEvent_t ev;
+      HIPCHK(engine_event(e, &ev));
+      HIPCHK(hipEventRecord(ev, e->st));
+      e->finishing.push_back({j, ev});
+    } else {
+      keep.push_back(j);
+    }
+  }
+  e->active.swap(keep);
+  return FWIME_OK;
+}
+
+int fwime_engine_poll(fwime_engine_t *e, int64_t *tickets, int32_t cap, int32_t *ndone) {
+  if (!e || !ndone || (cap > 0 && !tickets)) return FWIME_EINVAL;
+  fwime_ctx_t *ctx = e->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  int n = 0;
+  std::vector<std::pair<EngineJob *, hipEvent_t>> keep;
+  for (auto &f : e->finishing) {
+    if (n < cap && hipEventQuery(f.second) == hipSuccess) {
+      tickets[n++] = f.first->ticket;
+      e->free_events.push_back(f.second);
+      engine_release_job(e, f.first);
+    } else {
+      (void)hipGetLastError();
+      keep.push_back(f);
+    }
+  }
+  e->finishing.swap(keep);
+  *ndone = n;
+  return FWIME_OK;
+}
+
+int fwime_engine_info(const fwime_engine_t *e, fwime_engine_info_t *out) {
+  if (!e || !out) return FWIME_EINVAL;
+  out->pending = (int32_t)e->pending.size();
+  out->active = (int32_t)e->active.size();
+  out->finishing = (int32_t)e->finishing.size();
+  out->step = e->step;
+  out->rounds = e->rounds;
+  out->launches = e->launches;
+  return FWIME_OK;
+}
+
+void fwime_engine_destroy(fwime_engine_t *e) {
+  if (!e) return;
+  (void)hipSetDevice(e->ctx->device);
+  if (e->st) (void)hipStreamSynchronize(e->st);
+  for (EngineJob *j : e->pending) engine_release_job(e, j);
+  for (EngineJob *j : e->active) engine_release_job(e, j);
+  for (auto &f : e->finishing) {
+    engine_release_job(e, f.first);
+    (void)hipEventDestroy(f.second);
+  }
+  if (e->st) (void)hipStreamSynchronize(e->st);
+  for (hipEvent_t ev : e->free_events) (void)hipEventDestroy(ev);
+  for (int i = 0; i < kEngineRing; ++i) {
+    if (e->host_desc[i]) (void)hipHostFree(e->host_desc[i]);
+    if (e->dev_desc[i]) (void)hipFree(e->dev_desc[i]);
+    if (e->ring_ev[i]) (void)hipEventDestroy(e->ring_ev[i]);
+  }
+  delete e;
 }
 
 }  // extern "C"

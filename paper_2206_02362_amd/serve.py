@@ -8,9 +8,16 @@ first come, first served: the head of the queue starts as soon as a slot is
 free and its device footprint (fwime_footprint for its operator, shot count
 and grid, plus its outputs) fits in what the running requests leave of the
 HBM budget.  A request that arrives while others run therefore starts on a
-free slot and its kernels overlap theirs on the device.  Modeling requests
-that wait back to back at the head of the queue are merged into one
-fwime_model_batch call (one launch per time step over all of their shots).
+free slot and its kernels overlap theirs on the device.
+
+Modeling requests are batched continuously (engine=True): they go to one
+fwime_engine, whose time loop runs in rounds of a fixed number of time steps
+on its own stream; a request admitted while the loop runs joins it at the
+next round boundary and shares every launch with the jobs already in it (each
+at its own time index), and leaves it when its last sample is recorded.  The
+server keeps at most two rounds in flight, so new jobs wait at most about a
+round.  With engine=False, modeling requests that wait back to back at the
+head of the queue are merged into one fwime_model_batch call instead.
 Completion is observed with events.  Each context keeps its scratch arena
 (checkpoints, wavefield rings, tables) between requests, so a slot reuses
 device memory instead of reallocating it; idle slots give their arenas back
@@ -28,8 +35,8 @@ from typing import Any, Callable
 import numpy as np
 import torch
 
-from ._abi import (FWIME_OP_BORN_ADJ, FWIME_OP_BORN_FWD, FWIME_OP_GRADIENT, FWIME_OP_MODEL, Context, Geometry,
-                   Grid, footprint)
+from ._abi import (FWIME_OP_BORN_ADJ, FWIME_OP_BORN_FWD, FWIME_OP_GRADIENT, FWIME_OP_MODEL, Context, Engine,
+                   Geometry, Grid, footprint)
 
 _OPS = {"model": FWIME_OP_MODEL, "born_fwd": FWIME_OP_BORN_FWD, "born_adj": FWIME_OP_BORN_ADJ,
         "gradient": FWIME_OP_GRADIENT}
@@ -64,6 +71,7 @@ class Request:
     error: Exception | None = None
     reserved: int = 0
     merged: int = 1                      # requests sharing this one's launch
+    ticket: int = -1                     # engine job (continuously batched modeling)
     _ready: Any = None
 
     @property
@@ -99,16 +107,68 @@ class _Slot:
     def trim(self):
         self.ctx.trim(self.stream.cuda_stream)
 
+    def close(self):
+        self.stream.synchronize()
+        self.ctx.close()
+
+
+class _EngineLane:
+    """The continuous-batching engine with its own stream and context, a
+    stream for checking newly admitted inputs, and the rounds in flight."""
+
+    def __init__(self, device: int, budget: int, steps: int, max_jobs: int = 512):
+        self.stream = torch.cuda.Stream(device)
+        self.check_stream = torch.cuda.Stream(device)
+        self.ctx = Context(device, budget)
+        self.engine = Engine(self.ctx, self.stream, steps, max_jobs)
+        self.inflight: collections.deque = collections.deque()
+        self.reqs: dict[int, Request] = {}
+
+    def submit(self, r: Request, vel: torch.Tensor) -> None:
+        with torch.cuda.stream(self.stream):
+            r.result = torch.empty((r.geom.nshots, r.geom.nrec, r.grid.nt), device=vel.device,
+                                   dtype=torch.float32)
+        self.check_stream.wait_event(r._ready)
+        r.ticket = self.engine.submit(r.grid, vel, r.geom, r.result, self.check_stream)
+        self.reqs[r.ticket] = r
+
+    def pump(self) -> None:
+        """Keep two rounds in flight while jobs remain."""
+        while self.inflight and self.inflight[0].query():
+            self.inflight.popleft()
+        while len(self.inflight) < 2:
+            inf = self.engine.info()
+            if inf["pending"] == 0 and inf["active"] == 0:
+                return
+            self.engine.run()
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+            self.inflight.append(ev)
+
+    def finished(self) -> list[Request]:
+        return [self.reqs.pop(t) for t in self.engine.poll()]
+
+    def busy(self) -> bool:
+        return bool(self.reqs)
+
+    def close(self):
+        self.engine.close()
+        self.stream.synchronize()
+        self.ctx.close()
+
 
 class Server:
-    """FIFO admission by HBM footprint onto `slots` concurrent streams.
+    """FIFO admission by HBM footprint onto `slots` concurrent streams, with
+    modeling requests continuously batched in one engine (engine=True).
 
     hbm_budget: bytes the running requests may hold together (default 80 % of
     the free device memory when the server starts).  merge_models: the most
-    modeling requests one batched call may serve (1 turns merging off).
+    modeling requests one batched call may serve when there is no engine (1
+    turns merging off).  engine_steps: time steps per engine round.
     """
 
     def __init__(self, device: int = 0, slots: int = 3, hbm_budget: int | None = None, merge_models: int = 8,
+                 engine: bool = False, engine_steps: int = 64,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
         self.device = device
         self.clock = clock
@@ -119,6 +179,7 @@ class Server:
         self.merge_models = max(1, int(merge_models))
         self.models: dict[Any, tuple[Grid, torch.Tensor]] = {}
         self.slots = [self._new_slot(k) for k in range(slots)]
+        self.lane = self._new_engine(engine_steps) if engine else None
         self.queue: collections.deque[Request] = collections.deque()
         self.done: list[Request] = []
         self.reserved = 0
@@ -133,6 +194,9 @@ class Server:
 
     def _new_slot(self, k: int):
         return _Slot(self.device, self.budget)
+
+    def _new_engine(self, steps: int):
+        return _EngineLane(self.device, self.budget, steps)
 
     def _need(self, req: Request) -> int:
         return request_bytes(req)
@@ -150,7 +214,7 @@ class Server:
 
     def grid_for(self, req: Request) -> Grid:
         g, _ = self.models[req.model]
-        return Grid(g.nz, g.nx, g.nb, req.nt, g.dz, g.dx, g.dt, g.sponge_alpha)
+        return Grid(g.nz, g.nx, g.nb, req.nt, g.dz, g.dx, g.dt, g.sponge_alpha, g.free_surface)
 
     # -- public -----------------------------------------------------------------
     def submit(self, req: Request, t_arrival: float | None = None) -> Request:
@@ -164,12 +228,22 @@ class Server:
         self.queue.append(req)
         return req
 
+    def close(self) -> None:
+        """Wait for the slots' and the engine's work and release their contexts."""
+        for s in self.slots:
+            s.close()
+        if self.lane is not None:
+            self.lane.close()
+
     def busy(self) -> bool:
-        return bool(self.queue) or any(s.reqs for s in self.slots)
+        return (bool(self.queue) or any(s.reqs for s in self.slots)
+                or (self.lane is not None and self.lane.busy()))
 
     def poll(self) -> None:
         self._retire()
         self._admit()
+        if self.lane is not None:
+            self.lane.pump()
 
     def drain(self) -> list[Request]:
         while self.busy():
@@ -221,6 +295,13 @@ class Server:
                     self.done.append(r)
                 s.reqs = []
                 s.event = None
+        if self.lane is not None:
+            fin = self.lane.finished()
+            t = self.clock()
+            for r in fin:
+                r.t_done = t
+                self.reserved -= r.reserved
+                self.done.append(r)
         held = sum(s.held_bytes() for s in self.slots)
         if held > self.budget:
             for s in self.slots:
@@ -231,14 +312,32 @@ class Server:
 
     def _admit(self):
         while self.queue:
-            k = next((k for k, s in enumerate(self.slots) if not s.reqs), None)
-            if k is None:
-                return
             head = self.queue[0]
+            to_engine = self.lane is not None and head.kind == "model"
+            k = None
+            if not to_engine:
+                k = next((k for k, s in enumerate(self.slots) if not s.reqs), None)
+                if k is None:
+                    return
             need = min(self._need(head), self.budget)
-            running = any(s.reqs for s in self.slots)
+            running = any(s.reqs for s in self.slots) or (self.lane is not None and self.lane.busy())
             if running and self.reserved + need > self.budget:
                 return                      # first come, first served: wait for memory
+            if to_engine:
+                self.queue.popleft()
+                head.reserved = need
+                self.reserved += need
+                self.peak_reserved = max(self.peak_reserved, self.reserved)
+                head.t_admit = self.clock()
+                self.admit_order.append(head.id)
+                try:
+                    self._engine_submit(head)
+                except Exception as e:      # reported on the request; the server keeps going
+                    head.error = e
+                    head.t_done = self.clock()
+                    self.reserved -= need
+                    self.done.append(head)
+                continue
             group = [self.queue.popleft()]
             head.reserved = need
             total = need
@@ -260,6 +359,10 @@ class Server:
                 r.merged = len(group)
                 self.admit_order.append(r.id)
             self._start(self.slots[k], group)
+
+    def _engine_submit(self, r: Request):
+        _, vel = self.models[r.model]
+        self.lane.submit(r, vel)
 
     def _start(self, s: _Slot, group: list[Request]):
         s.reqs = group

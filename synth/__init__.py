@@ -270,7 +270,8 @@ def serve_mix(nreq: int = 24, seed: int = 42, rate: float = 20.0, npool: int = 6
               nz_choices=tuple(range(200, 601, 100)), nx_choices=tuple(range(600, 3001, 200)),
               shots=(1, 32), nt_choices=tuple(range(2000, 6001, 500)), dt: float = 8e-4, dx: float = 10.0,
               nb: int = 40, nh: int = 11,
-              mix=(("model", 0.4), ("born_fwd", 0.15), ("born_adj", 0.15), ("gradient", 0.3))) -> ServeMix:
+              mix=(("model", 0.4), ("born_fwd", 0.15), ("born_adj", 0.15), ("gradient", 0.3)),
+              velocities: bool = True) -> ServeMix:
     """Seeded Poisson request stream over a pool of resident velocity models.
 
     Inter-arrival times are exponential with mean 1/rate.  The pool holds
@@ -278,25 +279,30 @@ def serve_mix(nreq: int = 24, seed: int = 42, rate: float = 20.0, npool: int = 6
     sizes are drawn uniformly from the nz/nx choices; each request picks a
     pool model uniformly, a kind from `mix`, a shot count uniform in `shots`
     (sources at distinct random columns), nt from `nt_choices` and a Ricker
-    peak U(6, 12) Hz.  Receivers sit on every column at 20 m depth."""
+    peak U(6, 12) Hz.  Receivers sit on every column at 20 m depth.  Requests
+    are drawn one after the other, so a shorter stream is a prefix of a longer
+    one with the same seed.  velocities=False leaves the pool's velocity
+    arrays out (None): the request stream is the same."""
     rng = np.random.default_rng(seed)
     pool = []
     for i in range(npool):
         nz = int(rng.choice(nz_choices))
         nx = int(rng.choice(nx_choices))
-        pool.append((nz, nx, smooth_random_velocity(nz, nx, dx, seed + 1 + i, 1500.0, 4500.0, 300.0)))
+        v = smooth_random_velocity(nz, nx, dx, seed + 1 + i, 1500.0, 4500.0, 300.0) if velocities else None
+        pool.append((nz, nx, v))
     kinds = [k for k, _ in mix]
     probs = np.array([p for _, p in mix], dtype=np.float64)
     probs /= probs.sum()
-    t = np.cumsum(rng.exponential(1.0 / rate, nreq))
     reqs = []
+    t_now = 0.0
     for r in range(nreq):
+        t_now += float(rng.exponential(1.0 / rate))
         kind = str(rng.choice(kinds, p=probs))
         m = int(rng.integers(npool))
         nx = pool[m][1]
         ns = int(rng.integers(shots[0], shots[1] + 1))
         src = np.sort(rng.choice(nx, size=min(ns, nx), replace=False)).astype(np.int32)
-        reqs.append(ServeRequestSpec(float(t[r]), kind, m, src, int(rng.choice(nt_choices)),
+        reqs.append(ServeRequestSpec(t_now, kind, m, src, int(rng.choice(nt_choices)),
                                      float(rng.uniform(6.0, 12.0)), seed * 1000 + r))
     return ServeMix(pool, reqs, nb, dx, dt, nh)
 

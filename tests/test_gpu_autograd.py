@@ -36,15 +36,13 @@ def _dev(a):
     return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda:0")
 
 
-def test_autograd_matches_oracle_gradient(ctx):
+def _autograd_vs_oracle(ctx, w, seed):
     import torch
     import paper_2206_02362_amd as fw
-    say("case: autograd vs oracle, tiny nh5")
-    w = synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5, seed=3)
     g, geo, vel = oracle_problem_f32(w)
-    true = vel + 120.0 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 41, 80.0)
+    true = vel + 120.0 * synth.gaussian_perturbation(w.nz, w.nx, w.dx, 41 + seed, 80.0)
     dobs = oracle.model(g, true, geo).astype(np.float32)
-    pt = (0.2 * np.random.default_rng(5).standard_normal((w.nh, w.nx, w.nz))).astype(np.float32)
+    pt = (0.2 * np.random.default_rng(5 + seed).standard_normal((w.nh, w.nx, w.nz))).astype(np.float32)
     obj_r, gv_r, gp_r = oracle.gradient(g, vel, geo, pt.astype(np.float64), dobs.astype(np.float64), 0.0,
                                         np.ones(w.nh))
     grid, tv, tg = gpu_problem(w)
@@ -58,6 +56,17 @@ def test_autograd_matches_oracle_gradient(ctx):
     e_gp = rel_l2(p.grad.double().cpu().numpy(), gp_r)
     say("  obj", e_obj, "grad_vel", e_gv, "grad_ptilde", e_gp)
     assert e_obj < 1e-4 and e_gv < 1e-4 and e_gp < 1e-4
+
+
+def test_autograd_matches_oracle_gradient(ctx):
+    say("case: autograd vs oracle, tiny nh5")
+    _autograd_vs_oracle(ctx, synth.tiny(nz=24, nx=32, nb=8, nt=160, nshots=2, nh=5, seed=3), 0)
+
+
+def test_autograd_matches_oracle_gradient_plain_small(ctx):
+    # the 100 x 200 problem at its full length: nt = 1500, 11 offsets
+    say("case: autograd vs oracle, 100x200 nt1500 nh11")
+    _autograd_vs_oracle(ctx, synth.plain_small(), 1)
 
 
 def test_tape_serves_one_backward(ctx):

@@ -1,9 +1,10 @@
 """Batched modeling of jobs with different grids (fwime_model_batch).
 
-Each job's data must equal what fwime_model computes for that job alone,
-bit for bit (the per-cell arithmetic does not depend on the launch), with and
-without the captured graph, across graph replays interleaved with eager work,
-and for whichever tile width the autotuner picks.
+Each job's data must match the FP64 oracle for that job (relative L2 <= 1e-4)
+and equal what fwime_model computes for that job alone, bit for bit (the
+per-cell arithmetic does not depend on the launch), with and without the
+captured graph, across graph replays interleaved with eager work, and for
+whichever tile width the autotuner picks.
 """
 import os
 import sys
@@ -11,8 +12,9 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import synth
-from _helpers import gpu_problem
+from _helpers import gpu_problem, oracle_problem_f32, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +68,37 @@ def test_batch_equals_single_calls(ctx):
     assert ctx.info()["tuned_signatures"] == info1["tuned_signatures"]
     for r, o in zip(ref, out2):
         assert np.array_equal(r, o)
+
+
+def test_batch_matches_oracle(ctx):
+    # every job of an uneven batch (three grids, 1-3 shots, different nt and
+    # strips) against the FP64 oracle, on the direct-launch path and on the
+    # graph path
+    import torch
+    say("case: batch of 3 uneven jobs vs oracle.model")
+    ws = _jobs_small()
+    refs = []
+    for w in ws:
+        g, geo, vel = oracle_problem_f32(w)
+        refs.append(oracle.model(g, vel, geo))
+    old = os.environ.pop("FWIME_NO_GRAPH", None)
+    try:
+        for no_graph in ("1", None):
+            if no_graph:
+                os.environ["FWIME_NO_GRAPH"] = no_graph
+            else:
+                os.environ.pop("FWIME_NO_GRAPH", None)
+            out = _run_batch(ctx, ws)
+            torch.cuda.synchronize()
+            for w, r, o in zip(ws, refs, out):
+                e = rel_l2(o, r)
+                say(f"  {w.name} nt {w.nt} shots {w.nshots} graph {no_graph is None}: rel-L2 {e:.3e}")
+                assert e < 1e-4
+    finally:
+        if old is not None:
+            os.environ["FWIME_NO_GRAPH"] = old
+        else:
+            os.environ.pop("FWIME_NO_GRAPH", None)
 
 
 def test_batch_graph_replays_with_eager_work_between(ctx):

@@ -7,12 +7,15 @@ request is then run alone, one at a time, on a fresh context.  Modeling
 results must agree bit for bit (the per-cell arithmetic does not depend on
 the launch); the others to relative L2 <= 1e-6 (only the order of the
 per-shot sums may differ, when free memory splits the shots differently).
+Every served result of a small mix is also compared with the FP64 oracle
+(relative L2 <= 1e-4).
 """
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from _helpers import rel_l2, serve_setup
 
@@ -68,12 +71,13 @@ def _small_mix(seed):
                            nb=8, nh=5)
 
 
-def test_serve_mix_equals_alone():
+@pytest.mark.parametrize("engine", [True, False])
+def test_serve_mix_equals_alone(engine):
     import torch
     from paper_2206_02362_amd.serve import Server
-    say("case: 14-request mix, 3 slots, merging on")
+    say(f"case: 14-request mix, 3 slots, {'continuous batching engine' if engine else 'merging at admission'}")
     mix = _small_mix(5)
-    srv = Server(0, slots=3)
+    srv = Server(0, slots=3, engine=engine, engine_steps=16)
     reqs = serve_setup(mix, srv)
     torch.cuda.synchronize()
     srv.replay(reqs, [s.arrival for s in mix.requests])
@@ -83,6 +87,47 @@ def test_serve_mix_equals_alone():
     say("  merged groups:", sorted({r.merged for r in reqs}), "kinds:", [r.kind for r in reqs])
     worst = _compare(reqs, _alone(reqs, srv))
     say("  worst rel L2 (non-modeling):", worst)
+    srv.close()
+
+
+def _oracle_result(r, server):
+    """The FP64 oracle's result for a served request (float32 inputs as float64)."""
+    grid = server.grid_for(r)
+    gm, vel = server.models[r.model]
+    g = oracle.Grid(grid.nz, grid.nx, grid.nb, grid.nt, grid.dz, grid.dx, grid.dt, grid.sponge_alpha)
+    h = lambda t: t.detach().double().cpu().numpy()
+    geo = oracle.Geometry(r.geom.src_iz, r.geom.src_ix, r.geom.rec_iz, r.geom.rec_ix, h(r.geom.wavelet))
+    v = h(vel)
+    if r.kind == "model":
+        return oracle.model(g, v, geo)
+    if r.kind == "born_fwd":
+        return oracle.born_ext_fwd(g, v, geo, h(r.ptilde))
+    if r.kind == "born_adj":
+        return oracle.born_ext_adj(g, v, geo, h(r.data), r.nh)
+    return oracle.gradient(g, v, geo, h(r.ptilde), h(r.dobs), r.eps, r.dso)
+
+
+def test_serve_mix_matches_oracle():
+    import torch
+    from paper_2206_02362_amd.serve import Server
+    say("case: 14-request mix, 3 slots and the engine, every result vs the oracle")
+    mix = _small_mix(5)
+    srv = Server(0, slots=3, engine=True, engine_steps=16)
+    reqs = serve_setup(mix, srv)
+    torch.cuda.synchronize()
+    srv.replay(reqs, [s.arrival for s in mix.requests])
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert r.error is None, (r.id, r.kind, r.error)
+        ref = _oracle_result(r, srv)
+        if r.kind == "gradient":
+            obj, gv, gp = r.result
+            e = max(abs(float(obj.item()) - ref[0]) / abs(ref[0]), rel_l2(gv.cpu().numpy(), ref[1]),
+                    rel_l2(gp.cpu().numpy(), ref[2]))
+        else:
+            e = rel_l2(r.result.cpu().numpy(), ref)
+        say(f"  request {r.id} {r.kind} shots {r.geom.nshots} nt {r.grid.nt} merged {r.merged}: {e:.3e}")
+        assert e < 1e-4, (r.id, r.kind, e)
 
 
 def test_serve_tight_budget_waits_and_matches():
@@ -95,7 +140,7 @@ def test_serve_tight_budget_waits_and_matches():
     for r in reqs:
         r.grid = probe.grid_for(r)
     budget = int(1.5 * max(request_bytes(r) for r in reqs))
-    srv = Server(0, slots=4, hbm_budget=budget)
+    srv = Server(0, slots=4, hbm_budget=budget, engine=True, engine_steps=32)
     srv.models = probe.models
     torch.cuda.synchronize()
     srv.replay(reqs, [s.arrival for s in mix.requests])
@@ -109,7 +154,7 @@ def test_serve_full_size_grids_short_time():
     from paper_2206_02362_amd.serve import Server
     say("case: request mix on 200x600 .. 600x3000 grids, 1-32 shots, nt capped at 200")
     mix = synth.serve_mix(nreq=8, seed=42)
-    srv = Server(0, slots=3)
+    srv = Server(0, slots=3, engine=True)
     reqs = serve_setup(mix, srv, nt_cap=200)
     torch.cuda.synchronize()
     srv.replay(reqs, [s.arrival for s in mix.requests])

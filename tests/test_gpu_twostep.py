@@ -100,11 +100,7 @@ def test_two_step_born_and_gradient_bitwise(nt):
     for name, a, b in zip(("born_fwd", "born_adj", "obj", "grad_vel", "grad_ptilde"), outs[0], outs[1]):
         say(f"  {name}: max |diff| {np.abs(a - b).max():.3e} (max |x| {np.abs(a).max():.3e})")
         assert np.abs(a).max() > 0
-        if name == "obj":
-            # FP64 sum of squares combined across workgroups with atomics:
-            # its rounding order is not fixed even between identical runs
-            assert abs(a[0] - b[0]) <= 1e-12 * abs(a[0]), name
-        elif name.startswith("born"):
+        if name.startswith("born"):
             # the two-step path carries the Born background in extended
             # precision (FP32 + BF16 residual): close, not identical
             e = np.linalg.norm(a - b) / np.linalg.norm(a)

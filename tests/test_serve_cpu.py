@@ -31,6 +31,31 @@ class FakeSlot:
         self.trims += 1
 
 
+class FakeLane:
+    """Continuous-batching engine on the virtual clock: a job joins at once
+    and runs r.tag['dur'] seconds beside the others."""
+
+    def __init__(self, srv):
+        self.srv = srv
+        self.reqs = {}
+        self.joined = []
+
+    def submit(self, r, vel):
+        r.ticket = len(self.joined)
+        self.joined.append((r.ticket, self.srv.t))
+        self.reqs[r.ticket] = (r, self.srv.t + r.tag["dur"])
+
+    def pump(self):
+        pass
+
+    def finished(self):
+        out = [t for t, (r, f) in self.reqs.items() if self.srv.t >= f]
+        return [self.reqs.pop(t)[0] for t in out]
+
+    def busy(self):
+        return bool(self.reqs)
+
+
 class FakeServer(Server):
     """Virtual clock; request r runs r.tag['dur'] seconds and needs r.tag['bytes']."""
 
@@ -45,6 +70,9 @@ class FakeServer(Server):
 
     def _new_slot(self, k):
         return FakeSlot()
+
+    def _new_engine(self, steps):
+        return FakeLane(self)
 
     def _need(self, r):
         return r.tag["bytes"]
@@ -158,6 +186,39 @@ def test_merge_respects_budget():
     done = srv.replay(reqs, [0.0] * 4)
     assert [r.merged for r in sorted(done, key=lambda r: r.id)] == [2, 2, 2, 2]
     assert srv.peak_reserved <= 1000
+
+
+def test_engine_takes_modeling_requests_as_they_arrive():
+    # modeling requests join the engine at once, beside one another and beside
+    # slot work, without waiting for a free slot; arrival order and the
+    # budget still hold
+    srv = FakeServer(slots=1, hbm_budget=1000, engine=True)
+    blocker = _req("gradient", 300, 1.0)
+    models = [_req("model", 100, 0.3) for _ in range(4)]
+    done = srv.replay([blocker] + models, [0.0, 0.1, 0.2, 0.25, 0.3])
+    t = {r.id: r for r in done}
+    for i in range(1, 5):
+        assert t[i].t_admit == pytest.approx(t[i].t_arrival, abs=2e-3)   # no wait for the busy slot
+        assert t[i].t_done < t[0].t_done
+    assert len(srv.lane.joined) == 4 and srv.admit_order == [0, 1, 2, 3, 4]
+    assert srv.peak_reserved <= 1000 and srv.reserved == 0
+
+
+def test_engine_respects_budget_and_arrival_order():
+    srv = FakeServer(slots=2, hbm_budget=1000, engine=True)
+    a = _req("model", 700, 0.5)
+    b = _req("model", 500, 0.2)         # does not fit beside a: waits
+    c = _req("born_fwd", 100, 0.1)      # would fit, but must not overtake b
+    done = srv.replay([a, b, c], [0.0, 0.01, 0.02])
+    t = {r.id: r for r in done}
+    assert t[1].t_admit >= t[0].t_done - 1e-9
+    assert t[2].t_admit >= t[1].t_admit
+    assert srv.peak_reserved <= 1000
+    reqs, arr = _poisson(3, 60, 1000)
+    srv = FakeServer(slots=3, hbm_budget=1000, engine=True)
+    done = srv.replay(reqs, arr)
+    assert len(done) == 60 and srv.reserved == 0 and srv.peak_reserved <= 1000
+    assert srv.admit_order == sorted(srv.admit_order)
 
 
 def test_idle_arenas_trimmed_over_budget():
