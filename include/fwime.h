@@ -103,6 +103,24 @@ void fwime_ctx_destroy(fwime_ctx_t *ctx);
 int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
                 const fwime_geom_t *geom, float *data, void *stream);
 
+/* Allocation-free modeling, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and same results, bit for bit, as fwime_model,
+ * but every piece of device scratch (validation partials, padded velocity,
+ * tapers, geometry tables, wavefields) is carved from one static device array
+ * of FWIME_STATIC_SCRATCH_BYTES that the library holds on each device until
+ * the process ends; the call allocates no device or pinned host memory (its
+ * host-side table construction uses ordinary heap memory).  Shots run in as
+ * many batches as the array needs; if one shot's scratch does not fit,
+ * the call returns FWIME_ENOMEM and writes nothing.  Every call on a device
+ * shares that device's array, which keeps the last call's contents (the call
+ * clears what must start at zero): calls that overlap on one device, from any
+ * context or stream, race and must be serialized by the caller.  Like every
+ * entry point it validates its inputs with one stream synchronization. */
+#define FWIME_STATIC_SCRATCH_BYTES (64u << 20)
+int fwime_model_static(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,
+                       const fwime_geom_t *geom, float *data, void *stream);
+
 /* Extended Born modeling B~(m) p~ (the data-correcting term of eq. fwime.obj).
  * ptilde: DEVICE [nh][nx][nz]; nh odd, 1 <= nh <= 2 nx - 1; data as above. */
 int fwime_born_ext_fwd(fwime_ctx_t *ctx, const fwime_grid_t *grid, const float *vel,

@@ -26,7 +26,7 @@ FWIME_OP_MODEL, FWIME_OP_BORN_FWD, FWIME_OP_BORN_ADJ, FWIME_OP_GRADIENT = 0, 1, 
 
 EXPORTED = ("fwime_ctx_create", "fwime_ctx_destroy", "fwime_ctx_info", "fwime_ctx_set_timing", "fwime_ctx_trim",
             "fwime_footprint",
-            "fwime_model", "fwime_born_ext_fwd",
+            "fwime_model", "fwime_model_static", "fwime_born_ext_fwd",
             "fwime_born_ext_adj", "fwime_born_ext_tau_fwd", "fwime_born_ext_tau_adj", "fwime_gradient", "fwime_gradient_tau", "fwime_vp_solve", "fwime_vp_solve_tau", "fwime_spline_apply", "fwime_spline_adjoint", "fwime_spline_refine", "fwime_lbfgs_direction", "fwime_lbfgs_minimize", "fwime_model_batch", "fwime_engine_create", "fwime_engine_submit", "fwime_engine_run", "fwime_engine_poll",
             "fwime_engine_info", "fwime_engine_destroy", "fwime_forward_tape",
             "fwime_backward_tape", "fwime_tape_free", "fwime_strerror", "fwime_last_error")
@@ -90,6 +90,8 @@ def load() -> ctypes.CDLL:
     lib.fwime_ctx_destroy.restype = None
     lib.fwime_model.argtypes = [P, P, P, P, P, P]
     lib.fwime_model.restype = I
+    lib.fwime_model_static.argtypes = [P, P, P, P, P, P]
+    lib.fwime_model_static.restype = I
     lib.fwime_born_ext_fwd.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
     lib.fwime_born_ext_fwd.restype = I
     lib.fwime_born_ext_adj.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
@@ -249,6 +251,14 @@ class Context:
         g = grid._c()
         ge = geom._c()
         self._check(self._lib.fwime_model(
+            self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge),
+            _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _stream(vel.device)))
+
+    def fwime_model_static(self, grid: Grid, vel, geom: Geometry, data):
+        """fwime_model with its scratch in the library's static device array (no allocation)."""
+        g = grid._c()
+        ge = geom._c()
+        self._check(self._lib.fwime_model_static(
             self._h, ctypes.byref(g), _dptr(vel, (grid.nx, grid.nz)), ctypes.byref(ge),
             _dptr(data, (geom.nshots, geom.nrec, grid.nt)), _stream(vel.device)))
 

@@ -27,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,11 @@ struct fwime_ctx {
   bool timing = false;
   hipEvent_t tev[2] = {nullptr, nullptr};
   long timed_launches = -1;               // launches between the events of the last timed call
+  // while set, the call's scratch is carved from this fixed device buffer
+  // instead of the arena, and nothing is allocated (fwime_model_static)
+  char *fixed = nullptr;
+  size_t fixed_bytes = 0;
+  char *static_scratch = nullptr;         // device address of the static scratch array on `device`
 };
 
 static void release_graph(fwime_ctx_t *ctx) {
@@ -150,6 +156,14 @@ struct Carve {
 };
 
 int arena_get(fwime_ctx_t *ctx, Carve &cv) {
+  if (ctx->fixed) {
+    if (cv.total > ctx->fixed_bytes)
+      return set_err(ctx, FWIME_ENOMEM, "the call needs " + std::to_string(cv.total) +
+                                            " bytes of scratch; the static scratch array holds " +
+                                            std::to_string(ctx->fixed_bytes));
+    cv.assign(ctx->fixed);
+    return FWIME_OK;
+  }
   if (cv.total > ctx->arena_bytes) {
     if (ctx->budget && cv.total > ctx->budget)
       return set_err(ctx, FWIME_ENOMEM, "request of " + std::to_string(cv.total) + " bytes exceeds the HBM budget");
@@ -234,6 +248,7 @@ int check_nh(fwime_ctx_t *ctx, const fwime_grid_t *g, int nh) {
 // Pinned host space for at least n doubles of reduction results.
 int host_red_reserve(fwime_ctx_t *ctx, size_t n) {
   if (n <= ctx->host_red_n) return FWIME_OK;
+  if (ctx->fixed) return set_err(ctx, FWIME_ENOMEM, "too many arrays to validate without allocating");
   if (ctx->host_red) HIPCHK(hipHostFree(ctx->host_red));
   ctx->host_red = nullptr;
   ctx->host_red_n = 0;
@@ -706,11 +721,16 @@ int march2_back_lambda(fwime_ctx_t *ctx, const Common &c, float *ring, long ring
 }
 
 int choose_batch(fwime_ctx_t *ctx, long per_shot_bytes, size_t fixed_bytes, int nshots) {
-  size_t avail = 0, total = 0;
-  if (hipMemGetInfo(&avail, &total) != hipSuccess) avail = 0;
-  avail += ctx->arena_bytes;               // the arena can be reused
-  size_t cap = (size_t)(avail * 0.85);
-  if (ctx->budget && ctx->budget < cap) cap = ctx->budget;
+  size_t cap = 0;
+  if (ctx->fixed) {
+    cap = ctx->fixed_bytes;                // the static scratch array is all there is
+  } else {
+    size_t avail = 0, total = 0;
+    if (hipMemGetInfo(&avail, &total) != hipSuccess) avail = 0;
+    avail += ctx->arena_bytes;             // the arena can be reused
+    cap = (size_t)(avail * 0.85);
+    if (ctx->budget && ctx->budget < cap) cap = ctx->budget;
+  }
   if (cap <= fixed_bytes) return 1;
   long S = (long)((cap - fixed_bytes) / std::max<long>(per_shot_bytes, 1));
   S = std::max<long>(1, std::min<long>(S, nshots));
@@ -759,6 +779,41 @@ const char *fwime_strerror(int code) {
 
 const char *fwime_last_error(const fwime_ctx_t *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Static scratch for the allocation-free entry point (fwime_model_static).
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is looked up once per device (fwime_ctx_create, with that
+// device current) and only that address is ever passed to kernels or copies.
+// Every call on a device shares its array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[FWIME_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device).
+int static_scratch_address(int device, char **out) {
+  if (device < 0 || device >= kMaxDevices) return FWIME_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return FWIME_EHIP;
+    }
+    g_scratch_ptr[device] = (char *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return FWIME_OK;
+}
+}  // namespace
+
+extern "C" {
+
 
 int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   if (!out) return FWIME_EINVAL;
@@ -770,6 +825,11 @@ int fwime_ctx_create(int device, size_t hbm_budget_bytes, fwime_ctx_t **out) {
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
   if (host_red_reserve(ctx, 64) != FWIME_OK) {
+    delete ctx;
+    return FWIME_EHIP;
+  }
+  if (static_scratch_address(device, &ctx->static_scratch) != FWIME_OK) {
+    (void)hipHostFree(ctx->host_red);
     delete ctx;
     return FWIME_EHIP;
   }
@@ -914,6 +974,23 @@ int fwime_model(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const
   }
   HIPCHK(timing_end(ctx, st, launches));
   return FWIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+int fwime_model_static(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, const fwime_geom_t *geo,
+                       float *data, void *stream) {
+  if (!ctx) return FWIME_EINVAL;
+  if (!ctx->static_scratch) return set_err(ctx, FWIME_EHIP, "the static scratch array has no device address");
+  // every piece of scratch (validation partials, padded velocity, tapers,
+  // geometry tables, wavefields) comes from the static array; shots run in as
+  // many batches as it needs, and a call that cannot fit one shot fails
+  // with FWIME_ENOMEM before anything is written
+  ctx->fixed = ctx->static_scratch;
+  ctx->fixed_bytes = FWIME_STATIC_SCRATCH_BYTES;
+  const int rc = fwime_model(ctx, g, vel, geo, data, stream);
+  ctx->fixed = nullptr;
+  ctx->fixed_bytes = 0;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
