@@ -63,10 +63,10 @@ __device__ __forceinline__ unsigned short f32_bf16(float f) {   // round to near
 }
 
 // u = g (2 (c + cl) - g (p + pl) + r) in FP64, split into FP32 hi and BF16 lo
-__device__ __forceinline__ float df_update(float g, float c, float cl, float pv, float pl, float r,
+__device__ __forceinline__ float df_update(float g, float c, float cl, float pv, float pl, double r,
                                            unsigned short &lo) {
   const double gd = g;
-  const double ex = gd * (2.0 * ((double)c + (double)cl) - gd * ((double)pv + (double)pl) + (double)r);
+  const double ex = gd * (2.0 * ((double)c + (double)cl) - gd * ((double)pv + (double)pl) + r);
   const float hi = (float)ex;
   lo = f32_bf16((float)(ex - (double)hi));
   return hi;
@@ -322,12 +322,21 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       const float *col = base + j * ROWS;
       const float c = col[0];
       float lap = 0.f;
+      // extended precision: the neighbour differences (exact or nearly, in
+      // FP32) are summed and weighted in FP64, so the Laplacian carries no
+      // FP32 accumulation error into the update
+      [[maybe_unused]] double lapd = 0.0;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
         dxf[k - 1][j] = col[k * ROWS] - c;
         const float back = j >= k ? -dxf[k - 1][j - k] : col[-k * ROWS] - c;
-        lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
+        if constexpr (DF) {
+          lapd = fma((double)a.cz[k - 1], (double)(col[-k] - c) + (double)(col[k] - c), lapd);
+          lapd = fma((double)a.cx[k - 1], (double)back + (double)dxf[k - 1][j], lapd);
+        } else {
+          lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
+          lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
+        }
       }
       float cl = 0.f;
       if constexpr (DF) {
@@ -339,16 +348,18 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
           lapl += a.cz[k - 1] * (bf16_f32(cll[-k]) + bf16_f32(cll[k]));
           lapl += a.cx[k - 1] * (bf16_f32(cll[-k * ROWS]) + bf16_f32(cll[k * ROWS]));
         }
-        lap += lapl;
+        lapd += (double)lapl;
       }
       const int x = xs1 + j;
       const bool xin = x >= 0 && x < NX;     // wave-uniform
       // computed for every lane; cells outside the grid are set to zero
       const float g = gzv * gx1[j];
-      const float r = vv1[j] * (lap + ds1[j]);
+      [[maybe_unused]] double r64 = 0.0;
+      if constexpr (DF) r64 = (double)vv1[j] * (lapd + (double)ds1[j]);
+      const float r = DF ? (float)r64 : vv1[j] * (lap + ds1[j]);
       unsigned short u1l = 0;
       float u1;
-      if constexpr (DF) u1 = df_update(g, c, cl, pv[j], pl[j], r, u1l);
+      if constexpr (DF) u1 = df_update(g, c, cl, pv[j], pl[j], r64, u1l);
       else u1 = g * (2.f * c - g * pv[j] + r);
       if (!(xin && zin)) {
         u1 = 0.f;
@@ -431,12 +442,21 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
       const float *col = base + j * ROWS;
       const float c = col[0];
       float lap = 0.f;
+      // extended precision: the neighbour differences (exact or nearly, in
+      // FP32) are summed and weighted in FP64, so the Laplacian carries no
+      // FP32 accumulation error into the update
+      [[maybe_unused]] double lapd = 0.0;
 #pragma unroll
       for (int k = 1; k <= kR; ++k) {
         dxf[k - 1][j] = col[k * ROWS] - c;
         const float back = j >= k ? -dxf[k - 1][j - k] : col[-k * ROWS] - c;
-        lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
-        lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
+        if constexpr (DF) {
+          lapd = fma((double)a.cz[k - 1], (double)(col[-k] - c) + (double)(col[k] - c), lapd);
+          lapd = fma((double)a.cx[k - 1], (double)back + (double)dxf[k - 1][j], lapd);
+        } else {
+          lap += a.cz[k - 1] * ((col[-k] - c) + (col[k] - c));
+          lap += a.cx[k - 1] * (back + dxf[k - 1][j]);
+        }
       }
       float cl = 0.f;
       if constexpr (DF) {
@@ -448,16 +468,18 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
           lapl += a.cz[k - 1] * (bf16_f32(cll[-k]) + bf16_f32(cll[k]));
           lapl += a.cx[k - 1] * (bf16_f32(cll[-k * ROWS]) + bf16_f32(cll[k * ROWS]));
         }
-        lap += lapl;
+        lapd += (double)lapl;
       }
       const int x = xs2 + j;
       const bool xin = x < NX;               // wave-uniform
       const float g = gzv * gx2[j];
       const float un = base0[j * ROWS];
-      const float r = vv2[j] * (lap + ds2[j]);
+      [[maybe_unused]] double r64 = 0.0;
+      if constexpr (DF) r64 = (double)vv2[j] * (lapd + (double)ds2[j]);
+      const float r = DF ? (float)r64 : vv2[j] * (lap + ds2[j]);
       unsigned short u2l = 0;
       float u2;
-      if constexpr (DF) u2 = df_update(g, c, cl, un, bf16_f32(basel0[j * ROWS]), r, u2l);
+      if constexpr (DF) u2 = df_update(g, c, cl, un, bf16_f32(basel0[j * ROWS]), r64, u2l);
       else u2 = g * (2.f * c - g * un + r);
       [[maybe_unused]] float rs = r;
       if constexpr (FS) {
