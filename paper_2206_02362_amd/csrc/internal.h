@@ -243,14 +243,14 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
                               int in_ring = 0, int in_first = 0, int out_ring = 0, int out_first = 0);
 
 // acc(z,y,h) += sum_s sum_{n<nk} a_n(z, y-h) b_n(z, y+h) (FP64 accumulator;
-// products summed in FP32 over at most 64 slots at a time).  Slot n of a is
-// a + n*a_slot; slot of b is ring index (b_first + n) % b_ring.  parts:
-// scratch for up to kImageGroups FP64 partial images ([kImageGroups][nh][nx][nz])
-// that let the slots be split over more workgroups; null keeps one group.
-constexpr int kImageGroups = 4;
+// products summed in FP32 over at most 512 slots of a slot group while there
+// are at most kImageGroups groups).  Slot n of a is a + n*a_slot; slot of b
+// is ring index (b_first + n) % b_ring.  parts: scratch for up to kImageGroups
+// FP32 partial images ([kImageGroups][nh][nx][nz]), one per slot group.
+constexpr int kImageGroups = 16;
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
                             int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, double *acc,
-                            double *parts, hipStream_t st);
+                            float *parts, hipStream_t st);
 
 // Time-lag extension, lags tau_k = k L dt, k in [-K, K] (g.nh = 2K+1, g.H = K).
 // Slots hold one padded field per time step, slot n of shot s at

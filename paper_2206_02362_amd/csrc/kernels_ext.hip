@@ -539,17 +539,19 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
 constexpr int kImgYT = 8;
 constexpr int kImgHT = 8;
 
-// Each wavefront sums its tile in FP32 registers over at most kImgFlush
-// slots, then adds the sums to an FP64 image (the accumulator, or with
-// several slot groups its group's partial image), so no FP32 chain grows
-// with the number of shots and steps of a launch.
-constexpr int kImgFlush = 64;
+// Each wavefront sums its tile in FP32 registers over the slots of its
+// group, then stores the sums into its group's partial image; a second
+// kernel adds the partials to the FP64 accumulator in group order.  The launch splits its slots into enough
+// groups that no group sums more than kImgChain of them, which bounds the
+// FP32 chain's rounding to about 1e-6 of a sum of random-sign terms,
+// whatever the number of shots and steps of the launch.
+constexpr int kImgChain = 512;
 
 struct ImageArgs {
   const float *a;
   const float *b;
   double *acc;
-  double *parts;       // groups > 1: partial images, one per slot group
+  float *parts;        // partial images, one per slot group
   long a_slot, b_slot, a_sstride, b_sstride;
   int b_ring, b_first;
   int nshots, nk;
@@ -559,34 +561,22 @@ struct ImageArgs {
   int groups, slots_per_group;
 };
 
-// Adds a wavefront's FP32 tile sums to the FP64 image (its group's partial
-// image when the slots are split into groups; the first flush of a group
-// overwrites it) and clears them.  Every cell is owned by one wavefront.
-__device__ __forceinline__ void image_flush(const ImageArgs &p, float (&acc)[kImgYT][kImgHT], bool store, int grp,
-                                            int y0, int h0, int hhi, int z, bool first) {
-  if (store) {
+// Stores a wavefront's FP32 tile sums into its group's partial image.  Every
+// cell of a group's image is owned by one wavefront.
+__device__ __forceinline__ void image_store(const ImageArgs &p, const float (&acc)[kImgYT][kImgHT], int grp, int y0,
+                                            int h0, int hhi, int z) {
 #pragma unroll
-    for (int yy = 0; yy < kImgYT; ++yy) {
-      const int y = y0 + yy;
-      if (y >= p.nx) continue;
+  for (int yy = 0; yy < kImgYT; ++yy) {
+    const int y = y0 + yy;
+    if (y >= p.nx) continue;
 #pragma unroll
-      for (int hh = 0; hh < kImgHT; ++hh) {
-        const int ih = h0 + hh;
-        if (ih > hhi) continue;
-        const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
-        if (p.groups > 1) {
-          double *d = p.parts + (long)grp * p.nh * p.nx * p.nz + o;
-          *d = (first ? 0.0 : *d) + (double)acc[yy][hh];
-        } else {
-          p.acc[o] += (double)acc[yy][hh];
-        }
-      }
+    for (int hh = 0; hh < kImgHT; ++hh) {
+      const int ih = h0 + hh;
+      if (ih > hhi) continue;
+      const long o = ((long)(ih + p.H) * p.nx + y) * p.nz + z;
+      p.parts[(long)grp * p.nh * p.nx * p.nz + o] = acc[yy][hh];
     }
   }
-#pragma unroll
-  for (int yy = 0; yy < kImgYT; ++yy)
-#pragma unroll
-    for (int hh = 0; hh < kImgHT; ++hh) acc[yy][hh] = 0.f;
 }
 
 // LDS-staged, pipelined version.  A workgroup of 16 wavefronts covers one
@@ -695,7 +685,6 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   __syncthreads();
   int rb = 0;
   int q = q0;
-  bool first = true;
   for (; q + 1 < total; q += 2) {   // pairs of slots; no exit in between
     int nb1 = rb == 2 ? 0 : rb + 1;
     consume(rb);
@@ -709,13 +698,10 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
     fetch(q + 4, pB);
     __syncthreads();
     rb = nb1;
-    if ((q + 2 - q0) % kImgFlush == 0 && q + 2 < total) {
-      image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
-      first = false;
-    }
   }
   if (q < total) consume(rb);       // odd last slot, already staged
-  image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
+  if (!active || !zin) return;
+  image_store(p, acc, grp, y0, h0, hhi, z);
 }
 
 // Wide-offset variant with the windows brought in by 16-byte direct
@@ -822,7 +808,6 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   issue(q0, b0);
   issue(q0 + 1, b1);
   issue(q0 + 2, b2);
-  bool first = true;
   for (int q = q0; q < total; q += 4) {
     step(q, b0, b3);
     if (q + 1 >= total) break;
@@ -831,28 +816,23 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
     step(q + 2, b2, b1);
     if (q + 3 >= total) break;
     step(q + 3, b3, b2);
-    // the flush's own loads and stores are younger than the slot loads in
-    // flight, so the next ready() waits for them too: later, never earlier
-    if ((q + 4 - q0) % kImgFlush == 0 && q + 4 < total) {
-      image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
-      first = false;
-    }
   }
-  image_flush(p, acc, active && zin, grp, y0, h0, hhi, z, first);
+  if (!active || !zin) return;
+  image_store(p, acc, grp, y0, h0, hhi, z);
 }
 
 // acc += sum over g of parts[g], in group order (FP64)
-__global__ void k_image_reduce(double *acc, const double *parts, long n, int groups) {
+__global__ void k_image_reduce(double *acc, const float *parts, long n, int groups) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     double s = parts[i];
-    for (int g = 1; g < groups; ++g) s += parts[(long)g * n + i];
+    for (int g = 1; g < groups; ++g) s += (double)parts[(long)g * n + i];
     acc[i] += s;
   }
 }
 
 hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const float *b, long b_slot, long b_sstride,
                             int b_ring, int b_first, int nshots, int nk, const ExtGeom &g, double *acc,
-                            double *parts, hipStream_t st) {
+                            float *parts, hipStream_t st) {
   if (nk <= 0 || nshots <= 0) return hipSuccess;
   ImageArgs p;
   p.a = a;
@@ -881,10 +861,11 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.nhb = wide ? (g.nh + 31) / 32 : 1;
   // one workgroup fits a CU: split the slots into groups until there are
   // about eight workgroups per CU, so the last round of workgroups leaves
-  // little of the device idle (at most kImageGroups partial images)
+  // little of the device idle, and until no group sums more than kImgChain
+  // slots (at most kImageGroups partial images)
   const int total = nshots * nk;
-  const int want = (2048 + nblk * p.nhb - 1) / (nblk * p.nhb);
-  int groups = parts ? std::min(kImageGroups, std::max(1, want)) : 1;
+  const int want = std::max((2048 + nblk * p.nhb - 1) / (nblk * p.nhb), (total + kImgChain - 1) / kImgChain);
+  int groups = std::min(kImageGroups, std::max(1, want));
   groups = std::min(groups, total);
   p.slots_per_group = (total + groups - 1) / groups;
   p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
@@ -897,7 +878,7 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   else if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
   else k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p.groups == 1) return e;
+  if (e != hipSuccess) return e;
   const long n = (long)g.nh * g.nx * g.nz;
   long blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;

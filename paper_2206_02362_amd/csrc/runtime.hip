@@ -1309,7 +1309,7 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
   // (two-step path: the adjoint ring's BF16 low parts add R / 2 fields)
   const long per_shot = (nf + K + R + (two ? 2L + (R + 1) / 2 : 0L) + ck_fields) * d.field * 4 + (long)geo->nrec * 64;
   const long img = (long)nh * d.nx * d.nz;
-  const size_t fixed = (size_t)d.field * 8 + (size_t)img * 4 * (1 + kImageGroups);
+  const size_t fixed = (size_t)d.field * 8 + (size_t)img * (8 + 4 * kImageGroups);   // FP64 image + partials
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, two);
@@ -1322,7 +1322,7 @@ static int born_ext_adj_run(fwime_ctx_t *ctx, const fwime_grid_t *g, const float
   cv.add(&c.gx, d.NX + kGxPad);
   cv.add(&c.tables, table_set_ints(ts) + 64 * batches.size() * 8);
   unsigned short *lows = nullptr, *ckpt_lo = nullptr, *ring_lo = nullptr;
-  double *parts = nullptr;
+  float *parts = nullptr;
   cv.add(&acc, img);
   cv.add(&parts, kImageGroups * img);
   cv.add(&pairs, nf * d.field * S);
@@ -1480,7 +1480,7 @@ GradPlan grad_plan(const Dims &d, int nt) {
 
 struct GradWork {       // per-batch working fields (+ partial images of the imaging kernel)
   float *pairs, *t2u, *t2d, *lam, *er, *rho;
-  double *parts = nullptr;
+  float *parts = nullptr;
 };
 
 int grad_forward_batch(fwime_ctx_t *ctx, const Common &c, const ExtGeom &eg, const GradPlan &pl,
@@ -1870,7 +1870,7 @@ int fwime_gradient(fwime_ctx_t *ctx, const fwime_grid_t *g, const float *vel, co
   const long nrt = (long)geo->nrec * g->nt;
   const long per_shot =
       grad_work_per_shot(d, pl, ctx->two_step) + 2 * pl.ck_stride * 4 + 2 * nrt * 4 + (long)geo->nrec * 64;
-  const size_t fixed = (size_t)d.field * 12 + (size_t)img * 4 * (3 + kImageGroups);
+  const size_t fixed = (size_t)d.field * 12 + (size_t)img * 4 * (5 + kImageGroups);
   const int S = choose_batch(ctx, per_shot, fixed, geo->nshots);
   auto batches = split_batches(geo->nshots, S);
   TableSet ts = build_table_set(d, geo, batches, ctx->two_step);
@@ -2552,11 +2552,11 @@ int fwime_footprint(const fwime_grid_t *g, int32_t nshots, int32_t nrec, int32_t
     case FWIME_OP_BORN_FWD: per_shot = (8 + 2 * 16 + 4) * fb; fixed += img; break;
     case FWIME_OP_BORN_ADJ:
       per_shot = (4 + 2L * pl.nseg + pl.K + pl.R + 2 + (pl.R + 1) / 2 + pl.nseg) * fb;
-      fixed += (1 + kImageGroups) * img;
+      fixed += (2 + kImageGroups) * img;          // FP64 accumulator and partial images
       break;
     case FWIME_OP_GRADIENT:
       per_shot = grad_work_per_shot(d, pl, true) + 2 * pl.ck_stride * 4 + 2 * nrt;
-      fixed += (3 + kImageGroups) * img;
+      fixed += (5 + kImageGroups) * img;
       break;
     default: return FWIME_EINVAL;
   }

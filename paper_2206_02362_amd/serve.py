@@ -4,10 +4,12 @@ Requests on grids of different sizes arrive at any time.  The server owns a
 fixed number of slots; a slot is a HIP stream plus its own library context
 (the library runs one stream per context).  Velocity models are registered
 once and stay resident on the device; a request names one.  Admission is
-first come, first served: the head of the queue starts as soon as a slot is
-free and its device footprint (fwime_footprint for its operator, shot count
-and grid, plus its outputs) fits in what the running requests leave of the
-HBM budget.  A request that arrives while others run therefore starts on a
+first come, first served by default: the head of the queue starts as soon as
+a slot is free and its device footprint (fwime_footprint for its operator,
+shot count and grid, plus its outputs) fits in what the running requests
+leave of the HBM budget.  With policy="short_first" the request of least
+work (cell-updates) among those that can start goes first, unless the head
+has waited longer than an aging bound.  A request that arrives while others run therefore starts on a
 free slot and its kernels overlap theirs on the device.
 
 Modeling requests are batched continuously (engine=True): they go to one
@@ -165,11 +167,18 @@ class Server:
     the free device memory when the server starts).  merge_models: the most
     modeling requests one batched call may serve when there is no engine (1
     turns merging off).  engine_steps: time steps per engine round.
+    policy: "fcfs" (arrival order; nothing overtakes the head) or
+    "short_first" (the least work among the requests that can start now; a
+    head that has waited aging_s seconds goes first).
     """
 
     def __init__(self, device: int = 0, slots: int = 3, hbm_budget: int | None = None, merge_models: int = 8,
-                 engine: bool = False, engine_steps: int = 64,
+                 engine: bool = False, engine_steps: int = 64, policy: str = "fcfs", aging_s: float = 30.0,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+        if policy not in ("fcfs", "short_first"):
+            raise ValueError("policy must be 'fcfs' or 'short_first'")
+        self.policy = policy
+        self.aging_s = float(aging_s)
         self.device = device
         self.clock = clock
         self.sleep = sleep
@@ -310,21 +319,37 @@ class Server:
                     s.trim()
                     held -= h
 
+    def _pick(self):
+        """Index in the queue of the next request to start, or None.
+
+        fcfs: the head, once a slot (unless it goes to the engine) and its
+        memory are free; nothing overtakes it.  short_first: the request of
+        the least work (cell-updates) among those that can start now, except
+        that a head that has waited longer than `aging_s` goes first and
+        holds back the others until it starts."""
+        running = any(s.reqs for s in self.slots) or (self.lane is not None and self.lane.busy())
+        free_slot = any(not s.reqs for s in self.slots)
+
+        def startable(r):
+            if not (self.lane is not None and r.kind == "model") and not free_slot:
+                return False
+            need = min(self._need(r), self.budget)
+            return not (running and self.reserved + need > self.budget)
+
+        if self.policy == "fcfs" or self.clock() - self.queue[0].t_arrival > self.aging_s:
+            return 0 if startable(self.queue[0]) else None
+        order = sorted(range(len(self.queue)), key=lambda i: (self.queue[i].cell_updates(), i))
+        return next((i for i in order if startable(self.queue[i])), None)
+
     def _admit(self):
         while self.queue:
-            head = self.queue[0]
-            to_engine = self.lane is not None and head.kind == "model"
-            k = None
-            if not to_engine:
-                k = next((k for k, s in enumerate(self.slots) if not s.reqs), None)
-                if k is None:
-                    return
+            i = self._pick()
+            if i is None:
+                return
+            head = self.queue[i]
+            del self.queue[i]
             need = min(self._need(head), self.budget)
-            running = any(s.reqs for s in self.slots) or (self.lane is not None and self.lane.busy())
-            if running and self.reserved + need > self.budget:
-                return                      # first come, first served: wait for memory
-            if to_engine:
-                self.queue.popleft()
+            if self.lane is not None and head.kind == "model":
                 head.reserved = need
                 self.reserved += need
                 self.peak_reserved = max(self.peak_reserved, self.reserved)
@@ -338,10 +363,11 @@ class Server:
                     self.reserved -= need
                     self.done.append(head)
                 continue
-            group = [self.queue.popleft()]
+            k = next(k for k, s in enumerate(self.slots) if not s.reqs)
+            group = [head]
             head.reserved = need
             total = need
-            if head.kind == "model":
+            if head.kind == "model" and i == 0:
                 while (self.queue and self.queue[0].kind == "model" and len(group) < self.merge_models):
                     nxt = self.queue[0]
                     nn = min(self._need(nxt), self.budget)

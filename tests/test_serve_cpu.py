@@ -221,6 +221,36 @@ def test_engine_respects_budget_and_arrival_order():
     assert srv.admit_order == sorted(srv.admit_order)
 
 
+def _sized(kind, nbytes, dur, nshots):
+    r = _req(kind, nbytes, dur)
+    r.geom = _geom(nshots)
+    return r
+
+
+def test_short_first_lets_small_requests_by_and_ages():
+    # one slot busy with a long gradient; a big and a small Born request
+    # wait: short_first starts the small one first, fcfs keeps arrival order
+    for policy, first in (("short_first", 2), ("fcfs", 1)):
+        srv = FakeServer(slots=1, hbm_budget=1000, policy=policy, aging_s=100.0)
+        reqs = [_sized("gradient", 100, 1.0, 1), _sized("born_fwd", 100, 0.5, 8), _sized("born_fwd", 100, 0.1, 1)]
+        done = srv.replay(reqs, [0.0, 0.01, 0.02])
+        t = {r.id: r for r in done}
+        assert srv.admit_order[:2] == [0, first]
+        assert t[first].t_admit == pytest.approx(t[0].t_done, abs=2e-3)
+    # a head that waited past the aging bound goes first
+    srv = FakeServer(slots=1, hbm_budget=1000, policy="short_first", aging_s=0.5)
+    reqs = [_sized("gradient", 100, 1.0, 1), _sized("born_fwd", 100, 0.5, 8), _sized("born_fwd", 100, 0.1, 1)]
+    srv.replay(reqs, [0.0, 0.01, 0.02])
+    assert srv.admit_order == [0, 1, 2]
+    # budget and completion still hold on a Poisson stream
+    reqs, arr = _poisson(5, 60, 1000)
+    srv = FakeServer(slots=3, hbm_budget=1000, engine=True, policy="short_first")
+    done = srv.replay(reqs, arr)
+    assert len(done) == 60 and srv.reserved == 0 and srv.peak_reserved <= 1000
+    with pytest.raises(ValueError):
+        FakeServer(policy="lifo")
+
+
 def test_idle_arenas_trimmed_over_budget():
     srv = FakeServer(slots=2, hbm_budget=1000)
     srv.replay([_req("gradient", 900, 0.1)], [0.0])
