@@ -313,8 +313,11 @@ def serve_compare(nreq: int, seed: int = 42, slots: int = 3):
                 for k in ("served", "served_short_first")},
             "note": "plain_fifo: one request at a time on one stream; served: 3 slot streams for extended-Born and "
                     "gradient requests plus the continuous-batching engine for modeling requests, admission in "
-                    "arrival order; served_short_first: the same with the least-work request that fits first "
-                    "(aging bound 30 s). With fewer than 100 samples p99 is close to the maximum latency"}
+                    "arrival order by HBM footprint and by stencil workgroups (beside running requests a request "
+                    "starts only while all their workgroups per launch stay within 4096, so requests that fill "
+                    "the GPU run alone and small ones overlap); served_short_first: the same with the least-work "
+                    "request that can start first (aging bound 30 s). With fewer than 100 samples p99 is close "
+                    "to the maximum latency"}
 
 
 def serve_estimate_s(nreq: int, rate: float = 1.5e11) -> float:

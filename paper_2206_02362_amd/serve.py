@@ -7,10 +7,14 @@ once and stay resident on the device; a request names one.  Admission is
 first come, first served by default: the head of the queue starts as soon as
 a slot is free and its device footprint (fwime_footprint for its operator,
 shot count and grid, plus its outputs) fits in what the running requests
-leave of the HBM budget.  With policy="short_first" the request of least
-work (cell-updates) among those that can start goes first, unless the head
-has waited longer than an aging bound.  A request that arrives while others run therefore starts on a
-free slot and its kernels overlap theirs on the device.
+leave of the HBM budget, and, while others run, its stencil workgroups
+(56 x 32 tiles of every shot) fit beside theirs under a fill bound.  A
+request big enough to fill the GPU alone therefore runs alone, as in
+one-at-a-time order, while small requests, which leave most compute units
+idle, overlap: a request that arrives while others run starts on a free slot
+and its kernels run beside theirs.  With policy="short_first" the request of
+least work (cell-updates) among those that can start goes first, unless the
+head has waited longer than an aging bound.
 
 Modeling requests are batched continuously (engine=True): they go to one
 fwime_engine, whose time loop runs in rounds of a fixed number of time steps
@@ -72,6 +76,7 @@ class Request:
     result: Any = None
     error: Exception | None = None
     reserved: int = 0
+    tiles_held: int = 0
     merged: int = 1                      # requests sharing this one's launch
     ticket: int = -1                     # engine job (continuously batched modeling)
     _ready: Any = None
@@ -83,6 +88,11 @@ class Request:
     def cell_updates(self) -> float:
         g = self.grid
         return PROPAGATIONS[self.kind] * self.geom.nshots * (g.nz + 2 * g.nb) * (g.nx + 2 * g.nb) * (g.nt - 1)
+
+    def tiles(self) -> int:
+        """Workgroups of one stencil launch over all its shots (56 x 32 cell tiles)."""
+        g = self.grid
+        return self.geom.nshots * (-(-(g.nz + 2 * g.nb) // 56)) * (-(-(g.nx + 2 * g.nb) // 32))
 
 
 def request_bytes(req: Request) -> int:
@@ -170,15 +180,22 @@ class Server:
     policy: "fcfs" (arrival order; nothing overtakes the head) or
     "short_first" (the least work among the requests that can start now; a
     head that has waited aging_s seconds goes first).
+    fill_tiles: while requests run, another starts only if the stencil
+    workgroups of all of them stay within this bound (None: no bound).  The
+    default, 4096, is about three waves of two-step stencil workgroups over
+    the 256 compute units, beyond which a launch keeps the GPU busy alone.
     """
 
     def __init__(self, device: int = 0, slots: int = 3, hbm_budget: int | None = None, merge_models: int = 8,
                  engine: bool = False, engine_steps: int = 64, policy: str = "fcfs", aging_s: float = 30.0,
+                 fill_tiles: int | None = 4096,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
         if policy not in ("fcfs", "short_first"):
             raise ValueError("policy must be 'fcfs' or 'short_first'")
         self.policy = policy
         self.aging_s = float(aging_s)
+        self.fill_tiles = None if fill_tiles is None else int(fill_tiles)
+        self.running_tiles = 0
         self.device = device
         self.clock = clock
         self.sleep = sleep
@@ -301,6 +318,7 @@ class Server:
                 for r in s.reqs:
                     r.t_done = t
                     self.reserved -= r.reserved
+                    self.running_tiles -= r.tiles_held
                     self.done.append(r)
                 s.reqs = []
                 s.event = None
@@ -310,6 +328,7 @@ class Server:
             for r in fin:
                 r.t_done = t
                 self.reserved -= r.reserved
+                self.running_tiles -= r.tiles_held
                 self.done.append(r)
         held = sum(s.held_bytes() for s in self.slots)
         if held > self.budget:
@@ -322,9 +341,10 @@ class Server:
     def _pick(self):
         """Index in the queue of the next request to start, or None.
 
-        fcfs: the head, once a slot (unless it goes to the engine) and its
-        memory are free; nothing overtakes it.  short_first: the request of
-        the least work (cell-updates) among those that can start now, except
+        fcfs: the head, once a slot (unless it goes to the engine), its
+        memory and, beside running requests, its share of the compute units
+        are free; nothing overtakes it.  short_first: the request of the
+        least work (cell-updates) among those that can start now, except
         that a head that has waited longer than `aging_s` goes first and
         holds back the others until it starts."""
         running = any(s.reqs for s in self.slots) or (self.lane is not None and self.lane.busy())
@@ -333,8 +353,11 @@ class Server:
         def startable(r):
             if not (self.lane is not None and r.kind == "model") and not free_slot:
                 return False
-            need = min(self._need(r), self.budget)
-            return not (running and self.reserved + need > self.budget)
+            if not running:
+                return True
+            if self.fill_tiles is not None and self.running_tiles + r.tiles() > self.fill_tiles:
+                return False
+            return self.reserved + min(self._need(r), self.budget) <= self.budget
 
         if self.policy == "fcfs" or self.clock() - self.queue[0].t_arrival > self.aging_s:
             return 0 if startable(self.queue[0]) else None
@@ -351,7 +374,9 @@ class Server:
             need = min(self._need(head), self.budget)
             if self.lane is not None and head.kind == "model":
                 head.reserved = need
+                head.tiles_held = head.tiles()
                 self.reserved += need
+                self.running_tiles += head.tiles_held
                 self.peak_reserved = max(self.peak_reserved, self.reserved)
                 head.t_admit = self.clock()
                 self.admit_order.append(head.id)
@@ -361,6 +386,7 @@ class Server:
                     head.error = e
                     head.t_done = self.clock()
                     self.reserved -= need
+                    self.running_tiles -= head.tiles_held
                     self.done.append(head)
                 continue
             k = next(k for k, s in enumerate(self.slots) if not s.reqs)
@@ -380,6 +406,8 @@ class Server:
             self.peak_reserved = max(self.peak_reserved, self.reserved)
             now = self.clock()
             for r in group:
+                r.tiles_held = r.tiles()
+                self.running_tiles += r.tiles_held
                 r.slot = k
                 r.t_admit = now
                 r.merged = len(group)

@@ -4,8 +4,9 @@ The server's slot, footprint and completion hooks are replaced by a fake
 device with a virtual clock: each request runs for a stated time and holds a
 stated number of bytes.  Checked: admission never holds more than the HBM
 budget, requests start in arrival order, a seeded Poisson replay is
-deterministic, an oversized request runs alone, modeling requests at the
-head of the queue merge, idle arenas are trimmed under memory pressure, and
+deterministic, an oversized request runs alone, a request whose stencil
+workgroups would overfill the GPU beside running ones waits, modeling
+requests at the head of the queue merge, idle arenas are trimmed under memory pressure, and
 the latency percentiles.
 """
 import numpy as np
@@ -249,6 +250,38 @@ def test_short_first_lets_small_requests_by_and_ages():
     assert len(done) == 60 and srv.reserved == 0 and srv.peak_reserved <= 1000
     with pytest.raises(ValueError):
         FakeServer(policy="lifo")
+
+
+def test_fill_bound_runs_gpu_filling_requests_alone():
+    # the fake grid has 2 stencil tiles per shot; fill bound 10 tiles
+    def reqs():
+        return [_sized("gradient", 100, 1.0, 4),     # 8 tiles
+                _sized("born_fwd", 100, 0.2, 2),     # 4 tiles: 12 > 10 beside the first, waits
+                _sized("model", 100, 0.2, 1),        # 2 tiles: would fit beside the first
+                _sized("born_adj", 100, 0.3, 6)]     # 12 tiles: fills the GPU alone
+    arr = [0.0, 0.01, 0.02, 0.03]
+    srv = FakeServer(slots=3, hbm_budget=1000, fill_tiles=10)
+    t = {r.id: r for r in srv.replay(reqs(), arr)}
+    assert [t[i].tiles() for i in range(4)] == [8, 4, 2, 12]
+    assert t[1].t_admit >= t[0].t_done - 1e-9           # b waits for a
+    assert t[2].t_admit >= t[1].t_admit                 # fcfs: c stays behind b
+    assert t[2].t_admit < t[1].t_done                   # then b and c overlap (6 tiles)
+    assert t[3].t_admit >= max(t[i].t_done for i in range(3)) - 1e-9   # the big one runs alone
+    assert srv.running_tiles == 0 and srv.admit_order == [0, 1, 2, 3]
+    # short_first: c starts beside a at once; b still waits for the tiles
+    srv = FakeServer(slots=3, hbm_budget=1000, fill_tiles=10, policy="short_first", aging_s=100.0)
+    t = {r.id: r for r in srv.replay(reqs(), arr)}
+    assert t[2].t_admit == pytest.approx(0.02, abs=2e-3)
+    assert t[1].t_admit >= t[0].t_done - 1e-9
+    assert srv.admit_order == [0, 2, 1, 3]
+    # no bound: b overlaps a
+    srv = FakeServer(slots=3, hbm_budget=1000, fill_tiles=None)
+    t = {r.id: r for r in srv.replay(reqs(), arr)}
+    assert t[1].t_admit < t[0].t_done
+    # the engine's modeling jobs count as well
+    srv = FakeServer(slots=3, hbm_budget=1000, fill_tiles=10, engine=True)
+    t = {r.id: r for r in srv.replay([_sized("model", 100, 1.0, 4), _sized("model", 100, 0.2, 2)], [0.0, 0.01])}
+    assert t[1].t_admit >= t[0].t_done - 1e-9 and srv.running_tiles == 0
 
 
 def test_idle_arenas_trimmed_over_budget():
