@@ -333,11 +333,14 @@ def serve_estimate_s(nreq: int, rate: float = 1.5e11) -> float:
     return 3.0 * cells / rate + 8.0
 
 
-def marmousi_pass(ctx):
+def marmousi_pass(ctx, nt: int = 0):
     import torch
     import paper_2206_02362_amd as fw
     import synth
     w = synth.marmousi_set(100)
+    if nt > 0:                       # counter runs: a shorter time axis, the same launch shapes
+        w.nt = min(nt, w.nt)
+        w.wavelet = w.wavelet[:, :w.nt].copy()
     dev = "cuda:0"
     grid = fw.Grid(w.nz, w.nx, w.nb, w.nt, w.dz, w.dx, w.dt, w.sponge_alpha)
     vel = torch.tensor(w.vel, dtype=torch.float32, device=dev)
@@ -454,6 +457,8 @@ def main():
     ap.add_argument("--sections", default="roofline,plain,cpu,serving,marmousi,time_lag,spline,vp",
                     help="comma list of the sections to run after the timed steps")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests in the serving replay (0: fit)")
+    ap.add_argument("--marmousi-nt", type=int, default=0,
+                    help="time steps of the four-operator section (0: the workload's 5000); for counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -555,7 +560,7 @@ def main():
 
     marm_ctx = None
     if fits("marmousi", 45):
-        marm, marm_ctx = marmousi_pass(ctx)
+        marm, marm_ctx = marmousi_pass(ctx, args.marmousi_nt)
         log(f"marmousi four-operator pass: {marm['total_s']:.1f} s")
     if marm_ctx is not None:
         grid, vel, geo, dobs, w = marm_ctx

@@ -6,8 +6,8 @@ wide-offset imaging condition as the direct-load ring (the default) and the
 register-staged ring (FWIME_IMAGE_KERNEL=lds).  Each pair forms the same
 products and sums them in the same order, so extended Born data, adjoint
 images and gradients must agree bit for bit.  nh = 61 (H = 30, the widest
-kernels) and nh = 21, on a grid whose width is not a multiple of the
-scatter's 32-column blocks.
+kernels), 21 and 5, on a grid whose width is not a multiple of the scatter's
+32-column blocks.
 """
 import sys
 
@@ -24,12 +24,12 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.mark.parametrize("nh", [61, 21])
+@pytest.mark.parametrize("nh", [61, 21, 5])
 def test_offset_kernel_variants_bitwise(nh, monkeypatch):
     import torch
     import paper_2206_02362_amd as fw
-    say(f"case: offset kernel variants, 70x150 nb8 nt120, 2 shots, nh {nh}")
-    w = synth.tiny(nz=70, nx=150, nb=8, nt=120, nshots=2, nh=nh, seed=7)
+    say(f"case: offset kernel variants, 70x150 nb8 nt121, 2 shots, nh {nh}")
+    w = synth.tiny(nz=70, nx=150, nb=8, nt=121, nshots=2, nh=nh, seed=7)
     grid, tv, tg = gpu_problem(w)
     pt = torch.tensor(1e-2 * synth.random_ptilde(nh, w.nz, w.nx, 3), dtype=torch.float32, device="cuda:0")
     dobs = torch.tensor(1e-3 * np.random.default_rng(5).standard_normal((w.nshots, w.nrec, w.nt)),
@@ -44,12 +44,13 @@ def test_offset_kernel_variants_bitwise(nh, monkeypatch):
         torch.cuda.synchronize()
         return born, adj, gv.cpu().numpy(), gp.cpu().numpy()
 
+    names = ("born_fwd", "born_adj", "grad_vel", "grad_ptilde")
     ref = run()
     monkeypatch.setenv("FWIME_SCATTER_KERNEL", "ws")
     monkeypatch.setenv("FWIME_IMAGE_KERNEL", "lds")
     alt = run()
     ctx.close()
-    for name, a, b in zip(("born_fwd", "born_adj", "grad_vel", "grad_ptilde"), ref, alt):
+    for name, a, b in zip(names, ref, alt):
         say(f"  {name}: max |x| {np.abs(a).max():.3e}, max |diff| {np.abs(a - b).max():.3e}")
         assert np.abs(a).max() > 0, name
         assert np.array_equal(a, b), name
