@@ -191,14 +191,16 @@ def stencil_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launches: int):
+def measured_traffic(launches: int, tile_x: int):
     """HBM bytes per stencil launch of the headline from the committed counter
-    runs, or None when those were taken on another kernel version or shape."""
+    runs, or None when those were taken on another kernel version, launch
+    count or tile width."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha") != stencil_source_hash() or rec.get("launches_per_call") != launches:
+    if (rec.get("kernel_source_sha") != stencil_source_hash() or rec.get("launches_per_call") != launches
+            or rec.get("tile_x") != tile_x):
         return None
     return rec.get("bytes_per_launch")
 
@@ -521,7 +523,7 @@ def main():
     achieved = algo_bytes / (kern_ms / 1e3)
     lpc = launches // args.steps
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": measured_traffic(lpc),
+                "frac": achieved / PEAK_HBM, "traffic": measured_traffic(lpc, ctx.info()["last_batch_tile_x"]),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": f"k_step2_multi<{ctx.info()['last_batch_tile_x']}> (two stencil time steps per launch, "
                           f"all active shots of all grids)",

@@ -557,7 +557,7 @@ struct ImageArgs {
   int nshots, nk;
   int nz, nx, nb, NX, LZ, nh, H;
   int nzs, nyt, nht;
-  int nhb;             // offset blocks (blockIdx.y = group * nhb + offset block)
+  int nhb;             // offset blocks (blockIdx.x: tile and offset block, offset block fastest)
   int groups, slots_per_group;
 };
 
@@ -580,8 +580,8 @@ __device__ __forceinline__ void image_store(const ImageArgs &p, const float (&ac
 }
 
 // LDS-staged, pipelined version.  A workgroup of 16 wavefronts covers one
-// depth strip, YB = 8 NYT model columns and 8 NHT offsets of the group
-// blockIdx.y; the wavefronts tile (y, h) as NYT x NHT tiles of 8 x 8
+// depth strip, YB = 8 NYT model columns and one block of 8 NHT offsets, for
+// the slots of group blockIdx.y; the wavefronts tile (y, h) as NYT x NHT tiles of 8 x 8
 // (NYT NHT = 16).  Per time slot the source-side window (y - h) and the
 // receiver-side window (y + h), each YB + 8 NHT - 1 columns wide, are staged in
 // a 3-deep LDS ring: slot q is consumed while slot q + 1 is written from
@@ -602,15 +602,19 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ntile = p.nzs * ((p.nx + YB - 1) / YB);
-  const int per = (ntile + 7) >> 3;
-  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-contiguous tiles
-  if (tile >= ntile) return;
+  // (tile, offset block) pairs in XCD-contiguous ranges, offset block
+  // fastest: the offset blocks of a tile read the same slots at the same
+  // time and share them through the XCD's L2
+  const int npair = p.nzs * ((p.nx + YB - 1) / YB) * p.nhb;
+  const int per = (npair + 7) >> 3;
+  const int pair = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (pair >= npair) return;
+  const int tile = pair / p.nhb;
   const int zs = tile % p.nzs;
   const int yblk = tile / p.nzs;
   const int yb = yblk * YB;
-  const int grp = blockIdx.y / p.nhb;
-  const int hlo = -p.H + HSPAN * (blockIdx.y - grp * p.nhb);
+  const int grp = blockIdx.y;
+  const int hlo = -p.H + HSPAN * (pair - tile * p.nhb);
   const int hhi = min(p.H, hlo + HSPAN - 1);
   const int z = zs * 64 + lane;
   const bool zin = z < p.nz;
@@ -724,18 +728,21 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ntile = p.nzs * ((p.nx + YB - 1) / YB);
-  const int per = (ntile + 7) >> 3;
-  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-contiguous tiles
-  if (tile >= ntile) return;
-  // column blocks fastest, as in the scatter: neighbouring windows of one
-  // strip are read together and come from the XCD's L2
+  // (tile, offset block) pairs in XCD-contiguous ranges, offset block
+  // fastest, then column blocks, as in the scatter: the offset blocks of a
+  // tile and the neighbouring windows of one strip are read together and
+  // come from the XCD's L2
   const int nyb = (p.nx + YB - 1) / YB;
+  const int npair = p.nzs * nyb * p.nhb;
+  const int per = (npair + 7) >> 3;
+  const int pair = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (pair >= npair) return;
+  const int tile = pair / p.nhb;
   const int yblk = tile % nyb;
   const int zs = tile / nyb;
   const int yb = yblk * YB;
-  const int grp = blockIdx.y / p.nhb;
-  const int hlo = -p.H + HSPAN * (blockIdx.y - grp * p.nhb);
+  const int grp = blockIdx.y;
+  const int hlo = -p.H + HSPAN * (pair - tile * p.nhb);
   const int hhi = min(p.H, hlo + HSPAN - 1);
   const int z = zs * 64 + lane;
   const bool zin = z < p.nz;
@@ -856,20 +863,20 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.H = g.H;
   p.nzs = (g.nz + 63) / 64;
   const bool wide = g.nh > 16;
-  const int ntile = p.nzs * ((g.nx + (wide ? 31 : 63)) / (wide ? 32 : 64));
-  const int nblk = (ntile + 7) / 8 * 8;
   p.nhb = wide ? (g.nh + 31) / 32 : 1;
+  const int npair = p.nzs * ((g.nx + (wide ? 31 : 63)) / (wide ? 32 : 64)) * p.nhb;
+  const int nblk = (npair + 7) / 8 * 8;
   // one workgroup fits a CU: split the slots into groups until there are
   // about eight workgroups per CU, so the last round of workgroups leaves
   // little of the device idle, and until no group sums more than kImgChain
   // slots (at most kImageGroups partial images)
   const int total = nshots * nk;
-  const int want = std::max((2048 + nblk * p.nhb - 1) / (nblk * p.nhb), (total + kImgChain - 1) / kImgChain);
+  const int want = std::max((2048 + nblk - 1) / nblk, (total + kImgChain - 1) / kImgChain);
   int groups = std::min(kImageGroups, std::max(1, want));
   groups = std::min(groups, total);
   p.slots_per_group = (total + groups - 1) / groups;
   p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
-  const dim3 grid((unsigned)nblk, (unsigned)(p.nhb * p.groups));
+  const dim3 grid((unsigned)nblk, (unsigned)p.groups);
   // FWIME_IMAGE_KERNEL=lds selects the register-staged ring for the wide
   // tiles too (for comparisons; read per launch)
   const char *sel = std::getenv("FWIME_IMAGE_KERNEL");
