@@ -2393,15 +2393,22 @@ std::string batch_signature(int njobs, const fwime_job_t *jobs) {
   return sig;
 }
 
+// Times every tile width on the batch's first steps (receivers off) and
+// keeps the context's width unless another is at least 2 % faster: the
+// widths next to the best one are within a few per cent of it, and a choice
+// made on noise would move the launch time from call to call.  Each width
+// gets three timed windows of 8 launches; its time is the fastest window.
 int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStream_t st, int *best_tx) {
   const int cand[5] = {16, 24, 32, 48, 64};
-  float best = 1e30f;
+  float t_cand[5];
   *best_tx = ctx->tile_x;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   int rc = FWIME_OK;
-  for (int tx : cand) {
+  for (int ci = 0; ci < 5; ++ci) {
+    const int tx = cand[ci];
+    t_cand[ci] = 1e30f;
     BatchPlan bp;
     void *dj = nullptr;
     int *dstep = nullptr;
@@ -2417,30 +2424,41 @@ int batch_autotune(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, hipStre
       rc = set_err(ctx, FWIME_EHIP, "autotune setup failed");
       break;
     }
-    const int warm = 2, timed = 8;
-    for (int i = 0; i < warm + timed; ++i) {
-      if (i == warm) (void)hipEventRecord(e0, st);
-      if (batch_launch(bp, dj, bp.total, dstep, 0, tx, st) != hipSuccess) {
+    const int warm = 2, timed = 8, windows = 3;
+    for (int i = 0; i < warm && rc == FWIME_OK; ++i)
+      if (batch_launch(bp, dj, bp.total, dstep, 0, tx, st) != hipSuccess)
         rc = set_err(ctx, FWIME_EHIP, "autotune launch failed");
+    for (int wdw = 0; wdw < windows && rc == FWIME_OK; ++wdw) {
+      (void)hipEventRecord(e0, st);
+      for (int i = 0; i < timed && rc == FWIME_OK; ++i)
+        if (batch_launch(bp, dj, bp.total, dstep, 0, tx, st) != hipSuccess)
+          rc = set_err(ctx, FWIME_EHIP, "autotune launch failed");
+      if (rc) break;
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_err(ctx, FWIME_EHIP, "autotune sync failed");
         break;
       }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      t_cand[ci] = std::min(t_cand[ci], ms);
     }
     if (rc) break;
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = set_err(ctx, FWIME_EHIP, "autotune sync failed");
-      break;
-    }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) {
-      best = ms;
-      *best_tx = tx;
-    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return rc;
+  if (rc) return rc;
+  float t_def = 1e30f, t_best = 1e30f;
+  int tx_best = ctx->tile_x;
+  for (int ci = 0; ci < 5; ++ci) {
+    if (cand[ci] == ctx->tile_x) t_def = t_cand[ci];
+    if (t_cand[ci] < t_best) {
+      t_best = t_cand[ci];
+      tx_best = cand[ci];
+    }
+  }
+  *best_tx = t_best < 0.98f * t_def ? tx_best : ctx->tile_x;
+  return FWIME_OK;
 }
 
 }  // namespace
