@@ -128,6 +128,14 @@ struct ScatterArgs {
 // nh + 1 LDS reads.
 constexpr int kScJB = 16;         // output columns per workgroup
 constexpr int kScThreads = 512;
+constexpr int kScMaxSlots = 2048; // time slots per workgroup of the direct-load kernel (offset table in LDS)
+
+// a value the whole wavefront read from the same LDS cell, as a scalar
+__device__ __forceinline__ long wave_uniform(long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long)v >> 32));
+  return (long)(((unsigned long)hi << 32) | lo);
+}
 
 template <int HMAX, int SG>
 __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs a) {
@@ -338,16 +346,25 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int off0 = (col0 * a.LZ + a.nb + zs * 64) * 4 + (2 * (lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
   const int gstep = 8 * a.LZ * 4;                                 // bytes per chunk of 4 window columns
 
-  // slots are issued and consumed in increasing order: one cursor each
-  OffCursor ic, oc;
-  ic.init(q0, a.nk, a.in_first, a.in_ring, a.in_slot, a.sstride);
-  oc.init(q0, a.nk, a.out_first, a.out_ring, a.out_slot, a.sstride);
+  // element offsets of the workgroup's input and output slots, computed once
+  // (slot q is shot s = q / nk, step n = q mod nk, at ring position
+  // (first + n) mod ring, or n without a ring), so that the per-slot scalar
+  // work is two table reads instead of two cursor updates with branches
+  __shared__ long tin[kScMaxSlots], tout[kScMaxSlots];
+  for (int i = tid; i < q1 - q0; i += kScThreads) {
+    const int q = q0 + i;
+    const int sh = q / a.nk, n = q - sh * a.nk;
+    const int ri = a.in_ring ? (a.in_first % a.in_ring + n) % a.in_ring : n;
+    const int ro = a.out_ring ? (a.out_first % a.out_ring + n) % a.out_ring : n;
+    tin[i] = (long)sh * a.sstride + (long)ri * a.in_slot;
+    tout[i] = (long)sh * a.sstride + (long)ro * a.out_slot;
+  }
+  __syncthreads();
   // wavefront w brings chunks g = w + 8 r (window columns 4 g .. 4 g + 3) of
   // slot q into buf, column-major with lane = depth
   auto issue = [&](int q, float *buf) {
     if (q >= q1) return;
-    const auto rs = slot_rsrc(a.in + ic.off, slot_bytes);
-    ic.next();
+    const auto rs = slot_rsrc(a.in + wave_uniform(tin[q - q0]), slot_bytes);
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int g = w + 8 * r;
@@ -362,6 +379,10 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   // memory operations complete in order, so waiting until no more than
   // PER y + 2 c remain is exact.
   auto ready = [&](int q) {
+    if (q + 2 < q1 && q - q0 >= 3) {      // steady state: y = 2, c = 3
+      wait_vmcnt_at_most<2 * PER + 6>(2 * PER + 6);
+      return;
+    }
     const int y = min(2, q1 - 1 - q);
     const int c = min(3, q - q0);
     wait_vmcnt_at_most<2 * PER + 6>(PER * y + 2 * c);
@@ -377,8 +398,7 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
       oa += ca[k] * row[(HMAX - SG * ih) * 64];
       ob += cb[k] * row[(HMAX + 1 - SG * ih) * 64];
     }
-    const auto ro = slot_rsrc(a.out + oc.off, slot_bytes);
-    oc.next();
+    const auto ro = slot_rsrc(a.out + wave_uniform(tout[q - q0]), slot_bytes);
     // always two store instructions (cells not written go past the end of
     // the buffer and are dropped), so that ready() can count them
     st(ro, oa, zin && ja < jend ? (ja * a.LZ + zp) * 4 : kOutOfRange, 0);
@@ -513,6 +533,7 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
     const int ntile = staged ? a.nzs * ((a.nj + kScJB - 1) / kScJB) : a.nzs * ((a.nj + 2 * kScJB - 1) / (2 * kScJB)) * 2;
     const int nblk = (ntile + 7) / 8 * 8;
     int groups = std::max(1, std::min(total, (2048 + nblk - 1) / nblk));
+    if (!staged) groups = std::max(groups, (total + kScMaxSlots - 1) / kScMaxSlots);
     a.slots_per_block = (total + groups - 1) / groups;
     groups = (total + a.slots_per_block - 1) / a.slots_per_block;
     const dim3 grid((unsigned)nblk, (unsigned)groups);
