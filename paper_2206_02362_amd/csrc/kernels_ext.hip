@@ -1077,10 +1077,38 @@ __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_
           for (int jj = 0; jj < 4; ++jj)
             if (q >= k0 + jj && q < Q + k0 + jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
         }
-        for (int q = qlo; q < qhi; ++q) {
-          const float x = tb[q * 64 + lane];
+        // the four history samples of step q are those of step q - 1 moved
+        // by one lag plus one new one: they stay in registers (w0..w3 =
+        // history at q - k0 .. q - k0 - 3 when four steps start), one new
+        // LDS read per step instead of four; each lag still sums in
+        // ascending q, as the per-step form does
+        if (qlo < qhi) {
+          const float *hq = &ta[(qlo - k0) * 64 + lane];
+          float w0 = hq[0], w1 = hq[-64], w2 = hq[-128], w3 = hq[-192];
+          int q = qlo;
+          for (; q + 4 <= qhi; q += 4) {
+            const float *tq = &tb[q * 64 + lane];
+            const float *hn = &ta[(q - k0) * 64 + lane];
+            float x = tq[0];
+            t[0] = fmaf(w0, x, t[0]); t[1] = fmaf(w1, x, t[1]); t[2] = fmaf(w2, x, t[2]); t[3] = fmaf(w3, x, t[3]);
+            w3 = hn[64];
+            x = tq[64];
+            t[0] = fmaf(w3, x, t[0]); t[1] = fmaf(w0, x, t[1]); t[2] = fmaf(w1, x, t[2]); t[3] = fmaf(w2, x, t[3]);
+            w2 = hn[128];
+            x = tq[128];
+            t[0] = fmaf(w2, x, t[0]); t[1] = fmaf(w3, x, t[1]); t[2] = fmaf(w0, x, t[2]); t[3] = fmaf(w1, x, t[3]);
+            w1 = hn[192];
+            x = tq[192];
+            t[0] = fmaf(w1, x, t[0]); t[1] = fmaf(w2, x, t[1]); t[2] = fmaf(w3, x, t[2]); t[3] = fmaf(w0, x, t[3]);
+            // w1, w2, w3 now hold the history at q + 3, q + 2, q + 1 (- k0):
+            // the next four steps need only q + 4
+            if (q + 8 <= qhi) w0 = hn[256];
+          }
+          for (; q < qhi; ++q) {
+            const float x = tb[q * 64 + lane];
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
+            for (int jj = 0; jj < 4; ++jj) t[jj] = fmaf(ta[(q - k0 - jj) * 64 + lane], x, t[jj]);
+          }
         }
         const int h0 = max(qhi, qlo), h1 = min(Q, Q + k0 + 3);
         for (int q = h0; q < h1; ++q) {
