@@ -1006,24 +1006,24 @@ __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, cons
   for (int k = -KMAX; k <= KMAX; ++k)
     c[k + KMAX] = (cin && k >= -K && k <= K) ? coef[((long)(k + K) * nx + y) * nz + z] : 0.f;
   __syncthreads();
-  // four consecutive outputs q0 .. q0 + 3 per pass, so that each LDS read
-  // feeds up to four multiply-adds; inputs j = q0 + t are taken from the
+  // eight consecutive outputs q0 .. q0 + 7 per pass, so that each LDS read
+  // feeds up to eight multiply-adds; inputs j = q0 + t are taken from the
   // highest down, which adds every output's terms in ascending k
-  for (int q0 = 4 * w; q0 < Q; q0 += 16) {
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q0 = 8 * w; q0 < Q; q0 += 32) {
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 3 + KMAX; t >= -KMAX; --t) {
+    for (int t = 7 + KMAX; t >= -KMAX; --t) {
       const int j = q0 + t;                  // wave-uniform
       if (j < 0 || j >= Q) continue;
       const float x = win[j * 64 + lane];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
+      for (int jj = 0; jj < 8; ++jj) {
         const int k = jj - t;                // output q0 + jj takes lag k from input j
         if (k >= -KMAX && k <= KMAX) acc[jj] = fmaf(c[k + KMAX], x, acc[jj]);
       }
     }
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < 8; ++jj)
       if (cin && q0 + jj < Q) out[off + (long)(P * (q0 + jj) + r) * slot] = acc[jj];
   }
 }
