@@ -114,6 +114,7 @@ struct ScatterArgs {
   int nz, nx, nb, NX, LZ, nh, H, sg;
   int j0, nj;       // writable padded columns [j0, j0 + nj)
   int nzs;          // z strips
+  int zpad;         // rows of the first strip above the model (direct-load kernel)
   int nk, nshots;
   int slots_per_block;
 };
@@ -266,6 +267,15 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_ws(const ScatterArgs
 // still be outstanding (vector memory operations complete in order).  The
 // barrier is a bare s_barrier: a fenced one would wait for every outstanding
 // load.
+//
+// A workgroup owns the 24 output columns of one parity in a 48-column block;
+// wavefront w holds the weights of three same-parity columns (ja, ja + 2,
+// ja + 4) in registers, so each LDS read of the window feeds up to three
+// multiply-adds.  The 64-row strips start a.zpad rows above the model, on a
+// 64-byte boundary of the (256-byte aligned) padded column, so every 256-byte
+// run a wavefront loads or stores covers whole 64-byte memory sectors.
+constexpr int kScDmaJB = 24;      // outputs of one parity per workgroup of the direct-load kernel
+
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // s_waitcnt vmcnt(min(n, N)) for a wave-uniform n, other counters untouched
@@ -285,17 +295,16 @@ __device__ __forceinline__ void wait_vmcnt_at_most(int n) {
 template <int HMAX, int SG>
 __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArgs a) {
   constexpr int NH = 2 * HMAX + 1;
-  constexpr int WMAX = kScJB + 2 * HMAX;                          // staged same-parity columns
+  constexpr int WMAX = kScDmaJB + 2 * HMAX;                       // staged same-parity columns
   constexpr int NCH = (WMAX + 3) / 4;                             // 4-column chunks per slot
   constexpr int PER = (NCH + 7) / 8;                              // chunk loads per wavefront and slot
-  static_assert(2 * PER <= 63, "window");
+  static_assert(2 * PER + 9 <= 63, "window");
   __shared__ float b0[NCH * 256], b1[NCH * 256], b2[NCH * 256], b3[NCH * 256];
   __shared__ float sink[256];                                     // destination of the padding loads
 
-  // A workgroup owns the 16 output columns of one parity in a 32-column
-  // block: every input column they read has that parity too, so the window
-  // holds only those (m = 0 .. WMAX - 1 <-> padded column col0 + 2 m).
-  const int nblk_j = (a.nj + 2 * kScJB - 1) / (2 * kScJB);
+  // every input column the workgroup's outputs read has their parity, so
+  // the window holds only those (m = 0 .. WMAX - 1 <-> padded column col0 + 2 m)
+  const int nblk_j = (a.nj + 2 * kScDmaJB - 1) / (2 * kScDmaJB);
   const int ntile = a.nzs * nblk_j * 2;
   const int per = (ntile + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -306,32 +315,34 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   const int jbk = tile % nblk_j;
   const int par = (tile / nblk_j) & 1;
   const int zs = tile / nblk_j >> 1;
-  const int jb = a.j0 + jbk * 2 * kScJB + par;                    // first output column
+  const int jb = a.j0 + jbk * 2 * kScDmaJB + par;                 // first output column
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int z = zs * 64 + lane;
-  const bool zin = z < a.nz;
+  const int z = zs * 64 + lane - a.zpad;                          // model row of this lane
+  const bool zin = z >= 0 && z < a.nz;
   const int zp = a.nb + z;
   const int H = a.H;
   const int col0 = jb - 2 * HMAX;
-  const int ja = jb + 4 * w;                                      // outputs k = 2 w and 2 w + 1
-  const int jc = ja + 2;
+  const int ja = jb + 6 * w;                                      // outputs k = 3 w .. 3 w + 2
+  const int jc = ja + 2, je = ja + 4;
   const int jend = a.j0 + a.nj;
 
-  float ca[NH], cb[NH];
+  float ca[NH], cb[NH], cc[NH];
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const int ih = k - HMAX;
-    float va = 0.f, vb = 0.f;
+    float va = 0.f, vb = 0.f, vc = 0.f;
     if (ih >= -H && ih <= H && zin) {
-      const int ya = ja - SG * ih - a.nb, yc = jc - SG * ih - a.nb;
+      const int ya = ja - SG * ih - a.nb, yc = jc - SG * ih - a.nb, ye = je - SG * ih - a.nb;
       const long hb = (long)(ih + H) * a.nx;
       if (ya >= 0 && ya < a.nx) va = a.coef[(hb + ya) * a.nz + z];
       if (yc >= 0 && yc < a.nx) vb = a.coef[(hb + yc) * a.nz + z];
+      if (ye >= 0 && ye < a.nx) vc = a.coef[(hb + ye) * a.nz + z];
     }
     ca[k] = va;
     cb[k] = vb;
+    cc[k] = vc;
   }
 
   const int total = a.nshots * a.nk;
@@ -340,11 +351,15 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   if (q0 >= q1) return;
   const unsigned slot_bytes = (unsigned)((long)a.NX * a.LZ * 4);
   // lane i of a chunk load: window column m = 4 g + i / 16 (padded column
-  // col0 + 2 m), depths 4 (i % 16) .. + 3 of the strip; columns left of the
+  // col0 + 2 m), rows 4 (i % 16) .. + 3 of the strip; columns left of the
   // grid give negative offsets, which wrap past the end of the buffer and
   // read as zero like those right of it
-  const int off0 = (col0 * a.LZ + a.nb + zs * 64) * 4 + (2 * (lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
+  const int off0 = (col0 * a.LZ + a.nb - a.zpad + zs * 64) * 4 + (2 * (lane >> 4) * a.LZ + 4 * (lane & 15)) * 4;
   const int gstep = 8 * a.LZ * 4;                                 // bytes per chunk of 4 window columns
+  // cells not written go past the end of the buffer and are dropped
+  const int oa_off = zin && ja < jend ? (ja * a.LZ + zp) * 4 : kOutOfRange;
+  const int oc_off = zin && jc < jend ? (jc * a.LZ + zp) * 4 : kOutOfRange;
+  const int oe_off = zin && je < jend ? (je * a.LZ + zp) * 4 : kOutOfRange;
 
   // element offsets of the workgroup's input and output slots, computed once
   // (slot q is shot s = q / nk, step n = q mod nk, at ring position
@@ -361,7 +376,7 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   }
   __syncthreads();
   // wavefront w brings chunks g = w + 8 r (window columns 4 g .. 4 g + 3) of
-  // slot q into buf, column-major with lane = depth
+  // slot q into buf, column-major with lane = row
   auto issue = [&](int q, float *buf) {
     if (q >= q1) return;
     const auto rs = slot_rsrc(a.in + wave_uniform(tin[q - q0]), slot_bytes);
@@ -375,34 +390,35 @@ __global__ void __launch_bounds__(kScThreads) k_ext_scatter_dma(const ScatterArg
   };
   // This wavefront's loads of slot q have landed.  Issued after them and
   // possibly still outstanding: the loads of the y younger slots already
-  // issued and the two stores of each of the c slots consumed since; vector
+  // issued and the three stores of each of the c slots consumed since; vector
   // memory operations complete in order, so waiting until no more than
-  // PER y + 2 c remain is exact.
+  // PER y + 3 c remain is exact.
   auto ready = [&](int q) {
     if (q + 2 < q1 && q - q0 >= 3) {      // steady state: y = 2, c = 3
-      wait_vmcnt_at_most<2 * PER + 6>(2 * PER + 6);
+      wait_vmcnt_at_most<2 * PER + 9>(2 * PER + 9);
       return;
     }
     const int y = min(2, q1 - 1 - q);
     const int c = min(3, q - q0);
-    wait_vmcnt_at_most<2 * PER + 6>(PER * y + 2 * c);
+    wait_vmcnt_at_most<2 * PER + 9>(PER * y + 3 * c);
   };
   auto consume = [&](int q, const float *buf) {
-    // output k reads window column m = k - SG ih + HMAX; based at m = 2 w so
+    // output k reads window column m = k - SG ih + HMAX; based at m = 3 w so
     // that every LDS offset is a non-negative immediate
-    const float *row = &buf[2 * w * 64 + lane];
-    float oa = 0.f, ob = 0.f;
+    const float *row = &buf[3 * w * 64 + lane];
+    float oa = 0.f, ob = 0.f, oc = 0.f;
 #pragma unroll
     for (int k = 0; k < NH; ++k) {
       const int ih = k - HMAX;
       oa += ca[k] * row[(HMAX - SG * ih) * 64];
       ob += cb[k] * row[(HMAX + 1 - SG * ih) * 64];
+      oc += cc[k] * row[(HMAX + 2 - SG * ih) * 64];
     }
+    // always three store instructions, so that ready() can count them
     const auto ro = slot_rsrc(a.out + wave_uniform(tout[q - q0]), slot_bytes);
-    // always two store instructions (cells not written go past the end of
-    // the buffer and are dropped), so that ready() can count them
-    st(ro, oa, zin && ja < jend ? (ja * a.LZ + zp) * 4 : kOutOfRange, 0);
-    st(ro, ob, zin && jc < jend ? (jc * a.LZ + zp) * 4 : kOutOfRange, 0);
+    st(ro, oa, oa_off, 0);
+    st(ro, ob, oc_off, 0);
+    st(ro, oc, oe_off, 0);
   };
   // slot q sits in buffer q mod 4; the slot loaded in its place is q + 3,
   // whose buffer held slot q - 1 (everyone is past it once the barrier passed)
@@ -482,6 +498,15 @@ __global__ void __launch_bounds__(256) k_ext_scatter(const ScatterArgs a) {
   }
 }
 
+// Rows above the model at which the 64-row strips of the direct-load offset
+// kernels start: the first strip begins on a 64-byte boundary of the padded
+// column (256-byte aligned), so each wavefront's 256-byte runs cover whole
+// 64-byte memory sectors; 0 where that would take one more strip.
+static int strip_pad(int nz, int nb) {
+  const int pad = nb % 16;
+  return (nz + pad + 63) / 64 == (nz + 63) / 64 ? pad : 0;
+}
+
 hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const float *in, long in_slot,
                               float *out, long out_slot, long sstride, int nshots, int nk, hipStream_t st,
                               int in_ring, int in_first, int out_ring, int out_first) {
@@ -510,6 +535,7 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
   const int j1 = min(g.NX, g.nb + g.nx + g.H);
   a.nj = j1 - a.j0;
   a.nzs = (g.nz + 63) / 64;
+  a.zpad = 0;
   a.nk = nk;
   a.nshots = nshots;
   const int total = nshots * nk;
@@ -529,8 +555,11 @@ hipError_t launch_ext_scatter(const float *coef, const ExtGeom &g, int sg, const
     sg > 0 ? K<30, 1><<<GRID, THREADS, 0, st>>>(a) : K<30, -1><<<GRID, THREADS, 0, st>>>(a);
   if (g.H <= 30) {
     // spread the slots over enough workgroups to fill the device (the
-    // direct-load kernel tiles 32-column blocks once per column parity)
-    const int ntile = staged ? a.nzs * ((a.nj + kScJB - 1) / kScJB) : a.nzs * ((a.nj + 2 * kScJB - 1) / (2 * kScJB)) * 2;
+    // direct-load kernel tiles 48-column blocks once per column parity)
+    if (!staged) a.zpad = strip_pad(g.nz, g.nb);
+    a.nzs = (g.nz + a.zpad + 63) / 64;
+    const int ntile = staged ? a.nzs * ((a.nj + kScJB - 1) / kScJB)
+                             : a.nzs * ((a.nj + 2 * kScDmaJB - 1) / (2 * kScDmaJB)) * 2;
     const int nblk = (ntile + 7) / 8 * 8;
     int groups = std::max(1, std::min(total, (2048 + nblk - 1) / nblk));
     if (!staged) groups = std::max(groups, (total + kScMaxSlots - 1) / kScMaxSlots);
@@ -578,6 +607,7 @@ struct ImageArgs {
   int nshots, nk;
   int nz, nx, nb, NX, LZ, nh, H;
   int nzs, nyt, nht;
+  int zpad;            // rows of the first strip above the model (direct-load kernel)
   int nhb;             // offset blocks (blockIdx.x: tile and offset block, offset block fastest)
   int groups, slots_per_group;
 };
@@ -735,7 +765,9 @@ __global__ void __launch_bounds__(1024) k_ext_image_lds(const ImageArgs p) {
 // padded to 64 columns, 16 chunks of four 64-deep columns, so wavefront w
 // loads chunk w of the source-side and of the receiver-side window; columns
 // outside the grid read as zero through the range check.  Slots are consumed
-// in the same order as in k_ext_image_lds, so both give the same bits.
+// in the same order as in k_ext_image_lds, so both give the same bits.  As in
+// the scatter, the 64-row strips start on a 64-byte boundary of the column
+// (p.zpad rows above the model).
 template <int NYT, int NHT>
 __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   constexpr int NA = kImgYT + kImgHT - 1;
@@ -765,8 +797,8 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   const int grp = blockIdx.y;
   const int hlo = -p.H + HSPAN * (pair - tile * p.nhb);
   const int hhi = min(p.H, hlo + HSPAN - 1);
-  const int z = zs * 64 + lane;
-  const bool zin = z < p.nz;
+  const int z = zs * 64 + lane - p.zpad;           // model row of this lane
+  const bool zin = z >= 0 && z < p.nz;
   const int yt = w % NYT, ht = w / NYT;
   const int y0 = yb + 8 * yt;
   const int h0 = hlo + 8 * ht;
@@ -787,7 +819,7 @@ __global__ void __launch_bounds__(1024) k_ext_image_dma(const ImageArgs p) {
   const unsigned slot_bytes = (unsigned)((long)p.NX * p.LZ * 4);
   const int CBy = p.LZ * 4;
   // lane i of a chunk: column 4 w + i / 16 of the window, depths 4 (i % 16) .. + 3
-  const int lane_off = (p.nb + zs * 64 + 4 * (lane & 15)) * 4 + (lane >> 4) * CBy;
+  const int lane_off = (p.nb - p.zpad + zs * 64 + 4 * (lane & 15)) * 4 + (lane >> 4) * CBy;
   const int offa = lane_off + (xa0 + 4 * w) * CBy;
   const int offb = lane_off + (xb0 + 4 * w) * CBy;
   OffCursor fa, fb;                              // issue walks q0, q0 + 1, ... once, in order
@@ -882,8 +914,13 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.LZ = g.LZ;
   p.nh = g.nh;
   p.H = g.H;
-  p.nzs = (g.nz + 63) / 64;
   const bool wide = g.nh > 16;
+  // FWIME_IMAGE_KERNEL=lds selects the register-staged ring for the wide
+  // tiles too (for comparisons; read per launch)
+  const char *sel = std::getenv("FWIME_IMAGE_KERNEL");
+  const bool staged = sel && std::string(sel) == "lds";
+  p.zpad = wide && !staged ? strip_pad(g.nz, g.nb) : 0;
+  p.nzs = (g.nz + p.zpad + 63) / 64;
   p.nhb = wide ? (g.nh + 31) / 32 : 1;
   const int npair = p.nzs * ((g.nx + (wide ? 31 : 63)) / (wide ? 32 : 64)) * p.nhb;
   const int nblk = (npair + 7) / 8 * 8;
@@ -898,10 +935,6 @@ hipError_t launch_ext_image(const float *a, long a_slot, long a_sstride, const f
   p.slots_per_group = (total + groups - 1) / groups;
   p.groups = (total + p.slots_per_group - 1) / p.slots_per_group;
   const dim3 grid((unsigned)nblk, (unsigned)p.groups);
-  // FWIME_IMAGE_KERNEL=lds selects the register-staged ring for the wide
-  // tiles too (for comparisons; read per launch)
-  const char *sel = std::getenv("FWIME_IMAGE_KERNEL");
-  const bool staged = sel && std::string(sel) == "lds";
   if (wide && !staged) k_ext_image_dma<4, 4><<<grid, 1024, 0, st>>>(p);
   else if (wide) k_ext_image_lds<4, 4><<<grid, 1024, 0, st>>>(p);
   else k_ext_image_lds<8, 2><<<grid, 1024, 0, st>>>(p);

@@ -7,7 +7,8 @@ register-staged ring (FWIME_IMAGE_KERNEL=lds).  Each pair forms the same
 products and sums them in the same order, so extended Born data, adjoint
 images and gradients must agree bit for bit.  nh = 61 (H = 30, the widest
 kernels), 21 and 5, on a grid whose width is not a multiple of the scatter's
-32-column blocks.
+48-column blocks and whose strips start above the model (the direct-load
+kernels align them to 64-byte boundaries, the register-staged ones do not).
 """
 import sys
 
