@@ -1005,6 +1005,7 @@ __global__ void k_tau_image(const float *in, long in_slot, long in_sstride, cons
 // the Q_r samples of a residue for 64 model cells (lane = cell) in LDS, so
 // each history sample is read from HBM once instead of once per lag.
 constexpr int kTauQMax = 128;                 // samples per residue held in LDS
+constexpr int kTauImgWaves = 8;               // wavefronts per workgroup of the lag imaging kernel
 
 // Scatter: workgroup = (64-cell block, shot, residue); weights of the lane's
 // cell in registers (zero beyond K); every output adds the same terms in the
@@ -1069,10 +1070,12 @@ __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, cons
 // q, where every lag of the group is in range without a test and at the two
 // edges with one.
 template <int KPW>
-__global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_slot, long in_sstride,
+__global__ void __launch_bounds__(kTauImgWaves * 64) k_tau_image_lds(const float *in, long in_slot, long in_sstride,
                                                        const float *lam, long lam_slot, long lam_sstride, int nslots,
                                                        int nshots, int K, int L, int nz, int nx, int nb, int LZ,
                                                        const float *vel, float dt, float *acc) {
+  constexpr int NW = kTauImgWaves;
+  constexpr int PQ = kTauQMax / NW;            // samples per wavefront and residue
   __shared__ float ta[kTauQMax * 64], tb[kTauQMax * 64];
   const int P = 2 * L;
   const int lane = threadIdx.x & 63;
@@ -1085,20 +1088,40 @@ __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_
   float sum[KPW];
 #pragma unroll
   for (int i = 0; i < KPW; ++i) sum[i] = 0.f;
+  // Samples q = w + NW i of residue r of shot s (history and adjoint field).
+  // Every load reads a valid slot (clamped) and none sits behind a branch or
+  // feeds an instruction before the next residue's LDS writes, so the loads
+  // stay in flight while the current residue is summed; samples past the
+  // residue's Q steps or outside the model are zeroed when written to LDS.
+  // The slot is the same for the whole wavefront: each load is a buffer
+  // resource on that slot (scalar registers) plus one per-lane byte offset.
+  float pa[PQ], pb[PQ];
+  const int pcb = (int)pc * 4;
+  auto fetch = [&](int s, int r) {
+#pragma unroll
+    for (int i = 0; i < PQ; ++i) {
+      const long n = min(P * (w + NW * i) + r, nslots - 1);
+      pa[i] = bload(slot_rsrc(in + (long)s * in_sstride + n * in_slot, (unsigned)(in_slot * 4)), pcb);
+      pb[i] = bload(slot_rsrc(lam + (long)s * lam_sstride + n * lam_slot, (unsigned)(lam_slot * 4)), pcb);
+    }
+  };
+  fetch(0, 0);
   for (int s = 0; s < nshots; ++s) {
-    const float *a = in + (long)s * in_sstride + pc;
-    const float *bb = lam + (long)s * lam_sstride + pc;
     for (int r = 0; r < P; ++r) {
       const int Q = (nslots - r + P - 1) / P;
       __syncthreads();                         // the previous residue's reads are done
-      for (int q = w; q < Q; q += 4) {
-        ta[q * 64 + lane] = cin ? a[(long)(P * q + r) * in_slot] : 0.f;
-        tb[q * 64 + lane] = cin ? bb[(long)(P * q + r) * lam_slot] : 0.f;
+#pragma unroll
+      for (int i = 0; i < PQ; ++i) {
+        const bool ok = cin && w + NW * i < Q;
+        ta[(w + NW * i) * 64 + lane] = ok ? pa[i] : 0.f;
+        tb[(w + NW * i) * 64 + lane] = ok ? pb[i] : 0.f;
       }
       __syncthreads();
+      const int s2 = r + 1 < P ? s : s + 1;    // the next residue
+      if (s2 < nshots) fetch(s2, r + 1 < P ? r + 1 : 0);
 #pragma unroll
       for (int g = 0; g < KPW / 4; ++g) {
-        const int k0 = -K + 4 * (w + 4 * g);   // lags k0 .. k0 + 3, wave-uniform
+        const int k0 = -K + 4 * (w + NW * g);  // lags k0 .. k0 + 3, wave-uniform
         if (k0 > K) break;
         float t[4] = {0.f, 0.f, 0.f, 0.f};
         // lag k takes q in [max(0, k), min(Q, Q + k)); all four in [qlo, qhi)
@@ -1160,7 +1183,7 @@ __global__ void __launch_bounds__(256) k_tau_image_lds(const float *in, long in_
   const float sc = 2.f / (v * v * v * dt * dt);
 #pragma unroll
   for (int g = 0; g < KPW / 4; ++g) {
-    const int k0 = -K + 4 * (w + 4 * g);
+    const int k0 = -K + 4 * (w + NW * g);
     if (k0 > K) break;
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
@@ -1203,8 +1226,10 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
   if (nslots <= 0 || nshots <= 0) return hipSuccess;
   const int P = 2 * L;
   const long ncell = (long)g.nx * g.nz;
-  const int kpw = 4 * (((g.nh + 3) / 4 + 3) / 4); // lags per wavefront (whole groups of four)
-  if ((nslots + P - 1) / P > kTauQMax || kpw > 32) {
+  // lags per wavefront, whole groups of four dealt round-robin over the
+  // workgroup's wavefronts
+  const int kpw = 4 * (((g.nh + 3) / 4 + kTauImgWaves - 1) / kTauImgWaves);
+  if ((nslots + P - 1) / P > kTauQMax || kpw > 16) {
     k_tau_image<<<tau_blocks(ncell * g.nh), 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride,
                                                           nslots, nshots, g.H, L, g.nz, g.nx, g.nb, g.LZ, vel, dt,
                                                           acc);
@@ -1212,12 +1237,12 @@ hipError_t launch_tau_image(const float *in, long in_slot, long in_sstride, cons
   }
   const dim3 grid((unsigned)((ncell + 63) / 64));
 #define FW_TAU_I(KP)                                                                                              \
-  k_tau_image_lds<KP><<<grid, 256, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride, nslots, nshots, g.H, \
-                                            L, g.nz, g.nx, g.nb, g.LZ, vel, dt, acc)
+  k_tau_image_lds<KP><<<grid, kTauImgWaves * 64, 0, st>>>(in, in_slot, in_sstride, lam, lam_slot, lam_sstride,  \
+                                                          nslots, nshots, g.H, L, g.nz, g.nx, g.nb, g.LZ, vel, dt, \
+                                                          acc)
   if (kpw <= 4) FW_TAU_I(4);
   else if (kpw <= 8) FW_TAU_I(8);
-  else if (kpw <= 16) FW_TAU_I(16);
-  else FW_TAU_I(32);
+  else FW_TAU_I(16);
 #undef FW_TAU_I
   return hipGetLastError();
 }
