@@ -1014,51 +1014,71 @@ template <int KMAX>
 __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, const float *in, float *out, long slot,
                                                          long sstride, int nslots, int K, int L, int nz, int nx,
                                                          int nb, int LZ, int nshots, int ncb) {
+  constexpr int PQ = kTauQMax / 4;             // samples per wavefront and residue
   __shared__ float win[kTauQMax * 64];
   const int P = 2 * L;
-  // residue fastest, then shot, then cell block, in XCD-contiguous ranges:
-  // the workgroups of one cell block run together on one XCD and share its
-  // lag weights in that XCD's L2
-  const int total = ncb * nshots * P;
+  // shot fastest, then cell block, in XCD-contiguous ranges: the workgroups
+  // of one cell block run together on one XCD and share its lag weights in
+  // that XCD's L2; a workgroup walks every residue of its shot
+  const int total = ncb * nshots;
   const int per = (total + 7) >> 3;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (b >= total) return;
-  const int r = b % P;
-  const int s = (b / P) % nshots;
-  const int cbk = b / P / nshots;
+  const int s = b % nshots;
+  const int cbk = b / nshots;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long ncell = (long)nx * nz;
   const long cell = (long)cbk * 64 + lane;
   const bool cin = cell < ncell;
   const int y = cin ? (int)(cell / nz) : 0, z = cin ? (int)(cell - (long)y * nz) : 0;
-  const long off = (long)s * sstride + (long)(y + nb) * LZ + (z + nb);
-  const int Q = (nslots - r + P - 1) / P;   // steps P q + r < nslots
-  for (int q = w; q < Q; q += 4) win[q * 64 + lane] = cin ? in[off + (long)(P * q + r) * slot] : 0.f;
+  const long pc = (long)(y + nb) * LZ + (z + nb);
+  const long off = (long)s * sstride + pc;
+  // Samples q = w + 4 i of residue r: loaded into registers (a buffer
+  // resource on the wave's slot plus one per-lane offset, clamped to a valid
+  // slot, no branch) while the previous residue is summed, zeroed past the
+  // residue's Q steps or outside the model when written to LDS.
+  float pw[PQ];
+  const int pcb = (int)pc * 4;
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int i = 0; i < PQ; ++i) {
+      const long n = min(P * (w + 4 * i) + r, nslots - 1);
+      pw[i] = bload(slot_rsrc(in + (long)s * sstride + n * slot, (unsigned)(slot * 4)), pcb);
+    }
+  };
+  fetch(0);
   float c[2 * KMAX + 1];
 #pragma unroll
   for (int k = -KMAX; k <= KMAX; ++k)
     c[k + KMAX] = (cin && k >= -K && k <= K) ? coef[((long)(k + K) * nx + y) * nz + z] : 0.f;
-  __syncthreads();
-  // eight consecutive outputs q0 .. q0 + 7 per pass, so that each LDS read
-  // feeds up to eight multiply-adds; inputs j = q0 + t are taken from the
-  // highest down, which adds every output's terms in ascending k
-  for (int q0 = 8 * w; q0 < Q; q0 += 32) {
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < P; ++r) {
+    const int Q = (nslots - r + P - 1) / P;   // steps P q + r < nslots
+    __syncthreads();                         // the previous residue's reads are done
 #pragma unroll
-    for (int t = 7 + KMAX; t >= -KMAX; --t) {
-      const int j = q0 + t;                  // wave-uniform
-      if (j < 0 || j >= Q) continue;
-      const float x = win[j * 64 + lane];
+    for (int i = 0; i < PQ; ++i) win[(w + 4 * i) * 64 + lane] = cin && w + 4 * i < Q ? pw[i] : 0.f;
+    __syncthreads();
+    if (r + 1 < P) fetch(r + 1);
+    // eight consecutive outputs q0 .. q0 + 7 per pass, so that each LDS read
+    // feeds up to eight multiply-adds; inputs j = q0 + t are taken from the
+    // highest down, which adds every output's terms in ascending k
+    for (int q0 = 8 * w; q0 < Q; q0 += 32) {
+      float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const int k = jj - t;                // output q0 + jj takes lag k from input j
-        if (k >= -KMAX && k <= KMAX) acc[jj] = fmaf(c[k + KMAX], x, acc[jj]);
+      for (int t = 7 + KMAX; t >= -KMAX; --t) {
+        const int j = q0 + t;                  // wave-uniform
+        if (j < 0 || j >= Q) continue;
+        const float x = win[j * 64 + lane];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+          const int k = jj - t;                // output q0 + jj takes lag k from input j
+          if (k >= -KMAX && k <= KMAX) acc[jj] = fmaf(c[k + KMAX], x, acc[jj]);
+        }
       }
-    }
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-      if (cin && q0 + jj < Q) out[off + (long)(P * (q0 + jj) + r) * slot] = acc[jj];
+      for (int jj = 0; jj < 8; ++jj)
+        if (cin && q0 + jj < Q) out[off + (long)(P * (q0 + jj) + r) * slot] = acc[jj];
+    }
   }
 }
 
@@ -1202,8 +1222,8 @@ hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const 
   const int P = 2 * L;
   const long ncell = (long)g.nx * g.nz;
   const int ncb = (int)((ncell + 63) / 64);
-  const long nblk = (long)ncb * nshots * P;
-  if ((nslots + P - 1) / P > kTauQMax || g.H > 64 || nblk + 8 >= (1L << 31)) {
+  const long nblk = (long)ncb * nshots;
+  if ((nslots + P - 1) / P > kTauQMax || g.H > 64 || nblk + 8 >= (1L << 31) || (long)slot * 4 >= (1L << 32)) {
     k_tau_scatter<<<tau_blocks(ncell * nshots), 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz,
                                                               g.nx, g.nb, g.LZ, nshots);
     return hipGetLastError();
