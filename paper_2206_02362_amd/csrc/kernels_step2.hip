@@ -143,6 +143,12 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
   const bool zin = z >= 0 && z < NZ;
   const bool zown = lane >= kR && lane < kR + kTZ2;
   const int vz = z * 4;                       // byte offset of this lane's row
+  // Branch-free stores (the multi-job kernel): a row the lane does not own
+  // (or outside the grid) goes past the end of the buffer, and a column the
+  // wave must not write goes to a resource of size zero; the hardware drops
+  // both, so no store needs an exec-mask branch.
+  [[maybe_unused]] const int vz_st = zin && zown ? vz : kOutOfRange;
+  [[maybe_unused]] const int vz16_st = zin && zown ? z * 2 : kOutOfRange;
   const int xs1 = x0 - kR + w * W1;          // first step-1 column of this wave
   const int xs2 = x0 + w * W2;               // first step-2 column
 
@@ -372,7 +378,12 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
           u1l = 0;
         }
       }
-      if (xin && x >= x0 && x < x0 + TX) {   // wave-uniform
+      if constexpr (!EARLY2) {
+        const bool xst = xin && x >= x0 && x < x0 + TX;             // wave-uniform
+        st(rsrc(a.out + soff, xst ? FB : 0u), u1, vz_st, x * CB);
+        if constexpr (DF) st16(rsrc(p.lo_out + soff, xst ? FB / 2 : 0u), u1l, vz16_st, x * (CB / 2));
+        if constexpr (T2) st(rsrc(a.t2 + (long)s * a.t2_sstride, xst ? FB : 0u), FS ? rs : r, vz_st, x * CB);
+      } else if (xin && x >= x0 && x < x0 + TX) {                   // wave-uniform
         if (zin && zown) {
           st(r_out, u1, vz, x * CB);
           if constexpr (DF) st16(r_lout, u1l, z * 2, x * (CB / 2));
@@ -488,7 +499,11 @@ __device__ __forceinline__ void step2_body(const Step2Args &p, int logical,
           u2l = 0;
         }
       }
-      if (xin) {
+      if constexpr (!EARLY2) {
+        st(rsrc(p.out2 + soff, xin ? FB : 0u), u2, vz_st, x * CB);
+        if constexpr (DF) st16(rsrc(p.lo_out2 + soff, xin ? FB / 2 : 0u), u2l, vz16_st, x * (CB / 2));
+        if constexpr (T2) st(rsrc(p.t2b + (long)s * a.t2_sstride, xin ? FB : 0u), FS ? rs : r, vz_st, x * CB);
+      } else if (xin) {
         if (zown && zin) {
           st(r_out, u2, vz, x * CB);
           if constexpr (DF) st16(r_lout, u2l, z * 2, x * (CB / 2));
@@ -517,9 +532,21 @@ __global__ void __launch_bounds__(256) k_step2(const Step2Args p) {
 // Job j's fields rotate through buf[0..3] (prev = buf[n % 4]).  At
 // n = nt_j - 2 it takes one step and samples u^n and u^{n+1}; at n = nt_j - 1
 // it only samples u^n; outside [0, nt_j - 1] it is idle.
+// Workgroups per CU that the multi-job tile's LDS allows (at most 8).  The
+// kernel is held to the registers of that many workgroups: without the
+// bound, the branch-free stores let the compiler keep more operands live and
+// cost a wavefront per SIMD.  Width 24 (LDS for 7) needs 73 registers, one
+// more than 7 workgroups leave, so it is held to 6 rather than spill.
+template <int TX>
+constexpr int step2_multi_blocks() {
+  constexpr int n = 163840 / (int)sizeof(Step2Tile<TX>);
+  return TX == 24 ? 6 : n < 8 ? n : 8;
+}
+
 template <int TX, int MODE>
-__global__ void __launch_bounds__(256) k_step2_multi(const BatchJob2 *jobs, int njobs, int total, const int *step,
-                                                     int step_val) {
+__global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(const BatchJob2 *jobs, int njobs,
+                                                                              int total, const int *step,
+                                                                              int step_val) {
   __shared__ Step2Tile<TX> sh;
   const int per = (total + 7) >> 3;
   const int b = blockIdx.x;
