@@ -25,12 +25,16 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# 70 rows: the direct-load strips start 8 rows above the model (2 strips
+# either way); 60 rows: starting them there would take a second strip, so
+# they start at the model's first row
+@pytest.mark.parametrize("nz", [70, 60])
 @pytest.mark.parametrize("nh", [61, 21, 5])
-def test_offset_kernel_variants_bitwise(nh, monkeypatch):
+def test_offset_kernel_variants_bitwise(nh, nz, monkeypatch):
     import torch
     import paper_2206_02362_amd as fw
-    say(f"case: offset kernel variants, 70x150 nb8 nt121, 2 shots, nh {nh}")
-    w = synth.tiny(nz=70, nx=150, nb=8, nt=121, nshots=2, nh=nh, seed=7)
+    say(f"case: offset kernel variants, {nz}x150 nb8 nt121, 2 shots, nh {nh}")
+    w = synth.tiny(nz=nz, nx=150, nb=8, nt=121, nshots=2, nh=nh, seed=7)
     grid, tv, tg = gpu_problem(w)
     pt = torch.tensor(1e-2 * synth.random_ptilde(nh, w.nz, w.nx, 3), dtype=torch.float32, device="cuda:0")
     dobs = torch.tensor(1e-3 * np.random.default_rng(5).standard_normal((w.nshots, w.nrec, w.nt)),
