@@ -119,7 +119,8 @@ struct ScatterArgs {
   int slots_per_block;
 };
 
-// Pipelined weight-stationary kernel.  A workgroup of 8 wavefronts owns 16
+// Pipelined weight-stationary kernel, register-staged (k_ext_scatter_ws; the
+// direct-load kernel further below is the default).  A workgroup of 8 wavefronts owns 16
 // consecutive output columns of one 64-row depth strip; wavefront w holds the
 // weights of two same-parity columns ja and ja + 2 in registers for every h.
 // Input windows [jb - 2H, jb + 16 + 2H) of successive time slots flow through a
@@ -127,7 +128,7 @@ struct ScatterArgs {
 // registers and the global loads of slot q + 2 are in flight, with one barrier
 // per slot.  Each wavefront forms its two outputs with 2 nh multiply-adds from
 // nh + 1 LDS reads.
-constexpr int kScJB = 16;         // output columns per workgroup
+constexpr int kScJB = 16;         // output columns per workgroup of the register-staged kernel
 constexpr int kScThreads = 512;
 constexpr int kScMaxSlots = 2048; // time slots per workgroup of the direct-load kernel (offset table in LDS)
 
@@ -1007,9 +1008,10 @@ __global__ void k_tau_image(const float *in, long in_slot, long in_sstride, cons
 constexpr int kTauQMax = 128;                 // samples per residue held in LDS
 constexpr int kTauImgWaves = 8;               // wavefronts per workgroup of the lag imaging kernel
 
-// Scatter: workgroup = (64-cell block, shot, residue); weights of the lane's
-// cell in registers (zero beyond K); every output adds the same terms in the
-// same order as in k_tau_scatter, so both give the same bits.
+// Scatter: workgroup = (64-cell block, shot), walking the shot's residues;
+// weights of the lane's cell in registers (zero beyond K); every output adds
+// the same terms in the same order as in k_tau_scatter, so both give the
+// same bits.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, const float *in, float *out, long slot,
                                                          long sstride, int nslots, int K, int L, int nz, int nx,
@@ -1082,11 +1084,11 @@ __global__ void __launch_bounds__(256) k_tau_scatter_lds(const float *coef, cons
   }
 }
 
-// Image: workgroup = 64-cell block; it walks every shot and residue, staging
-// the history and adjoint samples.  Lags come in groups of four consecutive
-// ones, group G = w + 4 g to wavefront w (at most KPW lags per wavefront,
-// accumulated in registers): one adjoint sample and a window of four history
-// samples feed four multiply-adds.  Each lag sums its products in ascending
+// Image: workgroup = 64-cell block of kTauImgWaves wavefronts; it walks every
+// shot and residue, staging the history and adjoint samples.  Lags come in
+// groups of four consecutive ones, group G = w + kTauImgWaves g to wavefront w
+// (at most KPW lags per wavefront, accumulated in registers): one adjoint
+// sample and a window of four history samples feed four multiply-adds.  Each lag sums its products in ascending
 // q, where every lag of the group is in range without a test and at the two
 // edges with one.
 template <int KPW>
