@@ -1234,9 +1234,14 @@ hipError_t launch_tau_scatter(const float *coef, const ExtGeom &g, int L, const 
 #define FW_TAU_S(KM)                                                                                     \
   k_tau_scatter_lds<KM><<<grid, 256, 0, st>>>(coef, in, out, slot, sstride, nslots, g.H, L, g.nz, g.nx, g.nb, \
                                               g.LZ, nshots, ncb)
+  // every pass multiplies 2 KMAX + 1 weights, those beyond K being zero:
+  // buckets of 8 lags keep that waste small for the wide lag ranges
   if (g.H <= 8) FW_TAU_S(8);
   else if (g.H <= 16) FW_TAU_S(16);
   else if (g.H <= 32) FW_TAU_S(32);
+  else if (g.H <= 40) FW_TAU_S(40);
+  else if (g.H <= 48) FW_TAU_S(48);
+  else if (g.H <= 56) FW_TAU_S(56);
   else FW_TAU_S(64);
 #undef FW_TAU_S
   return hipGetLastError();
