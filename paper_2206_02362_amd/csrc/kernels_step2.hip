@@ -525,13 +525,6 @@ __global__ void __launch_bounds__(256) k_step2(const Step2Args p) {
   step2_body<TX, MODE>(p, logical, sh, false, p.two != 0);
 }
 
-// Many jobs (grids, models, geometries) in one launch, two steps per launch.
-// The time index of job j is n = step - t0_j, with step read from device
-// memory (*step, advanced by 2 per launch under graph replay) or, when that
-// pointer is null, the launch argument step_val.
-// Job j's fields rotate through buf[0..3] (prev = buf[n % 4]).  At
-// n = nt_j - 2 it takes one step and samples u^n and u^{n+1}; at n = nt_j - 1
-// it only samples u^n; outside [0, nt_j - 1] it is idle.
 // Workgroups per CU that the multi-job tile's LDS allows (at most 8).  The
 // kernel is held to the registers of that many workgroups: without the
 // bound, the branch-free stores let the compiler keep more operands live and
@@ -543,6 +536,13 @@ constexpr int step2_multi_blocks() {
   return TX == 24 ? 6 : n < 8 ? n : 8;
 }
 
+// Many jobs (grids, models, geometries) in one launch, two steps per launch.
+// The time index of job j is n = step - t0_j, with step read from device
+// memory (*step, advanced by 2 per launch under graph replay) or, when that
+// pointer is null, the launch argument step_val.
+// Job j's fields rotate through buf[0..3] (prev = buf[n % 4]).  At
+// n = nt_j - 2 it takes one step and samples u^n and u^{n+1}; at n = nt_j - 1
+// it only samples u^n; outside [0, nt_j - 1] it is idle.
 template <int TX, int MODE>
 __global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(const BatchJob2 *jobs, int njobs,
                                                                               int total, const int *step,
