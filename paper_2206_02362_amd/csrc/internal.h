@@ -194,8 +194,10 @@ struct BatchJob2 {
 // The global step is *step when `step` is non-null (a device counter that
 // graph replays advance with launch_bump), else step_val.  fs: some job has
 // a free surface (the FS kernel then serves every job of the launch).
-hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int step_val,
-                              int tile_x, bool fs, hipStream_t st);
+// tile_job: job of every tile of the launch, or null (binary search over the
+// jobs' tile_begin).
+hipError_t launch_step2_multi(const BatchJob2 *jobs, const int *tile_job, int njobs, int total_tiles, const int *step,
+                              int step_val, int tile_x, bool fs, hipStream_t st);
 
 hipError_t launch_step_multi(const BatchJob *jobs, int njobs, int total_tiles, const int *step, int step_val,
                              int tile_x, bool fs, hipStream_t st);

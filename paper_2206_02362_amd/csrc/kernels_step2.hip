@@ -544,7 +544,8 @@ constexpr int step2_multi_blocks() {
 // n = nt_j - 2 it takes one step and samples u^n and u^{n+1}; at n = nt_j - 1
 // it only samples u^n; outside [0, nt_j - 1] it is idle.
 template <int TX, int MODE>
-__global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(const BatchJob2 *jobs, int njobs,
+__global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(const BatchJob2 *jobs,
+                                                                              const int *tile_job, int njobs,
                                                                               int total, const int *step,
                                                                               int step_val) {
   __shared__ Step2Tile<TX> sh;
@@ -552,11 +553,16 @@ __global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(c
   const int b = blockIdx.x;
   const int logical = (b & 7) * per + (b >> 3);
   if (logical >= total) return;
-  int lo = 0, hi = njobs - 1;                       // last job with tile_begin <= logical
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].tile_begin <= logical) lo = mid;
-    else hi = mid - 1;
+  int lo = 0;                                       // last job with tile_begin <= logical
+  if (tile_job) {
+    lo = tile_job[logical];
+  } else {
+    int hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile_begin <= logical) lo = mid;
+      else hi = mid - 1;
+    }
   }
   const BatchJob2 &jb = jobs[lo];
   const int n = (step ? *step : step_val) - jb.t0;
@@ -574,22 +580,22 @@ __global__ void __launch_bounds__(256, step2_multi_blocks<TX>()) k_step2_multi(c
 }
 
 template <int TX>
-static void launch_step2_multi_tx(dim3 grid, const BatchJob2 *jobs, int njobs, int total_tiles, const int *step,
-                                  int step_val, bool fs, hipStream_t st) {
-  if (fs) k_step2_multi<TX, kModeFS><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
-  else k_step2_multi<TX, kModePlain><<<grid, 256, 0, st>>>(jobs, njobs, total_tiles, step, step_val);
+static void launch_step2_multi_tx(dim3 grid, const BatchJob2 *jobs, const int *tile_job, int njobs, int total_tiles,
+                                  const int *step, int step_val, bool fs, hipStream_t st) {
+  if (fs) k_step2_multi<TX, kModeFS><<<grid, 256, 0, st>>>(jobs, tile_job, njobs, total_tiles, step, step_val);
+  else k_step2_multi<TX, kModePlain><<<grid, 256, 0, st>>>(jobs, tile_job, njobs, total_tiles, step, step_val);
 }
 
-hipError_t launch_step2_multi(const BatchJob2 *jobs, int njobs, int total_tiles, const int *step, int step_val,
-                              int tile_x, bool fs, hipStream_t st) {
+hipError_t launch_step2_multi(const BatchJob2 *jobs, const int *tile_job, int njobs, int total_tiles, const int *step,
+                              int step_val, int tile_x, bool fs, hipStream_t st) {
   const long per = (total_tiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   switch (tile_x) {
-    case 16: launch_step2_multi_tx<16>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
-    case 24: launch_step2_multi_tx<24>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
-    case 32: launch_step2_multi_tx<32>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
-    case 48: launch_step2_multi_tx<48>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
-    case 64: launch_step2_multi_tx<64>(grid, jobs, njobs, total_tiles, step, step_val, fs, st); break;
+    case 16: launch_step2_multi_tx<16>(grid, jobs, tile_job, njobs, total_tiles, step, step_val, fs, st); break;
+    case 24: launch_step2_multi_tx<24>(grid, jobs, tile_job, njobs, total_tiles, step, step_val, fs, st); break;
+    case 32: launch_step2_multi_tx<32>(grid, jobs, tile_job, njobs, total_tiles, step, step_val, fs, st); break;
+    case 48: launch_step2_multi_tx<48>(grid, jobs, tile_job, njobs, total_tiles, step, step_val, fs, st); break;
+    case 64: launch_step2_multi_tx<64>(grid, jobs, tile_job, njobs, total_tiles, step, step_val, fs, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -2264,6 +2264,7 @@ struct BatchPlan {
   int total = 0;
   int nt_max = 0;
   bool fs = false;               // some job has a free surface
+  int *dtile_job = nullptr;      // device: position k of every tile (two-step plans)
   int stride() const { return two ? 2 : 1; }
   // launches until the longest job has sampled its last time
   long launches() const { return two ? (nt_max - 1) / 2 + 1 : nt_max; }
@@ -2325,7 +2326,8 @@ int batch_active_tiles(const BatchPlan &bp, long n) {
 hipError_t batch_launch(const BatchPlan &bp, const void *djobs, int tiles, int *dstep, int step_val, int tx,
                         hipStream_t st) {
   const int nj = (int)bp.order.size();
-  hipError_t e = bp.two ? launch_step2_multi((const BatchJob2 *)djobs, nj, tiles, dstep, step_val, tx, bp.fs, st)
+  hipError_t e = bp.two ? launch_step2_multi((const BatchJob2 *)djobs, bp.dtile_job, nj, tiles, dstep, step_val, tx,
+                                             bp.fs, st)
                         : launch_step_multi((const BatchJob *)djobs, nj, tiles, dstep, step_val, tx, bp.fs, st);
   if (e != hipSuccess || !dstep) return e;
   return launch_bump(dstep, bp.stride(), st);
@@ -2349,6 +2351,7 @@ int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, 
   char *dj = nullptr;
   cv.add(&dj, jb_bytes * njobs);
   cv.add(dstep, 1);
+  if (bp.two) cv.add(&bp.dtile_job, bp.total);
   int rc = arena_get(ctx, cv);
   if (rc) return rc;
   for (int k = 0; k < njobs; ++k) {
@@ -2377,6 +2380,14 @@ int batch_carve_and_setup(fwime_ctx_t *ctx, int njobs, const fwime_job_t *jobs, 
   }
   const void *host = bp.two ? (const void *)bp.jobs2.data() : (const void *)bp.jobs.data();
   HIPCHK(hipMemcpyAsync(dj, host, jb_bytes * njobs, hipMemcpyHostToDevice, st));
+  // the job of every tile, so that a workgroup finds its job with one load
+  std::vector<int> tile_job;
+  if (bp.two) {
+    tile_job.resize(bp.total);
+    for (int k = 0; k < njobs; ++k)
+      std::fill(tile_job.begin() + bp.prefix[k], tile_job.begin() + bp.prefix[k + 1], k);
+    HIPCHK(hipMemcpyAsync(bp.dtile_job, tile_job.data(), sizeof(int) * bp.total, hipMemcpyHostToDevice, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   *djobs = dj;
   return FWIME_OK;
@@ -2787,7 +2798,8 @@ int fwime_engine_run(fwime_engine_t *e) {
   HIPCHK(hipMemcpyAsync(e->dev_desc[i], e->host_desc[i], sizeof(BatchJob2) * nj, hipMemcpyHostToDevice, e->st));
   const int L = e->steps / 2;
   for (int l = 0; l < L; ++l)
-    HIPCHK(launch_step2_multi(e->dev_desc[i], nj, total, nullptr, (int)(e->step + 2L * l), ctx->tile_x, fs, e->st));
+    HIPCHK(launch_step2_multi(e->dev_desc[i], nullptr, nj, total, nullptr, (int)(e->step + 2L * l), ctx->tile_x, fs,
+                              e->st));
   HIPCHK(hipEventRecord(e->ring_ev[i], e->st));
   e->ring_used[i] = true;
   e->ring_i = (i + 1) % kEngineRing;
